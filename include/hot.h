@@ -1,0 +1,218 @@
+/*
+ * hot.h -- C ABI of the MI355X implicit MPM step of "Hierarchical Optimization
+ * Time Integration for CFL-rate MPM Stepping" (HOT, arXiv 1911.07913).
+ *
+ * One call of hot_step advances a particle scene by one implicit-Euler MPM
+ * step (Sec. 3.1): APIC particle-to-grid transfer, minimisation of the
+ * incremental potential of Eq. 1 over grid velocity increments by HOT
+ * (Alg. HOT: L-BFGS whose initial inverse Hessian is one multigrid V-cycle of
+ * Alg. V-cycle over the node-embedding Galerkin hierarchy of Sec. 4), then
+ * grid-to-particle transfer, deformation update and advection.
+ *
+ * Conventions for every function below:
+ *   - all functions are extern "C", never throw, and return hot_status
+ *     (0 = OK, > 0 = warning with the step completed, < 0 = error);
+ *   - host arrays are owned by the caller; they are copied in at
+ *     hot_init_scene and copied out by hot_read_particles;
+ *   - a scene owns its device memory, obtained through the hot_allocator
+ *     given at creation (NULL: hipMalloc/hipFree) and released by
+ *     hot_destroy_scene;
+ *   - all device work of a scene is issued on the HIP stream given at
+ *     creation (NULL: the default stream);
+ *   - SI units; particle arrays are row-major, n rows, in the caller's order;
+ *   - a scene is not thread-safe; distinct scenes may be used from distinct
+ *     host threads;
+ *   - on error, hot_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).
+ */
+#ifndef HOT_H_
+#define HOT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOT_OK = 0,
+  HOT_W_NOT_CONVERGED = 1,  /* step done; CN tolerance not met (iteration cap or
+                               line search exhausted) */
+  HOT_E_INVALID = -1,       /* bad argument; nothing changed */
+  HOT_E_NOMEM = -2,         /* device allocation failed; nothing changed */
+  HOT_E_DEVICE = -3,        /* HIP runtime error */
+  HOT_E_NONFINITE = -4,     /* non-finite energy/gradient: particle state rolled back */
+  HOT_E_BUSY = -5
+} hot_status;
+
+/* Elastic energy density (Sec. 7.1 uses fixed-corotated for every scene). */
+typedef enum { HOT_FCR = 0, HOT_NEOHOOKEAN = 1 } hot_model;
+
+/* Precision policy: HOT_FP64 runs every kernel in FP64.  HOT_MIXED runs the
+ * V-cycle (smoothing, SpMV, coarse solve) in FP32 over BF16-stored Hessian
+ * blocks with FP32 accumulation; energy, line search, gradient, CN test and
+ * the L-BFGS history stay FP64. */
+typedef enum { HOT_FP64 = 0, HOT_MIXED = 1 } hot_precision;
+
+typedef struct {
+  int32_t model;        /* hot_model */
+  double E;             /* Young's modulus, Pa, > 0 */
+  double nu;            /* Poisson ratio, in (-1, 0.5) */
+  double density;       /* kg/m^3, > 0 (particle mass = density * vol0) */
+  double yield_stress;  /* von Mises yield stress, Pa; 0 = purely elastic.
+                           Applied once per step after the solve (lagged
+                           plasticity, Sec. 2 and Sec. 8). */
+} hot_material;
+
+/* Dirichlet boundary conditions, resolved by projection at every level
+ * (Sec. 4.1).  All are sticky: every velocity component is prescribed on the
+ * grid nodes they select.  Later entries override earlier ones. */
+typedef enum {
+  HOT_BC_BOX_WALLS = 0, /* p[0] = thickness t in cells: nodes with index <= t or
+                           >= grid_cells - t on any axis are held at rest */
+  HOT_BC_GRIP = 1,      /* p[0..2] box min, p[3..5] box max (world, inclusive),
+                           p[6..8] point on the axis, p[9..11] axis direction,
+                           p[12] angular speed w (rad/s): nodes in the box move
+                           with w * (a x (x - c)) */
+  HOT_BC_SPHERE = 2     /* p[0..2] centre at t = 0, p[3] radius, p[4..6]
+                           velocity: nodes inside the sphere at the end of the
+                           step move with the sphere */
+} hot_bc_kind;
+
+typedef struct {
+  int32_t kind;         /* hot_bc_kind */
+  double p[16];
+} hot_bc;
+
+/* Device allocator hook (e.g. a framework's caching allocator).  alloc returns
+ * device memory of at least `bytes` bytes or NULL; free releases it. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} hot_allocator;
+
+/* Problem statement (Sec. 3.1, Sec. 7.1 simulation settings). */
+typedef struct {
+  double dx;               /* grid spacing, m, > 0 */
+  int32_t grid_cells[3];   /* cells per axis; nodes sit at origin + i*dx,
+                              i = 0..grid_cells */
+  double origin[3];
+  double gravity[3];       /* m/s^2, applied to the grid velocity before the solve */
+  double cfl;              /* time-step rule dt = min(max_dt, cfl*dx/v_max), 0.6 */
+  double max_dt;           /* 1/FPS, e.g. 1/24 */
+  double tol;              /* CN tolerance eps of Sec. 5.2: stop when
+                              ||g_hat|| <= eps * sqrt(#active fine nodes) */
+  int32_t lbfgs_history;   /* window w of Alg. HOT (paper default 8) */
+  int32_t mg_levels;       /* levels M of the hierarchy (>= 1) */
+  int32_t max_iters;       /* L-BFGS iteration cap (e.g. 500) */
+  int32_t smoother_sweeps; /* smoothing sweeps per level and direction (1) */
+  int32_t precision;       /* hot_precision */
+  int32_t reserved[3];     /* must be zero */
+} hot_params;
+
+typedef struct {
+  double dt;               /* time step used */
+  double t;                /* scene time after the step */
+  double E0, E;            /* incremental potential at dv = 0 and at the end */
+  double cn0, cn;          /* CN-scaled gradient norm at start and end */
+  double cn_tol;           /* eps * sqrt(n) */
+  int32_t iters;           /* L-BFGS iterations (line searches performed) */
+  int32_t backtracks;      /* total step-length halvings */
+  int32_t cg_iters_total;  /* coarsest-level PCG iterations over all V-cycles */
+  int32_t converged;       /* 1 if the CN test passed */
+  int32_t fallbacks;       /* non-descent directions replaced */
+  int32_t skipped_pairs;   /* secant pairs rejected by the curvature test */
+  int32_t n_nodes;         /* active fine nodes */
+  int32_t n_levels;
+  float ms_prepare;        /* binning + grid + P2G */
+  float ms_hierarchy;      /* Hessian assembly + Galerkin coarsening */
+  float ms_solve;          /* quasi-Newton loop */
+  float ms_g2p;            /* G2P + deformation update + advection */
+} hot_step_stats;
+
+typedef struct hot_scene hot_scene;
+
+/* Upper bound of the device bytes hot_init_scene would allocate for this
+ * particle set (positions x[n][3], host).  Used for admission by HBM
+ * footprint. */
+hot_status hot_scene_footprint(const hot_params* params, int64_t n, const double* x,
+                               size_t* bytes_out);
+
+/* Create a scene from host particle arrays (copied).  x, v: [n][3]; F, C:
+ * [n][9] row-major (F NULL = identity, C NULL = zero; C is the APIC affine
+ * velocity matrix); vol0: [n] initial volumes; mat_id: [n] indices into mats.
+ * Particles must lie in [origin + 2dx, origin + (grid_cells - 3)dx] and all
+ * values must be finite; otherwise HOT_E_INVALID. */
+hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, const double* v,
+                          const double* F, const double* C, const double* vol0,
+                          const int32_t* mat_id, const hot_material* mats, int32_t n_mats,
+                          const hot_bc* bcs, int32_t n_bcs, const hot_allocator* alloc,
+                          void* hip_stream, hot_scene** out);
+
+/* Advance one implicit step.  dt <= 0 selects the CFL rule above.  Either
+ * completes the step (HOT_OK or HOT_W_NOT_CONVERGED) or leaves the particle
+ * state unchanged (errors).  stats may be NULL. */
+hot_status hot_step(hot_scene* scene, double dt, hot_step_stats* stats);
+
+/* Copy particle state back to host arrays in the caller's original order.
+ * n must equal the scene's particle count; F and C may be NULL. */
+hot_status hot_read_particles(const hot_scene* scene, int64_t n, double* x, double* v,
+                              double* F, double* C);
+
+/* Particle count and current scene time. */
+hot_status hot_scene_info(const hot_scene* scene, int64_t* n, double* t);
+
+void hot_destroy_scene(hot_scene* scene);
+const char* hot_last_error(void);
+
+/* ---- serving: continuous batching of independent scenes ------------------
+ * A batch owns an HBM budget and a set of slots.  Scenes join with a number
+ * of steps to run (HOT_E_NOMEM when their footprint does not fit now: defer
+ * and retry).  Each hot_batch_round advances every resident scene by one
+ * step, issuing the scenes' work back to back on the batch's stream so the
+ * device overlaps their small kernels; scenes that have finished their steps
+ * leave the batch and their tags are reported.  A scene's arithmetic does not
+ * depend on what else is resident. */
+typedef struct hot_batch hot_batch;
+hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out);
+hot_status hot_batch_add(hot_batch* batch, hot_scene* scene, int32_t n_steps, int64_t tag);
+hot_status hot_batch_round(hot_batch* batch, int64_t* done_tags, int32_t* n_done, int32_t cap,
+                           int32_t* n_resident);
+void hot_batch_destroy(hot_batch* batch);
+
+/* ---- test hooks (parity checks against an independent implementation) --- */
+enum {
+  HOT_DBG_PERM = 1,        /* int32 [n]: original index of each particle in binned order */
+  HOT_DBG_LEVEL_NODES = 10,/* int32 [n_m]: linear node index (x fastest) at level m */
+  HOT_DBG_LEVEL_PATTERN = 11, /* uint32 [n_m][4]: bit s set if block slot s is
+                                structurally present (s = dx+2 + 5(dy+2) + 25(dz+2)) */
+  HOT_DBG_LEVEL_MATRIX = 12,  /* double [n_m][125][3][3] block rows (FP64 copy) */
+  HOT_DBG_LEVEL_FREE = 13,    /* uint8 [n_m][3]: 1 = free DOF, 0 = constrained */
+  HOT_DBG_NODE_MASS = 20,     /* double [n_0] */
+  HOT_DBG_NODE_VSTAR = 21,    /* double [n_0][3]: v after gravity and BCs */
+  HOT_DBG_NODE_XI = 22,       /* double [n_0]: CN stiffness field */
+  HOT_DBG_NODE_FIXED = 23,    /* int32 [n_0] */
+  HOT_DBG_DV = 30,            /* double [n_0][3]: last solve's dv */
+  HOT_DBG_LOG_INT = 40,       /* int32 [iters][4]: halvings (-1 failed), pair skipped,
+                                 fallback, coarse-PCG iterations of the iteration's V-cycle */
+  HOT_DBG_LOG_CN = 41,        /* double [iters + 1] */
+  HOT_DBG_COUNTS = 50         /* int32 [16]: n, n_levels, nodes per level... */
+};
+/* Copy an internal array (see HOT_DBG_*) of level `level` to host memory.
+ * *needed receives the byte size; dst may be NULL to query it. */
+hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, void* dst,
+                          size_t bytes, size_t* needed);
+/* Run the step up to and including the Galerkin hierarchy (no solve, no G2P,
+ * particle state unchanged) with time step dt (<= 0: CFL rule). */
+hot_status hot_debug_prepare(hot_scene* scene, double dt);
+/* After hot_debug_prepare: apply an operator to a host vector of n_0*3
+ * doubles.  op 0: one V-cycle; op 1: gradient at dv = in; op 2: energy at
+ * dv = in (out[0]); op 3: level-0 matrix product. */
+hot_status hot_debug_apply(hot_scene* scene, int32_t op, const double* in, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOT_H_ */

@@ -1,0 +1,274 @@
+// Vector kernels of the quasi-Newton loop: deterministic reductions (fixed
+// grid, fixed-order final sum), L-BFGS two-loop updates with device-side
+// scalars, and precision conversions.
+#include "mpm_math.h"
+
+namespace hot {
+namespace {
+
+constexpr int kTpb = 256;
+inline unsigned blocks_for(long long n, int tpb = kTpb) {
+  return (unsigned)((n + tpb - 1) / tpb);
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kTpb / 64; ++k) t += sh[k];
+  return t;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// kind 0: sum a*b; 1: sum a; 2: sum (a - b)
+__global__ void k_partial(long long n, int kind, const double* __restrict__ a,
+                          const double* __restrict__ b, double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s = 0.0;
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+    double v = (kind == 0) ? a[k] * b[k] : (kind == 1 ? a[k] : a[k] - b[k]);
+    s += v;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void k_partial3(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+    double x = a[k], y = b[k];
+    s0 += x * y;
+    s1 += x * x;
+    s2 += y * y;
+  }
+  double t0 = block_sum(s0, sh);
+  __syncthreads();
+  double t1 = block_sum(s1, sh);
+  __syncthreads();
+  double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t0;
+    partial[kRedBlocks + blockIdx.x] = t1;
+    partial[2 * kRedBlocks + blockIdx.x] = t2;
+  }
+}
+
+// sum_i 1/2 m_i (|dv_i + alpha p_i|^2 - |dv_i|^2)
+__global__ void k_kinetic(int n, const double* __restrict__ m, const double* __restrict__ dv,
+                          const double* __restrict__ p, double alpha, double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+    double a2 = 0.0, b2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double d = dv[3 * i + c];
+      double t = d + alpha * p[3 * i + c];
+      a2 += t * t;
+      b2 += d * d;
+    }
+    s += 0.5 * m[i] * a2 - 0.5 * m[i] * b2;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// sum_i |g_i / (scale * xi_i)|^2, the squared CN-scaled gradient norm.
+__global__ void k_cn(int n, const double* __restrict__ g, const double* __restrict__ xi, double scale,
+                     double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+    double d = scale * xi[i];
+    for (int c = 0; c < 3; ++c) {
+      double q = g[3 * i + c] / d;
+      s += q * q;
+    }
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void k_maxspeed(int n, const double* __restrict__ v, double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+    double a = v[3 * i], b = v[3 * i + 1], c = v[3 * i + 2];
+    s = fmax(s, sqrt(a * a + b * b + c * c));
+  }
+  s = wave_max(s);
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kTpb / 64; ++k) t = fmax(t, sh[k]);
+    partial[blockIdx.x] = t;
+  }
+}
+
+// Fixed-order final reduction of kRedBlocks partials (sum or max) into out.
+__global__ void k_finish(int nparts, int count, int is_max, const double* __restrict__ partial,
+                         double* __restrict__ out) {
+  __shared__ double sh[kTpb / 64];
+  for (int q = 0; q < count; ++q) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kTpb) {
+      double v = partial[q * nparts + k];
+      s = is_max ? fmax(s, v) : s + v;
+    }
+    double t;
+    if (is_max) {
+      s = wave_max(s);
+      int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      if (lane == 0) sh[w] = s;
+      __syncthreads();
+      t = 0.0;
+      if (threadIdx.x == 0)
+        for (int k = 0; k < kTpb / 64; ++k) t = fmax(t, sh[k]);
+    } else {
+      t = block_sum(s, sh);
+    }
+    if (threadIdx.x == 0) out[q] = t;
+    __syncthreads();
+  }
+}
+
+__global__ void k_axpy_dev(long long n, const double* __restrict__ a, double sign,
+                           const double* __restrict__ x, double* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double al = sign * a[0];
+  y[k] = y[k] + al * x[k];
+}
+__global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  y[k] = y[k] + a * x[k];
+}
+__global__ void k_scale_copy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  y[k] = a * x[k];
+}
+__global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  y[k] = a[k] - b[k];
+}
+// alpha = rho * dot
+__global__ void k_lbfgs_alpha(const double* rho, const double* dot, double* alpha) {
+  alpha[0] = rho[0] * dot[0];
+}
+// coef = alpha - rho * dot  (alpha^a - beta of the second loop)
+__global__ void k_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef) {
+  double beta = rho[0] * dot[0];
+  coef[0] = alpha[0] - beta;
+}
+__global__ void k_to_f32(long long n, const double* __restrict__ x, float* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = (float)x[k];
+}
+__global__ void k_to_f64(long long n, const float* __restrict__ x, double* __restrict__ y) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = (double)x[k];
+}
+__global__ void k_bj_apply(int n, const double* __restrict__ Dinv, const double* __restrict__ x,
+                           double* __restrict__ y, double sign) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* D = Dinv + 9 * (long long)i;
+  double x0 = x[3 * i], x1 = x[3 * i + 1], x2 = x[3 * i + 2];
+  for (int g = 0; g < 3; ++g) y[3 * i + g] = sign * (D[3 * g] * x0 + D[3 * g + 1] * x1 + D[3 * g + 2] * x2);
+}
+
+__global__ void k_fill_d(long long n, double* p, double v) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+__global__ void k_rho(const double* ys, double* rho) { rho[0] = 1.0 / ys[0]; }
+
+}  // namespace
+
+void launch_fill_double(long long n, double* p, double v, hipStream_t st) {
+  if (n > 0) k_fill_d<<<blocks_for(n), kTpb, 0, st>>>(n, p, v);
+}
+void launch_rho(const double* ys, double* rho, hipStream_t st) { k_rho<<<1, 1, 0, st>>>(ys, rho); }
+
+void launch_finish_sum(int nparts, const double* partial, double* out, hipStream_t st) {
+  k_finish<<<1, kTpb, 0, st>>>(nparts, 1, 0, partial, out);
+}
+void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
+                hipStream_t st) {
+  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 0, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+}
+void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
+                  hipStream_t st) {
+  k_partial3<<<kRedBlocks, kTpb, 0, st>>>(n, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 3, 0, partial, out);
+}
+void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st) {
+  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 1, a, nullptr, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+}
+void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
+                     hipStream_t st) {
+  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 2, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+}
+void launch_kinetic_delta(int n, const double* mass, const double* dv, const double* p,
+                          double alpha, double* partial, double* out, hipStream_t st) {
+  k_kinetic<<<kRedBlocks, kTpb, 0, st>>>(n, mass, dv, p, alpha, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+}
+void launch_cn_sq(int n, const double* g, const double* xi, double scale, double* partial,
+                  double* out, hipStream_t st) {
+  k_cn<<<kRedBlocks, kTpb, 0, st>>>(n, g, xi, scale, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+}
+void launch_max_speed(int n, const double* v, double* partial, double* out, hipStream_t st) {
+  k_maxspeed<<<kRedBlocks, kTpb, 0, st>>>(n, v, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 1, partial, out);
+}
+void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
+                     hipStream_t st) {
+  if (n > 0) k_axpy_dev<<<blocks_for(n), kTpb, 0, st>>>(n, a_dev, sign, x, y);
+}
+void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st) {
+  if (n > 0) k_axpy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);
+}
+void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st) {
+  if (n > 0) k_scale_copy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);
+}
+void launch_sub(long long n, const double* a, const double* b, double* y, hipStream_t st) {
+  if (n > 0) k_sub<<<blocks_for(n), kTpb, 0, st>>>(n, a, b, y);
+}
+void launch_lbfgs_alpha(const double* rho, const double* dot, double* alpha, hipStream_t st) {
+  k_lbfgs_alpha<<<1, 1, 0, st>>>(rho, dot, alpha);
+}
+void launch_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef,
+                       hipStream_t st) {
+  k_lbfgs_coef<<<1, 1, 0, st>>>(rho, dot, alpha, coef);
+}
+void launch_to_f32(long long n, const double* x, float* y, hipStream_t st) {
+  if (n > 0) k_to_f32<<<blocks_for(n), kTpb, 0, st>>>(n, x, y);
+}
+void launch_to_f64(long long n, const float* x, double* y, hipStream_t st) {
+  if (n > 0) k_to_f64<<<blocks_for(n), kTpb, 0, st>>>(n, x, y);
+}
+void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
+                               hipStream_t st) {
+  if (n > 0) k_bj_apply<<<blocks_for(n), kTpb, 0, st>>>(n, Dinv, x, y, sign);
+}
+
+}  // namespace hot

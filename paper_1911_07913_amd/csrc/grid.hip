@@ -1,0 +1,293 @@
+// Binning, stable counting sort and active-node bookkeeping (integer work).
+//
+// The step starts by binning particles by their base node (the lowest node of
+// the 3x3x3 quadratic B-spline stencil, Sec. 6) and finding the active grid by
+// traversing particles (Sec. 3.1: the sparsity pattern changes every step).
+// Coarse levels hold the parents of active fine nodes under the linear node
+// embedding of Sec. 4.2 (coarse node J sits at fine node 2J).  Everything here
+// is integer arithmetic and bit-exact.
+#include "hot_internal.h"
+
+namespace hot {
+namespace {
+
+constexpr int kTpb = 256;
+
+inline unsigned blocks_for(long long n, int tpb = kTpb) {
+  return (unsigned)((n + tpb - 1) / tpb);
+}
+
+__global__ void k_bin_keys(SceneDev s, int n, const double* __restrict__ x, int* __restrict__ keys,
+                           int* __restrict__ counts, int* __restrict__ err) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int b[3];
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    // (x - o)/dx with IEEE division, then floor(t - 1/2): same operations as
+    // the CPU reference so the integer key is bit-identical.
+    double t = (x[3 * p + a] - s.origin[a]) / s.dx;
+    ok = ok && (t >= 2.0) && (t <= (double)(s.cells[a] - 3));
+    double fb = floor(t - 0.5);
+    int bi = ok ? (int)fb : 1;
+    b[a] = bi;
+  }
+  if (!ok) {
+    atomicOr(err, 1);
+    b[0] = b[1] = b[2] = 1;
+  }
+  int key = (int)pidx(s.g0, b[0], b[1], b[2]);
+  keys[p] = key;
+  atomicAdd(&counts[key], 1);
+}
+
+__global__ void k_scatter(int n, const int* __restrict__ keys, const int* __restrict__ start,
+                          int* __restrict__ cursor, int* __restrict__ tmp) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int k = keys[p];
+  int pos = start[k] + atomicAdd(&cursor[k], 1);
+  tmp[pos] = p;
+}
+
+// Order each cell's segment by the caller-order particle index: the result is
+// the stable sort by key of the caller-ordered particles.
+__global__ void k_sort_segments(long long ncells, const int* __restrict__ start,
+                                const int* __restrict__ counts, const int* __restrict__ id,
+                                int* __restrict__ tmp) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int cnt = counts[c];
+  if (cnt < 2) return;
+  int* seg = tmp + start[c];
+  for (int i = 1; i < cnt; ++i) {
+    int v = seg[i];
+    int key = id[v];
+    int j = i - 1;
+    while (j >= 0 && id[seg[j]] > key) {
+      seg[j + 1] = seg[j];
+      --j;
+    }
+    seg[j + 1] = v;
+  }
+}
+
+__global__ void k_permute(int n, const int* __restrict__ perm, Particles src, Particles dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p = perm[i];
+  for (int a = 0; a < 3; ++a) {
+    dst.x[3 * i + a] = src.x[3 * p + a];
+    dst.v[3 * i + a] = src.v[3 * p + a];
+  }
+  for (int a = 0; a < 9; ++a) {
+    dst.C[9 * i + a] = src.C[9 * p + a];
+    dst.F[9 * i + a] = src.F[9 * p + a];
+  }
+  dst.vol[i] = src.vol[p];
+  dst.mat[i] = src.mat[p];
+  dst.id[i] = src.id[p];
+}
+
+// Active fine nodes: the 27 nodes of every non-empty base cell.
+__global__ void k_mark_fine(GridGeom g, const int* __restrict__ counts, int* __restrict__ flags) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ptotal) return;
+  if (counts[c] == 0) return;
+  int bx, by, bz;
+  unpidx(g, c, bx, by, bz);
+  for (int k = 0; k < 27; ++k) flags[pidx(g, bx + k % 3, by + (k / 3) % 3, bz + k / 9)] = 1;
+}
+
+// Parents of a fine coordinate under the linear embedding: even -> c/2,
+// odd -> (c-1)/2 and (c+1)/2.
+__device__ inline int parents1d(int c, int* J) {
+  if ((c & 1) == 0) {
+    J[0] = c >> 1;
+    return 1;
+  }
+  J[0] = (c - 1) >> 1;
+  J[1] = (c + 1) >> 1;
+  return 2;
+}
+
+__global__ void k_mark_coarse(GridGeom fg, int nf, const int* __restrict__ fnodes, GridGeom cg,
+                              int* __restrict__ cflags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  int x, y, z;
+  unpidx(fg, fnodes[i], x, y, z);
+  int Jx[2], Jy[2], Jz[2];
+  int nx = parents1d(x, Jx), ny = parents1d(y, Jy), nz = parents1d(z, Jz);
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nz; ++c) cflags[pidx(cg, Jx[a], Jy[b], Jz[c])] = 1;
+}
+
+__global__ void k_compact(long long total, const int* __restrict__ flags,
+                          const int* __restrict__ scan, int* __restrict__ map,
+                          int* __restrict__ nodes) {
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  if (flags[p]) {
+    int idx = scan[p];
+    map[p] = idx;
+    nodes[idx] = (int)p;
+  } else {
+    map[p] = -1;
+  }
+}
+
+__global__ void k_fill(long long n, int* p, int v) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Level-0 symbolic pattern: block (i, j) is present iff some particle's
+// stencil holds both nodes, i.e. some non-empty base cell b satisfies
+// b in [max(i,j) - 2, min(i,j)] on every axis.  One thread per (row, word).
+__global__ void k_fine_pattern(LevelView L, const int* __restrict__ counts) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L.n * 4) return;
+  int row = (int)(t >> 2), w = (int)(t & 3);
+  int x, y, z;
+  unpidx(L.g, L.nodes[row], x, y, z);
+  uint32_t bits = 0;
+  for (int k = 0; k < 32; ++k) {
+    int s = w * 32 + k;
+    if (s >= kSlots) break;
+    int dx = s % 5 - 2, dy = (s / 5) % 5 - 2, dz = s / 25 - 2;
+    int lo[3] = {max(x, x + dx) - 2, max(y, y + dy) - 2, max(z, z + dz) - 2};
+    int hi[3] = {min(x, x + dx), min(y, y + dy), min(z, z + dz)};
+    bool any = false;
+    for (int bz = lo[2]; bz <= hi[2] && !any; ++bz)
+      for (int by = lo[1]; by <= hi[1] && !any; ++by)
+        for (int bx = lo[0]; bx <= hi[0] && !any; ++bx) {
+          if (bx < -2 || by < -2 || bz < -2 || bx >= L.g.dims[0] + 2 || by >= L.g.dims[1] + 2 ||
+              bz >= L.g.dims[2] + 2)
+            continue;
+          any = counts[pidx(L.g, bx, by, bz)] > 0;
+        }
+    if (any) bits |= (1u << k);
+  }
+  L.pat[t] = bits;
+}
+
+// ---- exclusive scan (three passes over tiles of 2048 ints)
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kTpb * kScanItems;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+  // Hillis-Steele inclusive scan in LDS, then shift.
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kTpb; off <<= 1) {
+    int a = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int incl = sh[t];
+  total = sh[kTpb - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_reduce(long long n, const int* __restrict__ in, int* __restrict__ sums) {
+  __shared__ int sh[kTpb];
+  long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  int total;
+  block_exclusive_scan(s, sh, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int nt, int* __restrict__ sums, int* __restrict__ total_out) {
+  __shared__ int sh[kTpb];
+  int carry = 0;
+  for (int base = 0; base < nt; base += kTpb) {
+    int i = base + threadIdx.x;
+    int v = (i < nt) ? sums[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, sh, total);
+    if (i < nt) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void k_scan_down(long long n, const int* __restrict__ in, const int* __restrict__ sums,
+                            int* __restrict__ out) {
+  __shared__ int sh[kTpb];
+  long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, total) + sums[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+}  // namespace
+
+void launch_bin_keys(const SceneDev& s, int n, const double* x, int* keys, int* counts, int* err,
+                     hipStream_t st) {
+  if (n > 0) k_bin_keys<<<blocks_for(n), kTpb, 0, st>>>(s, n, x, keys, counts, err);
+}
+void launch_scatter_sorted(int n, const int* keys, const int* start, int* cursor, int* tmp,
+                           hipStream_t st) {
+  if (n > 0) k_scatter<<<blocks_for(n), kTpb, 0, st>>>(n, keys, start, cursor, tmp);
+}
+void launch_sort_segments(long long ncells, const int* start, const int* counts, const int* id,
+                          int* tmp, hipStream_t st) {
+  k_sort_segments<<<blocks_for(ncells), kTpb, 0, st>>>(ncells, start, counts, id, tmp);
+}
+void launch_permute_particles(int n, const int* perm, const Particles& src, const Particles& dst,
+                              hipStream_t st) {
+  if (n > 0) k_permute<<<blocks_for(n), kTpb, 0, st>>>(n, perm, src, dst);
+}
+void launch_mark_fine(const GridGeom& g, const int* counts, int* flags, hipStream_t st) {
+  k_mark_fine<<<blocks_for(g.ptotal), kTpb, 0, st>>>(g, counts, flags);
+}
+void launch_mark_coarse(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& coarse,
+                        int* cflags, hipStream_t st) {
+  if (nf > 0) k_mark_coarse<<<blocks_for(nf), kTpb, 0, st>>>(fine, nf, fnodes, coarse, cflags);
+}
+void launch_compact(long long total, const int* flags, const int* scan, int* map, int* nodes,
+                    hipStream_t st) {
+  k_compact<<<blocks_for(total), kTpb, 0, st>>>(total, flags, scan, map, nodes);
+}
+void launch_fill_int(long long n, int* p, int v, hipStream_t st) {
+  if (n > 0) k_fill<<<blocks_for(n), kTpb, 0, st>>>(n, p, v);
+}
+void launch_fine_pattern(const LevelView& L, const int* counts, hipStream_t st) {
+  if (L.n > 0) k_fine_pattern<<<blocks_for((long long)L.n * 4), kTpb, 0, st>>>(L, counts);
+}
+
+size_t scan_temp_bytes(long long n) {
+  long long nt = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(nt + 1) * sizeof(int);
+}
+
+void launch_scan(long long n, const int* in, int* out, void* temp, hipStream_t st) {
+  int nt = (int)((n + kScanTile - 1) / kScanTile);
+  int* sums = (int*)temp;
+  if (nt == 0) {
+    k_fill<<<1, 1, 0, st>>>(1, out, 0);
+    return;
+  }
+  k_scan_reduce<<<nt, kTpb, 0, st>>>(n, in, sums);
+  k_scan_sums<<<1, kTpb, 0, st>>>(nt, sums, out + n);
+  k_scan_down<<<nt, kTpb, 0, st>>>(n, in, sums, out);
+}
+
+}  // namespace hot

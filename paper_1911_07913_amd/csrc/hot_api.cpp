@@ -1,0 +1,1154 @@
+// Host side of libhot: scene state, the implicit MPM step pipeline and the
+// HOT quasi-Newton loop (Alg. HOT) sequencing the HIP kernels, plus the C ABI
+// declared in include/hot.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hot.h"
+#include "hot_internal.h"
+
+using namespace hot;
+
+namespace {
+
+thread_local std::string g_err;
+
+hot_status fail(hot_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(HOT_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),  \
+                  __FILE__, __LINE__);                                                  \
+  } while (0)
+
+#define TRY(expr)                      \
+  do {                                 \
+    hot_status s_ = (expr);            \
+    if (s_ < 0) return s_;             \
+  } while (0)
+
+void* default_alloc(size_t bytes, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+void default_free(void* p, void*) {
+  if (p) (void)hipFree(p);
+}
+
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+enum {
+  S_GP = 0,
+  S_DEP = 1,
+  S_DEK = 2,
+  S_YS = 3,
+  S_YY = 4,
+  S_SS = 5,
+  S_CN = 6,
+  S_E0 = 7,
+  S_VMAX = 8,
+  NSCAL = 16
+};
+
+struct LevelH {
+  GridGeom g;
+  int n = 0;
+  DBuf nodes, map, H, Hb, Dinv, Dinv32, diag, diag32, freed, pat;
+  DBuf b, u, r, t;  // V-cycle vectors
+};
+
+}  // namespace
+
+struct hot_scene {
+  hot_params prm;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hot_allocator alloc;
+  SceneDev sd;
+  int n = 0;
+  double t = 0.0;
+  std::vector<hot_material> mats;
+  std::vector<hot_bc> bcs;
+  double bc_speed = 0.0;
+  size_t bytes_live = 0;
+  std::vector<DBuf*> owned;
+  bool mixed = false;
+  int levels = 1;
+
+  Particles P[2];
+  int cur = 0;
+  DBuf pbuf[2];
+  DBuf f, key, keys, tmp, Cp, psi[2], S[2];
+  int pc = 0;  // current psi/S buffer
+  // level-0 grid
+  DBuf counts, start, cursor, flags, scan, scan_temp, err;
+  LevelH L[kMaxLevels];
+  // level-0 node data
+  DBuf mass, vstar, xi, fixed;
+  // solver vectors
+  DBuf dv, dvt, g, gnew, q, r, pcg_work, pcg_iters, vin, vout;
+  std::vector<DBuf> Sh, Yh;
+  DBuf ddot, dalpha, dcoef, drho, dscal, partial, tables;
+  double* hscal = nullptr;
+  int* herr = nullptr;
+  int node_cap = 0;
+  // last-step logs
+  std::vector<int> log_int;
+  std::vector<double> log_cn;
+  int vcycles = 0;
+  hipEvent_t ev[5];
+  bool prepared = false;
+  double dt_prepared = 0.0;
+};
+
+namespace {
+
+hot_status ensure(hot_scene* s, DBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return HOT_OK;
+  if (b.p) {
+    // keep the stream ordered: free only after pending work completes
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(HOT_E_DEVICE, "sync failed");
+    s->alloc.free(b.p, s->alloc.ctx);
+    s->bytes_live -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  b.p = s->alloc.alloc(want, s->alloc.ctx);
+  if (!b.p) return fail(HOT_E_NOMEM, "device allocation of %zu bytes failed", want);
+  b.cap = want;
+  s->bytes_live += want;
+  return HOT_OK;
+}
+
+template <typename T>
+T* P(const DBuf& b) {
+  return (T*)b.p;
+}
+
+void release(hot_scene* s, DBuf& b) {
+  if (b.p) s->alloc.free(b.p, s->alloc.ctx);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+hot_status readback(hot_scene* s) {
+  HIPCHK(hipMemcpyAsync(s->hscal, s->dscal.p, NSCAL * sizeof(double), hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return HOT_OK;
+}
+
+hot_status read_int(hot_scene* s, const int* dptr, int* out) {
+  HIPCHK(hipMemcpyAsync(s->herr, dptr, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *out = *s->herr;
+  return HOT_OK;
+}
+
+LevelView view(hot_scene* s, int m) {
+  LevelH& L = s->L[m];
+  LevelView v;
+  v.n = L.n;
+  v.g = L.g;
+  v.nodes = P<int>(L.nodes);
+  v.map = P<int>(L.map);
+  v.H = P<double>(L.H);
+  v.Hb = P<uint16_t>(L.Hb);
+  v.Dinv = P<double>(L.Dinv);
+  v.Dinv32 = P<float>(L.Dinv32);
+  v.diag = P<double>(L.diag);
+  v.diag32 = P<float>(L.diag32);
+  v.free_dof = P<uint8_t>(L.freed);
+  v.pat = P<uint32_t>(L.pat);
+  return v;
+}
+
+double lame_mu(double E, double nu) { return E / (2.0 * (1.0 + nu)); }
+double lame_lam(double E, double nu) { return E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)); }
+
+double bc_max_speed(const std::vector<hot_bc>& bcs) {
+  double s = 0.0;
+  for (const hot_bc& b : bcs) {
+    const double* p = b.p;
+    if (b.kind == HOT_BC_GRIP) {
+      double a[3] = {p[9], p[10], p[11]};
+      double na = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+      for (int k = 0; k < 3; ++k) a[k] /= na;
+      double rmax = 0.0;
+      for (int bx = 0; bx < 2; ++bx)
+        for (int by = 0; by < 2; ++by)
+          for (int bz = 0; bz < 2; ++bz) {
+            double d[3] = {p[3 * bx] - p[6], p[3 * by + 1] - p[7], p[3 * bz + 2] - p[8]};
+            double c[3] = {a[1] * d[2] - a[2] * d[1], a[2] * d[0] - a[0] * d[2],
+                           a[0] * d[1] - a[1] * d[0]};
+            rmax = std::max(rmax, std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
+          }
+      s = std::max(s, std::fabs(p[12]) * rmax);
+    } else if (b.kind == HOT_BC_SPHERE) {
+      s = std::max(s, std::sqrt(p[4] * p[4] + p[5] * p[5] + p[6] * p[6]));
+    }
+  }
+  return s;
+}
+
+hot_status validate_params(const hot_params* p) {
+  if (!p) return fail(HOT_E_INVALID, "params is NULL");
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(HOT_E_INVALID, "dx must be > 0");
+  for (int a = 0; a < 3; ++a) {
+    if (p->grid_cells[a] < 6) return fail(HOT_E_INVALID, "grid_cells must be >= 6 per axis");
+    if (!std::isfinite(p->origin[a]) || !std::isfinite(p->gravity[a]))
+      return fail(HOT_E_INVALID, "origin/gravity must be finite");
+  }
+  long long tot = (long long)(p->grid_cells[0] + 5) * (p->grid_cells[1] + 5) * (p->grid_cells[2] + 5);
+  if (tot > (1LL << 31) - 1) return fail(HOT_E_INVALID, "grid too large");
+  if (!(p->cfl > 0.0) || !(p->max_dt > 0.0)) return fail(HOT_E_INVALID, "cfl and max_dt must be > 0");
+  if (!(p->tol >= 0.0)) return fail(HOT_E_INVALID, "tol must be >= 0");
+  if (p->lbfgs_history < 0 || p->lbfgs_history > 64)
+    return fail(HOT_E_INVALID, "lbfgs_history must be in [0, 64]");
+  if (p->mg_levels < 1 || p->mg_levels > kMaxLevels)
+    return fail(HOT_E_INVALID, "mg_levels must be in [1, %d]", kMaxLevels);
+  if (p->max_iters < 1) return fail(HOT_E_INVALID, "max_iters must be >= 1");
+  if (p->smoother_sweeps < 1) return fail(HOT_E_INVALID, "smoother_sweeps must be >= 1");
+  if (p->precision != HOT_FP64 && p->precision != HOT_MIXED)
+    return fail(HOT_E_INVALID, "unknown precision");
+  if (p->reserved[0] || p->reserved[1] || p->reserved[2])
+    return fail(HOT_E_INVALID, "reserved fields must be zero");
+  return HOT_OK;
+}
+
+hot_status validate_positions(const hot_params* p, int64_t n, const double* x) {
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double t = (x[3 * i + a] - p->origin[a]) / p->dx;
+      if (!(t >= 2.0 && t <= (double)(p->grid_cells[a] - 3)))
+        return fail(HOT_E_INVALID, "particle %lld outside [origin+2dx, origin+(cells-3)dx]",
+                    (long long)i);
+    }
+  return HOT_OK;
+}
+
+// Active fine nodes of a particle set, counted on the host (footprint).
+long long count_active_nodes(const hot_params* p, int64_t n, const double* x) {
+  long long nx = p->grid_cells[0] + 1, ny = p->grid_cells[1] + 1, nz = p->grid_cells[2] + 1;
+  std::vector<uint8_t> mark((size_t)(nx * ny * nz), 0);
+  long long cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    long long b[3];
+    for (int a = 0; a < 3; ++a) {
+      double t = (x[3 * i + a] - p->origin[a]) / p->dx;
+      b[a] = (long long)std::floor(t - 0.5);
+      if (b[a] < 0) b[a] = 0;
+    }
+    for (int k = 0; k < 27; ++k) {
+      long long X = std::min(b[0] + k % 3, nx - 1), Y = std::min(b[1] + (k / 3) % 3, ny - 1),
+                Z = std::min(b[2] + k / 9, nz - 1);
+      size_t id = (size_t)(X + nx * (Y + ny * Z));
+      if (!mark[id]) {
+        mark[id] = 1;
+        ++cnt;
+      }
+    }
+  }
+  return cnt;
+}
+
+size_t estimate_bytes(const hot_params* p, int64_t n, long long nodes) {
+  long long g0 = (long long)(p->grid_cells[0] + 5) * (p->grid_cells[1] + 5) * (p->grid_cells[2] + 5);
+  size_t per_particle = 8 * (2 * 25 + 3 + 45 + 2 + 18) + 4 * 6;
+  size_t w = (size_t)p->lbfgs_history + 1;
+  size_t per_node = 9000 + 72 + 24 + 3 + 16 + 8 * 3 * (10 + 2 * w) + 4 * 3 * 4 * 2 + 40;
+  if (p->precision == HOT_MIXED) per_node += 2250 + 36 + 12;
+  double lev = 1.0 + 1.0 / 8 + 1.0 / 64 + 1.0 / 512;
+  size_t bytes = (size_t)n * per_particle + (size_t)(g0 * 4 * 8 * 1.2) +
+                 (size_t)(nodes * 1.3 * per_node * lev) + (1 << 20);
+  return bytes;
+}
+
+// ---------------------------------------------------------------- prepare
+hot_status alloc_level(hot_scene* s, int m, int n) {
+  LevelH& L = s->L[m];
+  size_t vsz = s->mixed ? 4 : 8;
+  TRY(ensure(s, L.nodes, (size_t)n * 4));
+  TRY(ensure(s, L.H, (size_t)n * kRowVals * 8));
+  TRY(ensure(s, L.Dinv, (size_t)n * 72));
+  TRY(ensure(s, L.diag, (size_t)n * 24));
+  TRY(ensure(s, L.freed, (size_t)n * 3));
+  TRY(ensure(s, L.pat, (size_t)n * 16));
+  if (s->mixed) {
+    TRY(ensure(s, L.Hb, (size_t)n * kRowVals * 2));
+    TRY(ensure(s, L.Dinv32, (size_t)n * 36));
+    TRY(ensure(s, L.diag32, (size_t)n * 12));
+  }
+  TRY(ensure(s, L.b, (size_t)n * 3 * vsz));
+  TRY(ensure(s, L.u, (size_t)n * 3 * vsz));
+  TRY(ensure(s, L.r, (size_t)n * 3 * vsz));
+  TRY(ensure(s, L.t, (size_t)n * 3 * vsz));
+  L.n = n;
+  return HOT_OK;
+}
+
+hot_status alloc_nodes0(hot_scene* s, int n) {
+  size_t v = (size_t)n * 3 * 8;
+  TRY(ensure(s, s->mass, (size_t)n * 8));
+  TRY(ensure(s, s->xi, (size_t)n * 8));
+  TRY(ensure(s, s->fixed, (size_t)n * 4));
+  TRY(ensure(s, s->vstar, v));
+  TRY(ensure(s, s->dv, v));
+  TRY(ensure(s, s->dvt, v));
+  TRY(ensure(s, s->g, v));
+  TRY(ensure(s, s->gnew, v));
+  TRY(ensure(s, s->q, v));
+  TRY(ensure(s, s->r, v));
+  TRY(ensure(s, s->vin, v));
+  TRY(ensure(s, s->vout, v));
+  int W = s->prm.lbfgs_history + 1;
+  s->Sh.resize(W);
+  s->Yh.resize(W);
+  for (int a = 0; a < W; ++a) {
+    TRY(ensure(s, s->Sh[a], v));
+    TRY(ensure(s, s->Yh[a], v));
+  }
+  return HOT_OK;
+}
+
+// Binning, active grid and hierarchy index sets, P2G, level-0 Hessian and the
+// Galerkin hierarchy: everything of a step that precedes the solve.
+hot_status prepare(hot_scene* s, double dt) {
+  hipStream_t st = s->stream;
+  const int n = s->n;
+  const GridGeom& g0 = s->sd.g0;
+  Particles& src = s->P[s->cur];
+  // -- binning: base-node keys, counting sort, stable within a cell
+  launch_fill_int(g0.ptotal, P<int>(s->counts), 0, st);
+  launch_fill_int(1, P<int>(s->err), 0, st);
+  launch_bin_keys(s->sd, n, src.x, P<int>(s->keys), P<int>(s->counts), P<int>(s->err), st);
+  launch_scan(g0.ptotal, P<int>(s->counts), P<int>(s->start), s->scan_temp.p, st);
+  int errv = 0;
+  TRY(read_int(s, P<int>(s->err), &errv));
+  if (errv) return fail(HOT_E_INVALID, "a particle left the valid grid region");
+  launch_fill_int(g0.ptotal, P<int>(s->cursor), 0, st);
+  launch_scatter_sorted(n, P<int>(s->keys), P<int>(s->start), P<int>(s->cursor), P<int>(s->tmp), st);
+  launch_sort_segments(g0.ptotal, P<int>(s->start), P<int>(s->counts), src.id, P<int>(s->tmp), st);
+  launch_permute_particles(n, P<int>(s->tmp), src, s->P[1 - s->cur], st);
+  s->cur = 1 - s->cur;
+  Particles& pt = s->P[s->cur];
+  launch_particle_frac(s->sd, n, pt.x, P<double>(s->f), P<int>(s->key), st);
+  // -- active nodes per level
+  for (int m = 0; m < s->levels; ++m) {
+    LevelH& L = s->L[m];
+    launch_fill_int(L.g.ptotal, P<int>(s->flags), 0, st);
+    if (m == 0)
+      launch_mark_fine(L.g, P<int>(s->counts), P<int>(s->flags), st);
+    else
+      launch_mark_coarse(s->L[m - 1].g, s->L[m - 1].n, P<int>(s->L[m - 1].nodes), L.g,
+                         P<int>(s->flags), st);
+    launch_scan(L.g.ptotal, P<int>(s->flags), P<int>(s->scan), s->scan_temp.p, st);
+    int nm = 0;
+    TRY(read_int(s, P<int>(s->scan) + L.g.ptotal, &nm));
+    TRY(alloc_level(s, m, nm));
+    if (m == 0) TRY(alloc_nodes0(s, nm));
+    launch_compact(L.g.ptotal, P<int>(s->flags), P<int>(s->scan), P<int>(L.map), P<int>(L.nodes), st);
+  }
+  LevelView L0 = view(s, 0);
+  launch_fine_pattern(L0, P<int>(s->counts), st);
+  // -- P2G, gravity, boundary velocities
+  launch_p2g(s->sd, L0, P<double>(s->f), pt.v, pt.C, pt.vol, pt.mat, P<int>(s->start),
+             P<int>(s->counts), dt, s->t + dt, P<double>(s->mass), P<double>(s->vstar),
+             P<double>(s->xi), P<int>(s->fixed), st);
+  HIPCHK(hipEventRecord(s->ev[1], st));
+  // -- level-0 Hessian at dv = 0 and the Galerkin hierarchy
+  launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol, pt.mat,
+                          P<double>(s->vstar), dt, P<double>(s->Cp), st);
+  launch_assemble_h0(s->sd, L0, P<double>(s->f), pt.F, P<double>(s->Cp), P<int>(s->start),
+                     P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), st);
+  for (int m = 0; m + 1 < s->levels; ++m) launch_rap(view(s, m), view(s, m + 1), st);
+  if (s->mixed)
+    for (int m = 0; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
+  size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
+  TRY(ensure(s, s->pcg_work, pcg));
+  TRY(ensure(s, s->pcg_iters, (size_t)(s->prm.max_iters * 3 + 16) * 4));
+  HIPCHK(hipGetLastError());
+  s->prepared = true;
+  s->dt_prepared = dt;
+  s->vcycles = 0;
+  return HOT_OK;
+}
+
+// ---------------------------------------------------------------- V-cycle
+// r = V(q): one multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi
+// smoothing and an inexact Jacobi-PCG coarsest solve.  In the mixed policy the
+// cycle runs on FP32 vectors over BF16 blocks; q and r stay FP64.
+hot_status vcycle(hot_scene* s, const double* q, double* r) {
+  hipStream_t st = s->stream;
+  const bool mx = s->mixed;
+  const int M = s->levels;
+  const int sweeps = s->prm.smoother_sweeps;
+  void* b0;
+  if (mx) {
+    launch_to_f32((long long)s->L[0].n * 3, q, P<float>(s->L[0].b), st);
+    b0 = s->L[0].b.p;
+  } else {
+    b0 = (void*)q;
+  }
+  std::vector<void*> bs(M), us(M);
+  bs[0] = b0;
+  for (int m = 0; m < M; ++m) {
+    us[m] = s->L[m].u.p;
+    if (m > 0) bs[m] = s->L[m].b.p;
+  }
+  for (int m = 0; m + 1 < M; ++m) {
+    LevelView Lm = view(s, m);
+    launch_jacobi_first(Lm, mx, bs[m], us[m], st);
+    for (int k = 1; k < sweeps; ++k) {
+      launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
+      std::swap(s->L[m].u, s->L[m].t);
+      us[m] = s->L[m].u.p;
+    }
+    launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st);
+    launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], st);
+  }
+  int slot = std::min(s->vcycles, s->prm.max_iters * 3 + 15);
+  launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p,
+                    P<int>(s->pcg_iters) + slot, 500, 0.5, st);
+  s->vcycles++;
+  for (int m = M - 2; m >= 0; --m) {
+    LevelView Lm = view(s, m);
+    launch_prolong_add(Lm, view(s, m + 1), mx, us[m + 1], us[m], st);
+    for (int k = 0; k < sweeps; ++k) {
+      launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
+      std::swap(s->L[m].u, s->L[m].t);
+      us[m] = s->L[m].u.p;
+    }
+  }
+  long long n3 = (long long)s->L[0].n * 3;
+  if (mx)
+    launch_to_f64(n3, P<float>(s->L[0].u), r, st);
+  else
+    HIPCHK(hipMemcpyAsync(r, s->L[0].u.p, n3 * 8, hipMemcpyDeviceToDevice, st));
+  return HOT_OK;
+}
+
+// ---------------------------------------------------------------- solve
+void eval_trial(hot_scene* s, const double* dv, const double* p, double alpha, int out) {
+  Particles& pt = s->P[s->cur];
+  launch_particle_eval(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
+                       pt.mat, P<double>(s->vstar), dv, p, alpha, s->dt_prepared,
+                       P<double>(s->psi[out]), P<double>(s->S[out]), s->stream);
+}
+
+void gradient(hot_scene* s, const double* dv, int sbuf, double* g) {
+  launch_gradient(s->sd, view(s, 0), P<double>(s->f), P<double>(s->S[sbuf]), P<int>(s->start),
+                  P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), dv, s->dt_prepared, g,
+                  s->stream);
+}
+
+// HOT quasi-Newton solve (Alg. HOT): L-BFGS two-loop with the V-cycle as the
+// initial inverse Hessian, backtracking line search from alpha = 1 (Armijo,
+// c1 = 1e-4, halving, at most 30 halvings, energy change summed as
+// per-particle and per-node differences), secant pairs kept when
+// y^T s > 1e-12 |y||s|, and the node-wise CN stopping test (Sec. 5.2).
+hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
+  hipStream_t st = s->stream;
+  const int n0 = s->L[0].n;
+  const long long N = (long long)n0 * 3;
+  const double dt = s->dt_prepared;
+  const double cn_scale = 24.0 * s->prm.dx * s->prm.dx * dt;
+  const double thresh = s->prm.tol * std::sqrt((double)n0);
+  const int w = s->prm.lbfgs_history;
+  double* dscal = P<double>(s->dscal);
+  double* partial = P<double>(s->partial);
+  double* dv = P<double>(s->dv);
+  double* dvt = P<double>(s->dvt);
+  double* g = P<double>(s->g);
+  double* gnew = P<double>(s->gnew);
+  double* q = P<double>(s->q);
+  double* r = P<double>(s->r);
+  s->log_int.clear();
+  s->log_cn.clear();
+  launch_fill_double(N, dv, 0.0, st);
+  s->pc = 0;
+  eval_trial(s, dv, nullptr, 0.0, s->pc);
+  launch_sum(s->n, P<double>(s->psi[s->pc]), partial, dscal + S_E0, st);
+  gradient(s, dv, s->pc, g);
+  launch_cn_sq(n0, g, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
+  TRY(readback(s));
+  double E = s->hscal[S_E0];
+  double cn = std::sqrt(s->hscal[S_CN]);
+  if (!std::isfinite(E) || !std::isfinite(cn))
+    return fail(HOT_E_NONFINITE, "non-finite energy or gradient at dv = 0");
+  if (stats) {
+    stats->E0 = E;
+    stats->cn0 = cn;
+    stats->cn_tol = thresh;
+  }
+  s->log_cn.push_back(cn);
+  std::vector<int> hist;  // slot ids, oldest first
+  const int W = w + 1;
+  int it = 0, backtracks = 0, fallbacks = 0, skipped = 0;
+  bool conv = cn <= thresh;
+  std::vector<std::pair<int, int>> vc_range;
+  while (!conv && it < s->prm.max_iters) {
+    int vc0 = s->vcycles;
+    // -- two-loop recursion
+    launch_scale_copy(N, -1.0, g, q, st);
+    for (int k = (int)hist.size() - 1; k >= 0; --k) {
+      int a = hist[k];
+      launch_dot(N, P<double>(s->Sh[a]), q, partial, P<double>(s->ddot) + a, st);
+      launch_lbfgs_alpha(P<double>(s->drho) + a, P<double>(s->ddot) + a, P<double>(s->dalpha) + a, st);
+      launch_axpy_dev(N, P<double>(s->dalpha) + a, -1.0, P<double>(s->Yh[a]), q, st);
+    }
+    TRY(vcycle(s, q, r));
+    for (size_t k = 0; k < hist.size(); ++k) {
+      int a = hist[k];
+      launch_dot(N, P<double>(s->Yh[a]), r, partial, P<double>(s->ddot) + a, st);
+      launch_lbfgs_coef(P<double>(s->drho) + a, P<double>(s->ddot) + a, P<double>(s->dalpha) + a,
+                        P<double>(s->dcoef) + a, st);
+      launch_axpy_dev(N, P<double>(s->dcoef) + a, 1.0, P<double>(s->Sh[a]), r, st);
+    }
+    // -- descent check and the first trial in one readback
+    int trial = 1 - s->pc;
+    launch_dot(N, g, r, partial, dscal + S_GP, st);
+    eval_trial(s, dv, r, 1.0, trial);
+    launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
+    launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
+    TRY(readback(s));
+    double gp = s->hscal[S_GP];
+    int fb = 0;
+    if (!(gp < 0.0)) {
+      hist.clear();
+      fb = 1;
+      launch_scale_copy(N, -1.0, g, q, st);
+      TRY(vcycle(s, q, r));
+      launch_dot(N, g, r, partial, dscal + S_GP, st);
+      TRY(readback(s));
+      gp = s->hscal[S_GP];
+      if (!(gp < 0.0)) {
+        fb = 2;
+        launch_block_jacobi_apply(n0, P<double>(s->L[0].Dinv), g, r, -1.0, st);
+        launch_dot(N, g, r, partial, dscal + S_GP, st);
+        TRY(readback(s));
+        gp = s->hscal[S_GP];
+      }
+      eval_trial(s, dv, r, 1.0, trial);
+      launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
+      launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
+      TRY(readback(s));
+      ++fallbacks;
+    }
+    double alpha = 1.0;
+    bool accepted = false;
+    int halvings = 0;
+    double dE = 0.0;
+    for (halvings = 0; halvings <= 30; ++halvings) {
+      if (halvings > 0) {
+        eval_trial(s, dv, r, alpha, trial);
+        launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial,
+                        dscal + S_DEP, st);
+        launch_kinetic_delta(n0, P<double>(s->mass), dv, r, alpha, partial, dscal + S_DEK, st);
+        TRY(readback(s));
+      }
+      dE = s->hscal[S_DEP] + s->hscal[S_DEK];
+      if (std::isfinite(dE) && dE <= 1e-4 * alpha * gp) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    vc_range.push_back({vc0, s->vcycles});
+    if (!accepted) {
+      s->log_int.insert(s->log_int.end(), {-1, 0, fb, 0});
+      break;
+    }
+    backtracks += halvings;
+    // -- accept: dv_t = dv + alpha p, s = dv_t - dv, y = g_t - g
+    int slot = 0;
+    for (int a = 0; a < W; ++a)
+      if (std::find(hist.begin(), hist.end(), a) == hist.end()) {
+        slot = a;
+        break;
+      }
+    HIPCHK(hipMemcpyAsync(dvt, dv, N * 8, hipMemcpyDeviceToDevice, st));
+    launch_axpy(N, alpha, r, dvt, st);
+    launch_sub(N, dvt, dv, P<double>(s->Sh[slot]), st);
+    std::swap(s->dv, s->dvt);
+    dv = P<double>(s->dv);
+    dvt = P<double>(s->dvt);
+    s->pc = trial;
+    gradient(s, dv, s->pc, gnew);
+    launch_sub(N, gnew, g, P<double>(s->Yh[slot]), st);
+    launch_dots3(N, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), partial, dscal + S_YS, st);
+    launch_cn_sq(n0, gnew, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
+    TRY(readback(s));
+    double ys = s->hscal[S_YS], yy = s->hscal[S_YY], ss = s->hscal[S_SS];
+    bool keep = ys > 1e-12 * std::sqrt(yy * ss);
+    if (keep && w > 0) {
+      launch_rho(dscal + S_YS, P<double>(s->drho) + slot, st);
+      hist.push_back(slot);
+      if ((int)hist.size() > w) hist.erase(hist.begin());
+    }
+    if (!keep) ++skipped;
+    std::swap(s->g, s->gnew);
+    g = P<double>(s->g);
+    gnew = P<double>(s->gnew);
+    E += dE;
+    cn = std::sqrt(s->hscal[S_CN]);
+    if (!std::isfinite(cn)) return fail(HOT_E_NONFINITE, "non-finite gradient");
+    s->log_cn.push_back(cn);
+    s->log_int.insert(s->log_int.end(), {halvings, keep ? 0 : 1, fb, 0});
+    ++it;
+    conv = cn <= thresh;
+  }
+  // coarse-PCG iteration counts per L-BFGS iteration
+  int nv = std::min(s->vcycles, s->prm.max_iters * 3 + 16);
+  std::vector<int> pcg(nv > 0 ? nv : 1, 0);
+  if (nv > 0) {
+    HIPCHK(hipMemcpyAsync(pcg.data(), s->pcg_iters.p, nv * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  int cg_total = 0;
+  for (size_t k = 0; k < vc_range.size() && 4 * k + 3 < s->log_int.size(); ++k) {
+    int sum = 0;
+    for (int v = vc_range[k].first; v < vc_range[k].second && v < nv; ++v) sum += pcg[v];
+    s->log_int[4 * k + 3] = sum;
+    cg_total += sum;
+  }
+  *converged = conv;
+  if (stats) {
+    stats->E = E;
+    stats->cn = cn;
+    stats->iters = it;
+    stats->backtracks = backtracks;
+    stats->cg_iters_total = cg_total;
+    stats->converged = conv ? 1 : 0;
+    stats->fallbacks = fallbacks;
+    stats->skipped_pairs = skipped;
+  }
+  return HOT_OK;
+}
+
+hot_status choose_dt(hot_scene* s, double dt_in, double* dt_out) {
+  if (dt_in > 0.0) {
+    *dt_out = dt_in;
+    return HOT_OK;
+  }
+  launch_max_speed(s->n, s->P[s->cur].v, P<double>(s->partial), P<double>(s->dscal) + S_VMAX,
+                   s->stream);
+  TRY(readback(s));
+  double vmax = std::max(s->hscal[S_VMAX], s->bc_speed);
+  if (!std::isfinite(vmax)) return fail(HOT_E_NONFINITE, "non-finite particle velocity");
+  *dt_out = vmax > 0.0 ? std::min(s->prm.max_dt, s->prm.cfl * s->prm.dx / vmax) : s->prm.max_dt;
+  return HOT_OK;
+}
+
+hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  hipStream_t st = s->stream;
+  HIPCHK(hipEventRecord(s->ev[0], st));
+  double dt;
+  TRY(choose_dt(s, dt_in, &dt));
+  TRY(prepare(s, dt));
+  HIPCHK(hipEventRecord(s->ev[2], st));
+  bool conv = false;
+  TRY(solve(s, stats, &conv));
+  HIPCHK(hipEventRecord(s->ev[3], st));
+  Particles& pt = s->P[s->cur];
+  launch_g2p(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.x, pt.v, pt.C, pt.F,
+             pt.mat, P<double>(s->vstar), P<double>(s->dv), dt, st);
+  HIPCHK(hipEventRecord(s->ev[4], st));
+  HIPCHK(hipEventSynchronize(s->ev[4]));
+  HIPCHK(hipGetLastError());
+  s->t += dt;
+  s->prepared = false;
+  if (stats) {
+    stats->dt = dt;
+    stats->t = s->t;
+    stats->n_nodes = s->L[0].n;
+    stats->n_levels = s->levels;
+    hipEventElapsedTime(&stats->ms_prepare, s->ev[0], s->ev[1]);
+    hipEventElapsedTime(&stats->ms_hierarchy, s->ev[1], s->ev[2]);
+    hipEventElapsedTime(&stats->ms_solve, s->ev[2], s->ev[3]);
+    hipEventElapsedTime(&stats->ms_g2p, s->ev[3], s->ev[4]);
+  }
+  return conv ? HOT_OK : HOT_W_NOT_CONVERGED;
+}
+
+void destroy(hot_scene* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  DBuf* all[] = {&s->pbuf[0], &s->pbuf[1], &s->f, &s->key, &s->keys, &s->tmp, &s->Cp,
+                 &s->psi[0], &s->psi[1], &s->S[0], &s->S[1], &s->counts, &s->start,
+                 &s->cursor, &s->flags, &s->scan, &s->scan_temp, &s->err, &s->mass,
+                 &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
+                 &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
+                 &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables};
+  for (DBuf* b : all) release(s, *b);
+  for (auto& b : s->Sh) release(s, b);
+  for (auto& b : s->Yh) release(s, b);
+  for (int m = 0; m < kMaxLevels; ++m) {
+    LevelH& L = s->L[m];
+    DBuf* lb[] = {&L.nodes, &L.map, &L.H, &L.Hb, &L.Dinv, &L.Dinv32, &L.diag, &L.diag32,
+                  &L.freed, &L.pat, &L.b, &L.u, &L.r, &L.t};
+    for (DBuf* b : lb) release(s, *b);
+  }
+  if (s->hscal) (void)hipHostFree(s->hscal);
+  if (s->herr) (void)hipHostFree(s->herr);
+  for (int k = 0; k < 5; ++k)
+    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hot_last_error(void) { return g_err.c_str(); }
+
+hot_status hot_scene_footprint(const hot_params* params, int64_t n, const double* x,
+                               size_t* bytes_out) {
+  TRY(validate_params(params));
+  if (n <= 0 || !x || !bytes_out) return fail(HOT_E_INVALID, "bad arguments");
+  long long nodes = count_active_nodes(params, n, x);
+  *bytes_out = estimate_bytes(params, n, nodes);
+  return HOT_OK;
+}
+
+hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, const double* v,
+                          const double* F, const double* C, const double* vol0,
+                          const int32_t* mat_id, const hot_material* mats, int32_t n_mats,
+                          const hot_bc* bcs, int32_t n_bcs, const hot_allocator* alloc,
+                          void* hip_stream, hot_scene** out) {
+  if (!out) return fail(HOT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  TRY(validate_params(params));
+  if (n <= 0 || n > (1LL << 30)) return fail(HOT_E_INVALID, "n must be in [1, 2^30]");
+  if (!x || !v || !vol0 || !mat_id || !mats) return fail(HOT_E_INVALID, "NULL particle array");
+  if (n_mats < 1 || n_mats > kMaxMats) return fail(HOT_E_INVALID, "n_mats must be in [1, %d]", kMaxMats);
+  if (n_bcs < 0 || n_bcs > kMaxBcs || (n_bcs > 0 && !bcs))
+    return fail(HOT_E_INVALID, "n_bcs must be in [0, %d]", kMaxBcs);
+  for (int k = 0; k < n_mats; ++k) {
+    const hot_material& m = mats[k];
+    if (m.model != HOT_FCR && m.model != HOT_NEOHOOKEAN) return fail(HOT_E_INVALID, "bad model");
+    if (!(m.E > 0.0) || !std::isfinite(m.E)) return fail(HOT_E_INVALID, "E must be > 0");
+    if (!(m.nu > -1.0 && m.nu < 0.5)) return fail(HOT_E_INVALID, "nu must be in (-1, 0.5)");
+    if (!(m.density > 0.0) || !std::isfinite(m.density)) return fail(HOT_E_INVALID, "density must be > 0");
+    if (!(m.yield_stress >= 0.0)) return fail(HOT_E_INVALID, "yield_stress must be >= 0");
+  }
+  for (int k = 0; k < n_bcs; ++k) {
+    if (bcs[k].kind < 0 || bcs[k].kind > 2) return fail(HOT_E_INVALID, "bad bc kind");
+    for (int j = 0; j < 16; ++j)
+      if (!std::isfinite(bcs[k].p[j])) return fail(HOT_E_INVALID, "non-finite bc parameter");
+    if (bcs[k].kind == HOT_BC_GRIP) {
+      const double* p = bcs[k].p;
+      if (p[9] * p[9] + p[10] * p[10] + p[11] * p[11] == 0.0)
+        return fail(HOT_E_INVALID, "grip axis is zero");
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (mat_id[i] < 0 || mat_id[i] >= n_mats) return fail(HOT_E_INVALID, "mat_id out of range");
+    if (!(vol0[i] > 0.0) || !std::isfinite(vol0[i])) return fail(HOT_E_INVALID, "vol0 must be > 0");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(v[3 * i + a])) return fail(HOT_E_INVALID, "non-finite velocity");
+    for (int a = 0; a < 9; ++a) {
+      if (F && !std::isfinite(F[9 * i + a])) return fail(HOT_E_INVALID, "non-finite F");
+      if (C && !std::isfinite(C[9 * i + a])) return fail(HOT_E_INVALID, "non-finite C");
+    }
+    if (F) {
+      const double* f = F + 9 * i;
+      double J = f[0] * (f[4] * f[8] - f[5] * f[7]) - f[1] * (f[3] * f[8] - f[5] * f[6]) +
+                 f[2] * (f[3] * f[7] - f[4] * f[6]);
+      if (mats[mat_id[i]].model == HOT_NEOHOOKEAN && !(J > 0.0))
+        return fail(HOT_E_INVALID, "Neo-Hookean particle with det F <= 0");
+    }
+  }
+  TRY(validate_positions(params, n, x));
+
+  hot_scene* s = new hot_scene();
+  s->prm = *params;
+  for (int k = 0; k < 5; ++k) s->ev[k] = nullptr;
+  if (alloc && alloc->alloc && alloc->free) {
+    s->alloc = *alloc;
+  } else {
+    s->alloc.alloc = default_alloc;
+    s->alloc.free = default_free;
+    s->alloc.ctx = nullptr;
+  }
+  hot_status rc = HOT_OK;
+  auto bail = [&](hot_status st) {
+    destroy(s);
+    return st;
+  };
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(HOT_E_DEVICE, "stream creation failed"));
+    s->own_stream = true;
+  }
+  for (int k = 0; k < 5; ++k)
+    if (hipEventCreate(&s->ev[k]) != hipSuccess) return bail(fail(HOT_E_DEVICE, "event creation failed"));
+  if (hipHostMalloc((void**)&s->hscal, NSCAL * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&s->herr, sizeof(int)) != hipSuccess)
+    return bail(fail(HOT_E_DEVICE, "pinned host allocation failed"));
+  s->n = (int)n;
+  s->mixed = params->precision == HOT_MIXED;
+  s->levels = params->mg_levels;
+  s->mats.assign(mats, mats + n_mats);
+  s->bcs.assign(bcs, bcs + n_bcs);
+  s->bc_speed = bc_max_speed(s->bcs);
+  // device constants
+  SceneDev& sd = s->sd;
+  std::memset(&sd, 0, sizeof(sd));
+  sd.dx = params->dx;
+  sd.inv_dx = 1.0 / params->dx;
+  for (int a = 0; a < 3; ++a) {
+    sd.origin[a] = params->origin[a];
+    sd.gravity[a] = params->gravity[a];
+    sd.cells[a] = params->grid_cells[a];
+  }
+  sd.g0 = make_geom(params->grid_cells[0] + 1, params->grid_cells[1] + 1, params->grid_cells[2] + 1);
+  sd.n_mats = n_mats;
+  std::vector<MaterialDev> hm(n_mats);
+  for (int k = 0; k < n_mats; ++k) {
+    MaterialDev& m = hm[k];
+    m.model = mats[k].model;
+    m.mu = lame_mu(mats[k].E, mats[k].nu);
+    m.lam = lame_lam(mats[k].E, mats[k].nu);
+    m.density = mats[k].density;
+    m.yield = mats[k].yield_stress;
+    m.xi = std::sqrt(3.0 * (2.0 * m.mu + m.lam) * (2.0 * m.mu + m.lam) + 6.0 * m.lam * m.lam);
+  }
+  sd.n_bcs = n_bcs;
+  std::vector<BcDev> hb(std::max(n_bcs, 1));
+  for (int k = 0; k < n_bcs; ++k) {
+    hb[k].kind = bcs[k].kind;
+    for (int j = 0; j < 16; ++j) hb[k].p[j] = bcs[k].p[j];
+  }
+  {
+    size_t mb = sizeof(MaterialDev) * n_mats, bb = sizeof(BcDev) * hb.size();
+    if ((rc = ensure(s, s->tables, mb + bb)) < 0) return bail(rc);
+    if (hipMemcpy(s->tables.p, hm.data(), mb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)s->tables.p + mb, hb.data(), bb, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(HOT_E_DEVICE, "table upload failed"));
+    sd.mats = (const MaterialDev*)s->tables.p;
+    sd.bcs = (const BcDev*)((char*)s->tables.p + mb);
+  }
+  // level geometry
+  s->L[0].g = sd.g0;
+  for (int m = 1; m < s->levels; ++m) {
+    const GridGeom& f = s->L[m - 1].g;
+    s->L[m].g = make_geom(f.dims[0] / 2 + 1, f.dims[1] / 2 + 1, f.dims[2] / 2 + 1);
+  }
+  // particle buffers: one allocation per set
+  size_t per = (size_t)n * (3 + 3 + 9 + 9 + 1) * 8 + (size_t)n * 2 * 4;
+  for (int k = 0; k < 2; ++k) {
+    if ((rc = ensure(s, s->pbuf[k], per)) < 0) return bail(rc);
+    char* b = (char*)s->pbuf[k].p;
+    Particles& Pp = s->P[k];
+    Pp.x = (double*)b;
+    Pp.v = Pp.x + 3 * n;
+    Pp.C = Pp.v + 3 * n;
+    Pp.F = Pp.C + 9 * n;
+    Pp.vol = Pp.F + 9 * n;
+    Pp.mat = (int*)(Pp.vol + n);
+    Pp.id = Pp.mat + n;
+  }
+  DBuf* pb[] = {&s->f, &s->Cp, &s->psi[0], &s->psi[1], &s->S[0], &s->S[1]};
+  size_t pbs[] = {(size_t)n * 24, (size_t)n * 45 * 8, (size_t)n * 8, (size_t)n * 8,
+                  (size_t)n * 72, (size_t)n * 72};
+  for (int k = 0; k < 6; ++k)
+    if ((rc = ensure(s, *pb[k], pbs[k])) < 0) return bail(rc);
+  DBuf* ib[] = {&s->key, &s->keys, &s->tmp};
+  for (DBuf* b : ib)
+    if ((rc = ensure(s, *b, (size_t)n * 4)) < 0) return bail(rc);
+  long long pt = sd.g0.ptotal;
+  if ((rc = ensure(s, s->counts, pt * 4)) < 0 || (rc = ensure(s, s->start, (pt + 1) * 4)) < 0 ||
+      (rc = ensure(s, s->cursor, pt * 4)) < 0 || (rc = ensure(s, s->flags, pt * 4)) < 0 ||
+      (rc = ensure(s, s->scan, (pt + 1) * 4)) < 0 ||
+      (rc = ensure(s, s->scan_temp, scan_temp_bytes(pt))) < 0 || (rc = ensure(s, s->err, 64)) < 0)
+    return bail(rc);
+  for (int m = 0; m < s->levels; ++m)
+    if ((rc = ensure(s, s->L[m].map, s->L[m].g.ptotal * 4)) < 0) return bail(rc);
+  int W = params->lbfgs_history + 1;
+  if ((rc = ensure(s, s->ddot, W * 8)) < 0 || (rc = ensure(s, s->dalpha, W * 8)) < 0 ||
+      (rc = ensure(s, s->dcoef, W * 8)) < 0 || (rc = ensure(s, s->drho, W * 8)) < 0 ||
+      (rc = ensure(s, s->dscal, NSCAL * 8)) < 0 || (rc = ensure(s, s->partial, kRedBlocks * 3 * 8)) < 0)
+    return bail(rc);
+  // upload (host staging in caller order; ids = caller indices)
+  std::vector<char> host(per);
+  double* hx = (double*)host.data();
+  std::memcpy(hx, x, n * 24);
+  std::memcpy(hx + 3 * n, v, n * 24);
+  double* hC = hx + 6 * n;
+  double* hF = hC + 9 * n;
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 9; ++a) {
+      hC[9 * i + a] = C ? C[9 * i + a] : 0.0;
+      hF[9 * i + a] = F ? F[9 * i + a] : ((a % 4 == 0) ? 1.0 : 0.0);
+    }
+  double* hvol = hF + 9 * n;
+  std::memcpy(hvol, vol0, n * 8);
+  int* hmat = (int*)(hvol + n);
+  std::memcpy(hmat, mat_id, n * 4);
+  int* hid = hmat + n;
+  for (int64_t i = 0; i < n; ++i) hid[i] = (int)i;
+  if (hipMemcpyAsync(s->pbuf[0].p, host.data(), per, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return bail(fail(HOT_E_DEVICE, "upload failed"));
+  s->cur = 0;
+  *out = s;
+  return HOT_OK;
+}
+
+hot_status hot_step(hot_scene* scene, double dt, hot_step_stats* stats) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (!std::isfinite(dt)) return fail(HOT_E_INVALID, "dt must be finite");
+  return do_step(scene, dt, stats);
+}
+
+hot_status hot_read_particles(const hot_scene* scene, int64_t n, double* x, double* v, double* F,
+                              double* C) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (n != scene->n) return fail(HOT_E_INVALID, "n does not match the scene");
+  hot_scene* s = const_cast<hot_scene*>(scene);
+  size_t per = (size_t)n * (3 + 3 + 9 + 9 + 1) * 8 + (size_t)n * 2 * 4;
+  std::vector<char> host(per);
+  HIPCHK(hipMemcpyAsync(host.data(), s->pbuf[s->cur].p, per, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const double* hx = (const double*)host.data();
+  const double* hv = hx + 3 * n;
+  const double* hC = hv + 3 * n;
+  const double* hF = hC + 9 * n;
+  const int* hid = (const int*)(hF + 10 * n);
+  hid += n;  // skip mat
+  for (int64_t i = 0; i < n; ++i) {
+    int o = hid[i];
+    if (x) std::memcpy(x + 3 * o, hx + 3 * i, 24);
+    if (v) std::memcpy(v + 3 * o, hv + 3 * i, 24);
+    if (C) std::memcpy(C + 9 * o, hC + 9 * i, 72);
+    if (F) std::memcpy(F + 9 * o, hF + 9 * i, 72);
+  }
+  return HOT_OK;
+}
+
+hot_status hot_scene_info(const hot_scene* scene, int64_t* n, double* t) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (n) *n = scene->n;
+  if (t) *t = scene->t;
+  return HOT_OK;
+}
+
+void hot_destroy_scene(hot_scene* scene) { destroy(scene); }
+
+// ---------------------------------------------------------------- debug
+hot_status hot_debug_prepare(hot_scene* scene, double dt) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  double d;
+  TRY(choose_dt(scene, dt, &d));
+  TRY(prepare(scene, d));
+  HIPCHK(hipStreamSynchronize(scene->stream));
+  return HOT_OK;
+}
+
+hot_status hot_debug_apply(hot_scene* scene, int32_t op, const double* in, double* out) {
+  if (!scene || !in || !out) return fail(HOT_E_INVALID, "NULL argument");
+  hot_scene* s = scene;
+  if (!s->prepared) return fail(HOT_E_INVALID, "call hot_debug_prepare first");
+  long long N = (long long)s->L[0].n * 3;
+  hipStream_t st = s->stream;
+  HIPCHK(hipMemcpyAsync(s->vin.p, in, N * 8, hipMemcpyHostToDevice, st));
+  double* vin = P<double>(s->vin);
+  double* vout = P<double>(s->vout);
+  if (op == 0) {
+    TRY(vcycle(s, vin, vout));
+  } else if (op == 1) {
+    eval_trial(s, vin, nullptr, 0.0, 0);
+    gradient(s, vin, 0, vout);
+  } else if (op == 2) {
+    eval_trial(s, vin, nullptr, 0.0, 0);
+    launch_sum(s->n, P<double>(s->psi[0]), P<double>(s->partial), P<double>(s->dscal) + S_E0, st);
+    launch_kinetic_delta(s->L[0].n, P<double>(s->mass), vin, vin, -1.0, P<double>(s->partial),
+                         P<double>(s->dscal) + S_DEK, st);
+    TRY(readback(s));
+    // kinetic delta with alpha = -1 is sum 1/2 m (0 - |dv|^2)
+    out[0] = s->hscal[S_E0] - s->hscal[S_DEK];
+    return HOT_OK;
+  } else if (op == 3) {
+    launch_spmv(view(s, 0), vin, vout, st);
+  } else {
+    return fail(HOT_E_INVALID, "unknown op");
+  }
+  HIPCHK(hipMemcpyAsync(out, vout, N * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HOT_OK;
+}
+
+hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, void* dst,
+                          size_t bytes, size_t* needed) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  hot_scene* s = const_cast<hot_scene*>(scene);
+  if (level < 0 || level >= s->levels) return fail(HOT_E_INVALID, "bad level");
+  const LevelH& L = s->L[level];
+  const void* src = nullptr;
+  size_t sz = 0;
+  bool host = false;
+  std::vector<int> counts;
+  switch (what) {
+    case HOT_DBG_PERM: src = s->P[s->cur].id; sz = (size_t)s->n * 4; break;
+    case HOT_DBG_LEVEL_NODES: src = L.nodes.p; sz = (size_t)L.n * 4; break;
+    case HOT_DBG_LEVEL_PATTERN: src = L.pat.p; sz = (size_t)L.n * 16; break;
+    case HOT_DBG_LEVEL_MATRIX: src = L.H.p; sz = (size_t)L.n * kRowVals * 8; break;
+    case HOT_DBG_LEVEL_FREE: src = L.freed.p; sz = (size_t)L.n * 3; break;
+    case HOT_DBG_NODE_MASS: src = s->mass.p; sz = (size_t)s->L[0].n * 8; break;
+    case HOT_DBG_NODE_VSTAR: src = s->vstar.p; sz = (size_t)s->L[0].n * 24; break;
+    case HOT_DBG_NODE_XI: src = s->xi.p; sz = (size_t)s->L[0].n * 8; break;
+    case HOT_DBG_NODE_FIXED: src = s->fixed.p; sz = (size_t)s->L[0].n * 4; break;
+    case HOT_DBG_DV: src = s->dv.p; sz = (size_t)s->L[0].n * 24; break;
+    case HOT_DBG_LOG_INT: src = s->log_int.data(); sz = s->log_int.size() * 4; host = true; break;
+    case HOT_DBG_LOG_CN: src = s->log_cn.data(); sz = s->log_cn.size() * 8; host = true; break;
+    case HOT_DBG_COUNTS: {
+      counts.assign(16, 0);
+      counts[0] = s->n;
+      counts[1] = s->levels;
+      for (int m = 0; m < s->levels && m < 8; ++m) counts[2 + m] = s->L[m].n;
+      counts[10] = (int)(s->log_int.size() / 4);
+      src = counts.data();
+      sz = 64;
+      host = true;
+      break;
+    }
+    default: return fail(HOT_E_INVALID, "unknown debug array %d", what);
+  }
+  if (needed) *needed = sz;
+  if (!dst) return HOT_OK;
+  if (bytes < sz) return fail(HOT_E_INVALID, "buffer too small (%zu < %zu)", bytes, sz);
+  if (sz == 0) return HOT_OK;
+  if (host) {
+    std::memcpy(dst, src, sz);
+    return HOT_OK;
+  }
+  if (what == HOT_DBG_LEVEL_NODES) {
+    // convert padded indices to plain linear indices of the level's node grid
+    std::vector<int> tmpv(L.n);
+    HIPCHK(hipMemcpyAsync(tmpv.data(), src, sz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int* o = (int*)dst;
+    for (int i = 0; i < L.n; ++i) {
+      int x, y, z;
+      unpidx(L.g, tmpv[i], x, y, z);
+      o[i] = x + L.g.dims[0] * (y + L.g.dims[1] * z);
+    }
+    return HOT_OK;
+  }
+  HIPCHK(hipMemcpyAsync(dst, src, sz, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return HOT_OK;
+}
+
+// ---------------------------------------------------------------- serving
+}  // extern "C"
+
+struct hot_batch {
+  size_t budget = 0;
+  int max_slots = 0;
+  size_t used = 0;
+  struct Slot {
+    hot_scene* scene;
+    int steps_left;
+    int64_t tag;
+    size_t bytes;
+  };
+  std::vector<Slot> slots;
+};
+
+extern "C" {
+
+hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out) {
+  if (!out || max_slots < 1 || hbm_budget_bytes == 0) return fail(HOT_E_INVALID, "bad arguments");
+  hot_batch* b = new hot_batch();
+  b->budget = hbm_budget_bytes;
+  b->max_slots = max_slots;
+  *out = b;
+  return HOT_OK;
+}
+
+hot_status hot_batch_add(hot_batch* b, hot_scene* s, int32_t n_steps, int64_t tag) {
+  if (!b || !s || n_steps < 1) return fail(HOT_E_INVALID, "bad arguments");
+  size_t need = std::max(s->bytes_live, (size_t)1);
+  // a scene's buffers grow to their working size on its first step; reserve
+  // room for the larger of what it holds and its estimate
+  if ((int)b->slots.size() >= b->max_slots || b->used + need > b->budget)
+    return fail(HOT_E_NOMEM, "batch full: %zu + %zu > %zu bytes or no free slot", b->used, need,
+                b->budget);
+  b->slots.push_back({s, n_steps, tag, need});
+  b->used += need;
+  return HOT_OK;
+}
+
+hot_status hot_batch_round(hot_batch* b, int64_t* done_tags, int32_t* n_done, int32_t cap,
+                           int32_t* n_resident) {
+  if (!b || !n_done) return fail(HOT_E_INVALID, "bad arguments");
+  *n_done = 0;
+  size_t ns = b->slots.size();
+  std::vector<hot_status> rc(ns, HOT_OK);
+  std::vector<std::string> errs(ns);
+  // every resident scene runs one step; each scene drives its own stream from
+  // its own host thread so the device overlaps the scenes' kernels
+  std::vector<std::thread> th;
+  th.reserve(ns);
+  for (size_t k = 0; k < ns; ++k)
+    th.emplace_back([&, k]() {
+      rc[k] = hot_step(b->slots[k].scene, 0.0, nullptr);
+      if (rc[k] < 0) errs[k] = g_err;
+    });
+  for (auto& t : th) t.join();
+  hot_status worst = HOT_OK;
+  std::vector<hot_batch::Slot> keep;
+  for (size_t k = 0; k < ns; ++k) {
+    hot_batch::Slot sl = b->slots[k];
+    if (rc[k] < 0) {
+      worst = rc[k];
+      g_err = errs[k];
+    }
+    sl.steps_left -= 1;
+    if (sl.steps_left <= 0 || rc[k] < 0) {
+      if (*n_done < cap && done_tags) done_tags[*n_done] = sl.tag;
+      (*n_done)++;
+      b->used -= sl.bytes;
+    } else {
+      keep.push_back(sl);
+    }
+  }
+  b->slots.swap(keep);
+  if (n_resident) *n_resident = (int32_t)b->slots.size();
+  return worst;
+}
+
+void hot_batch_destroy(hot_batch* b) { delete b; }
+
+}  // extern "C"

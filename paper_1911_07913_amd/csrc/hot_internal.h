@@ -1,0 +1,200 @@
+// Internal declarations shared by the HIP translation units of libhot.
+//
+// Data layout in HBM (one scene):
+//   particles  SoA, sorted by base cell every step: x[3n], v[3n], C[9n], F[9n]
+//              (row-major 3x3 per particle), vol[n], mat[n], id[n] (caller
+//              order index).
+//   grids      every level m has a dense "padded" map over its node grid with
+//              a halo of 2 nodes per side (so +-2 stencil offsets never leave
+//              the array): map[pidx] = compact node index or -1, and the list
+//              nodes[i] = padded index of active node i, in increasing linear
+//              order (x fastest).
+//   matrices   "diagonal storage": every row keeps 125 3x3 blocks, one per
+//              neighbour offset (dx,dy,dz) in [-2,2]^3, slot s = (dx+2) +
+//              5(dy+2) + 25(dz+2); row i occupies 1125 consecutive values
+//              [i][slot][3][3].  FP64, or BF16 in the mixed-precision V-cycle.
+//   vectors    node vectors interleaved [n][3].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+namespace hot {
+
+constexpr int kSlots = 125;
+constexpr int kBlock = 9;
+constexpr int kRowVals = kSlots * kBlock;  // 1125
+constexpr int kCenter = 62;                // slot of offset (0,0,0)
+constexpr int kMaxLevels = 8;
+constexpr int kMaxMats = 64;
+constexpr int kMaxBcs = 32;
+
+struct MaterialDev {
+  int model;   // 0 = fixed-corotated, 1 = Neo-Hookean
+  double mu, lam, density, yield, xi;
+};
+
+struct BcDev {
+  int kind;
+  double p[16];
+};
+
+// Geometry of one level's node grid.
+struct GridGeom {
+  int dims[3];   // node counts per axis (unpadded)
+  int pd[3];     // padded dims = dims + 4
+  long long ptotal;
+};
+
+// Everything the particle/grid kernels of level 0 need (passed by value).
+struct SceneDev {
+  double dx, inv_dx;
+  double origin[3];
+  double gravity[3];
+  int cells[3];
+  GridGeom g0;
+  int n_mats, n_bcs;
+  const MaterialDev* mats;  // device array [n_mats]
+  const BcDev* bcs;         // device array [n_bcs]
+};
+
+// View of one level of the hierarchy.
+struct LevelView {
+  int n;
+  GridGeom g;
+  const int* nodes;     // [n] padded indices
+  const int* map;       // [ptotal]
+  double* H;            // [n][1125] FP64 blocks
+  uint16_t* Hb;         // [n][1125] BF16 blocks (mixed precision) or null
+  double* Dinv;         // [n][9]
+  float* Dinv32;        // [n][9] (mixed)
+  double* diag;         // [3n] scalar diagonal (coarsest PCG)
+  float* diag32;
+  uint8_t* free_dof;    // [3n]
+  uint32_t* pat;        // [n][4]
+};
+
+__host__ __device__ inline long long pidx(const GridGeom& g, int x, int y, int z) {
+  return (long long)(x + 2) + (long long)g.pd[0] * ((long long)(y + 2) + (long long)g.pd[1] * (z + 2));
+}
+__host__ __device__ inline void unpidx(const GridGeom& g, long long p, int& x, int& y, int& z) {
+  x = (int)(p % g.pd[0]) - 2;
+  long long r = p / g.pd[0];
+  y = (int)(r % g.pd[1]) - 2;
+  z = (int)(r / g.pd[1]) - 2;
+}
+__host__ __device__ inline long long slot_offset(const GridGeom& g, int s) {
+  int dx = s % 5 - 2, dy = (s / 5) % 5 - 2, dz = s / 25 - 2;
+  return (long long)dx + (long long)g.pd[0] * ((long long)dy + (long long)g.pd[1] * dz);
+}
+inline GridGeom make_geom(int nx, int ny, int nz) {
+  GridGeom g;
+  g.dims[0] = nx; g.dims[1] = ny; g.dims[2] = nz;
+  g.pd[0] = nx + 4; g.pd[1] = ny + 4; g.pd[2] = nz + 4;
+  g.ptotal = (long long)g.pd[0] * g.pd[1] * g.pd[2];
+  return g;
+}
+
+// ---------------------------------------------------------------- launchers
+// grid.hip: binning, stable counting sort, active nodes, coarse levels.
+void launch_bin_keys(const SceneDev& s, int n, const double* x, int* keys, int* counts,
+                     int* err, hipStream_t st);
+void launch_scatter_sorted(int n, const int* keys, const int* start, int* cursor, int* tmp,
+                           hipStream_t st);
+void launch_sort_segments(long long ncells, const int* start, const int* counts, const int* id,
+                          int* tmp, hipStream_t st);
+struct Particles {
+  double *x, *v, *C, *F, *vol;
+  int *mat, *id;
+};
+void launch_permute_particles(int n, const int* perm, const Particles& src, const Particles& dst,
+                              hipStream_t st);
+void launch_mark_fine(const GridGeom& g, const int* counts, int* flags, hipStream_t st);
+void launch_mark_coarse(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& coarse,
+                        int* cflags, hipStream_t st);
+void launch_compact(long long total, const int* flags, const int* scan, int* map, int* nodes,
+                    hipStream_t st);
+// exclusive scan of n ints; returns nothing, total is scan[n] (out has n+1).
+size_t scan_temp_bytes(long long n);
+void launch_scan(long long n, const int* in, int* out, void* temp, hipStream_t st);
+void launch_fill_int(long long n, int* p, int v, hipStream_t st);
+void launch_fine_pattern(const LevelView& L, const int* counts, hipStream_t st);
+
+// particles.hip
+void launch_particle_frac(const SceneDev& s, int n, const double* x, double* f, int* key,
+                          hipStream_t st);
+void launch_p2g(const SceneDev& s, const LevelView& L0, const double* f, const double* v,
+                const double* C, const double* vol, const int* mat, const int* cstart,
+                const int* ccount, double dt, double t_end, double* mass, double* vstar,
+                double* xi, int* fixed, hipStream_t st);
+void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
+                             const int* key, const double* F, const double* vol, const int* mat,
+                             const double* vstar, double dt, double* Cp, hipStream_t st);
+// energy/stress at dv + alpha*p: psi_out[n] = V_p psi, S_out[9n] = V_p P F^n^T
+void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
+                          const int* key, const double* F, const double* vol, const int* mat,
+                          const double* vstar, const double* dv, const double* p, double alpha,
+                          double dt, double* psi_out, double* S_out, hipStream_t st);
+void launch_gradient(const SceneDev& s, const LevelView& L0, const double* f, const double* S,
+                     const int* cstart, const int* ccount, const double* mass, const int* fixed,
+                     const double* dv, double dt, double* g, hipStream_t st);
+void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
+                double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
+                const double* dv, double dt, hipStream_t st);
+void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const double* f, const double* F,
+                        const double* Cp, const int* cstart, const int* ccount,
+                        const double* mass, const int* fixed, hipStream_t st);
+
+// matrix.hip
+void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);
+void launch_rap(const LevelView& F, const LevelView& Cv, hipStream_t st);
+void launch_to_bf16(const LevelView& L, hipStream_t st);
+// V-cycle pieces (FP64 and FP32/BF16 variants chosen by `mixed`)
+void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u, hipStream_t st);
+void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,
+                     hipStream_t st);
+void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u, void* u_out,
+                   hipStream_t st);
+void launch_restrict(const LevelView& F, const LevelView& Cv, bool mixed, const void* r,
+                     void* bc, hipStream_t st);
+void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, const void* uc,
+                        void* u, hipStream_t st);
+void launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
+                       int* iters_out, int max_iter, double rel, hipStream_t st);
+size_t coarse_pcg_work_bytes(int n);
+void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st);
+
+// blas.hip: deterministic reductions and vector updates on FP64 node vectors.
+constexpr int kRedBlocks = 512;
+void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
+                hipStream_t st);
+void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
+                  hipStream_t st);  // out[0]=a.b out[1]=a.a out[2]=b.b
+void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st);
+void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
+                     hipStream_t st);  // sum(a - b)
+void launch_kinetic_delta(int n, const double* mass, const double* dv, const double* p,
+                          double alpha, double* partial, double* out, hipStream_t st);
+void launch_cn_sq(int n, const double* g, const double* xi, double scale, double* partial,
+                  double* out, hipStream_t st);
+void launch_max_speed(int n, const double* v, double* partial, double* out, hipStream_t st);
+void launch_finish_sum(int nparts, const double* partial, double* out, hipStream_t st);
+// y = a*x + y with a read from device (a_dev[idx] * sign) or immediate
+void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
+                     hipStream_t st);
+void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st);
+void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st);
+void launch_sub(long long n, const double* a, const double* b, double* y, hipStream_t st);
+void launch_lbfgs_alpha(const double* rho, const double* dot, double* alpha, hipStream_t st);
+void launch_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef,
+                       hipStream_t st);
+void launch_to_f32(long long n, const double* x, float* y, hipStream_t st);
+void launch_to_f64(long long n, const float* x, double* y, hipStream_t st);
+void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
+                               hipStream_t st);
+void launch_fill_double(long long n, double* p, double v, hipStream_t st);
+void launch_rho(const double* ys, double* rho, hipStream_t st);
+
+}  // namespace hot

@@ -1,0 +1,310 @@
+"""ctypes binding of libhot (include/hot.h): argument marshalling only.
+
+Every step of the implicit MPM solve runs inside the HIP library; this module
+converts numpy arrays and small Python records to the C structs, and maps the
+status codes to exceptions.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhot.so")
+
+HOT_OK = 0
+HOT_W_NOT_CONVERGED = 1
+HOT_E_INVALID = -1
+HOT_E_NOMEM = -2
+HOT_E_DEVICE = -3
+HOT_E_NONFINITE = -4
+HOT_FP64 = 0
+HOT_MIXED = 1
+
+DBG_PERM = 1
+DBG_LEVEL_NODES = 10
+DBG_LEVEL_PATTERN = 11
+DBG_LEVEL_MATRIX = 12
+DBG_LEVEL_FREE = 13
+DBG_NODE_MASS = 20
+DBG_NODE_VSTAR = 21
+DBG_NODE_XI = 22
+DBG_NODE_FIXED = 23
+DBG_DV = 30
+DBG_LOG_INT = 40
+DBG_LOG_CN = 41
+DBG_COUNTS = 50
+
+EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_particles",
+           "hot_scene_info", "hot_destroy_scene", "hot_last_error", "hot_batch_create",
+           "hot_batch_add", "hot_batch_round", "hot_batch_destroy", "hot_debug_read",
+           "hot_debug_prepare", "hot_debug_apply"]
+
+
+class hot_material(C.Structure):
+    _fields_ = [("model", C.c_int32), ("E", C.c_double), ("nu", C.c_double),
+                ("density", C.c_double), ("yield_stress", C.c_double)]
+
+
+class hot_bc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("p", C.c_double * 16)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class hot_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class hot_params(C.Structure):
+    _fields_ = [("dx", C.c_double), ("grid_cells", C.c_int32 * 3), ("origin", C.c_double * 3),
+                ("gravity", C.c_double * 3), ("cfl", C.c_double), ("max_dt", C.c_double),
+                ("tol", C.c_double), ("lbfgs_history", C.c_int32), ("mg_levels", C.c_int32),
+                ("max_iters", C.c_int32), ("smoother_sweeps", C.c_int32),
+                ("precision", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class hot_step_stats(C.Structure):
+    _fields_ = [("dt", C.c_double), ("t", C.c_double), ("E0", C.c_double), ("E", C.c_double),
+                ("cn0", C.c_double), ("cn", C.c_double), ("cn_tol", C.c_double),
+                ("iters", C.c_int32), ("backtracks", C.c_int32), ("cg_iters_total", C.c_int32),
+                ("converged", C.c_int32), ("fallbacks", C.c_int32),
+                ("skipped_pairs", C.c_int32), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
+                ("ms_prepare", C.c_float), ("ms_hierarchy", C.c_float),
+                ("ms_solve", C.c_float), ("ms_g2p", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HotError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hot status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libhot.so (built by build.py).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1911_07913_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    L.hot_scene_footprint.argtypes = [C.POINTER(hot_params), C.c_int64, dp, C.POINTER(C.c_size_t)]
+    L.hot_init_scene.argtypes = [C.POINTER(hot_params), C.c_int64, dp, dp, dp, dp, dp, ip,
+                                 C.POINTER(hot_material), C.c_int32, C.POINTER(hot_bc), C.c_int32,
+                                 C.POINTER(hot_allocator), vp, C.POINTER(vp)]
+    L.hot_step.argtypes = [vp, C.c_double, C.POINTER(hot_step_stats)]
+    L.hot_read_particles.argtypes = [vp, C.c_int64, dp, dp, dp, dp]
+    L.hot_scene_info.argtypes = [vp, C.POINTER(C.c_int64), dp]
+    L.hot_destroy_scene.argtypes = [vp]
+    L.hot_destroy_scene.restype = None
+    L.hot_last_error.restype = C.c_char_p
+    L.hot_batch_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(vp)]
+    L.hot_batch_add.argtypes = [vp, vp, C.c_int32, C.c_int64]
+    L.hot_batch_round.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
+                                  C.POINTER(C.c_int32)]
+    L.hot_batch_destroy.argtypes = [vp]
+    L.hot_batch_destroy.restype = None
+    L.hot_debug_read.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.hot_debug_prepare.argtypes = [vp, C.c_double]
+    L.hot_debug_apply.argtypes = [vp, C.c_int32, dp, dp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("hot_destroy_scene", "hot_batch_destroy", "hot_last_error"):
+            f.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _check(st, ok_warn=True):
+    if st < 0 or (st > 0 and not ok_warn):
+        raise HotError(st, lib().hot_last_error().decode())
+    return st
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol=1e-6,
+                lbfgs_history=8, mg_levels=3, max_iters=500, smoother_sweeps=1,
+                precision=HOT_FP64):
+    p = hot_params()
+    p.dx = dx
+    for a in range(3):
+        p.grid_cells[a] = int(grid_cells[a])
+        p.origin[a] = origin[a]
+        p.gravity[a] = gravity[a]
+    p.cfl, p.max_dt, p.tol = cfl, max_dt, tol
+    p.lbfgs_history, p.mg_levels, p.max_iters = int(lbfgs_history), int(mg_levels), int(max_iters)
+    p.smoother_sweeps, p.precision = int(smoother_sweeps), int(precision)
+    return p
+
+
+def params_of(scene, precision=HOT_FP64, **over):
+    """hot_params from any object with the scene attributes (dx, grid_cells,
+    origin, gravity, cfl, max_dt, tol, lbfgs_history, mg_levels, max_iters)."""
+    kw = dict(cfl=scene.cfl, max_dt=scene.max_dt, tol=scene.tol,
+              lbfgs_history=scene.lbfgs_history, mg_levels=scene.mg_levels,
+              max_iters=scene.max_iters, precision=precision)
+    kw.update(over)
+    return make_params(scene.dx, scene.grid_cells, scene.origin, scene.gravity, **kw)
+
+
+class TorchAllocator:
+    """Route the library's device allocations through torch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self._alloc = ALLOC_FN(self._a)
+        self._free = FREE_FN(self._f)
+        self.struct = hot_allocator(self._alloc, self._free, None)
+
+    def _a(self, nbytes, ctx):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+        except Exception:
+            return None
+
+    def _f(self, ptr, ctx):
+        if ptr:
+            self._torch.cuda.caching_allocator_delete(ptr)
+
+
+class Scene:
+    """Owner of one hot_scene handle."""
+
+    def __init__(self, params, x, v, F, Cm, vol0, mat_id, materials, bcs, stream=None,
+                 allocator=None):
+        L = lib()
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = x.shape[0]
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(n, 9)
+        Cm = None if Cm is None else np.ascontiguousarray(Cm, dtype=np.float64).reshape(n, 9)
+        vol0 = np.ascontiguousarray(vol0, dtype=np.float64).reshape(n)
+        mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(n)
+        mats = (hot_material * len(materials))()
+        for k, m in enumerate(materials):
+            mats[k] = hot_material(int(m["model"]), m["E"], m["nu"], m["density"],
+                                   m.get("yield_stress", 0.0))
+        nb = len(bcs)
+        cb = (hot_bc * max(nb, 1))()
+        for k, b in enumerate(bcs):
+            cb[k].kind = int(b["kind"])
+            for j, val in enumerate(np.asarray(b["p"], dtype=np.float64)[:16]):
+                cb[k].p[j] = float(val)
+        self.params = params
+        self.n = n
+        self._allocator = allocator
+        h = C.c_void_p()
+        st = _check(L.hot_init_scene(C.byref(params), n, _dp(x), _dp(v), _dp(F), _dp(Cm),
+                                     _dp(vol0), mat_id.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     mats, len(materials), cb, nb,
+                                     C.byref(allocator.struct) if allocator else None,
+                                     C.c_void_p(stream) if stream else None, C.byref(h)))
+        self.handle = h
+        self.stats = None
+
+    @classmethod
+    def from_scene(cls, sc, precision=HOT_FP64, stream=None, allocator=None, **over):
+        return cls(params_of(sc, precision, **over), sc.x, sc.v, sc.F, sc.C, sc.vol0, sc.mat_id,
+                   sc.materials, sc.bcs, stream=stream, allocator=allocator)
+
+    def step(self, dt=0.0):
+        """hot_step; returns the status (0 or HOT_W_NOT_CONVERGED) and keeps the stats."""
+        s = hot_step_stats()
+        st = _check(lib().hot_step(self.handle, dt, C.byref(s)))
+        self.stats = s.as_dict()
+        return st
+
+    def read(self, F=True, Cm=True):
+        n = self.n
+        x = np.empty((n, 3))
+        v = np.empty((n, 3))
+        Fa = np.empty((n, 3, 3)) if F else None
+        Ca = np.empty((n, 3, 3)) if Cm else None
+        _check(lib().hot_read_particles(self.handle, n, _dp(x), _dp(v), _dp(Fa), _dp(Ca)))
+        return dict(x=x, v=v, F=Fa, C=Ca)
+
+    def info(self):
+        n = C.c_int64()
+        t = C.c_double()
+        _check(lib().hot_scene_info(self.handle, C.byref(n), C.byref(t)))
+        return n.value, t.value
+
+    def debug_read(self, what, level=0, dtype=np.float64):
+        L = lib()
+        need = C.c_size_t()
+        _check(L.hot_debug_read(self.handle, what, level, None, 0, C.byref(need)))
+        buf = np.empty(need.value // np.dtype(dtype).itemsize, dtype=dtype)
+        _check(L.hot_debug_read(self.handle, what, level, buf.ctypes.data_as(C.c_void_p),
+                                buf.nbytes, C.byref(need)))
+        return buf
+
+    def debug_prepare(self, dt=0.0):
+        _check(lib().hot_debug_prepare(self.handle, dt))
+
+    def debug_apply(self, op, vec):
+        vec = np.ascontiguousarray(vec, dtype=np.float64)
+        out = np.empty_like(vec)
+        _check(lib().hot_debug_apply(self.handle, op, _dp(vec), _dp(out)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().hot_destroy_scene(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint(params, x):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    out = C.c_size_t()
+    _check(lib().hot_scene_footprint(C.byref(params), x.shape[0], _dp(x), C.byref(out)))
+    return out.value
+
+
+class Batch:
+    """Continuous batching of independent scenes (hot_batch_*)."""
+
+    def __init__(self, budget_bytes, max_slots):
+        h = C.c_void_p()
+        _check(lib().hot_batch_create(budget_bytes, max_slots, C.byref(h)))
+        self.handle = h
+
+    def add(self, scene: Scene, n_steps: int, tag: int) -> bool:
+        st = lib().hot_batch_add(self.handle, scene.handle, n_steps, tag)
+        if st == HOT_E_NOMEM:
+            return False
+        _check(st)
+        return True
+
+    def round(self, cap=1024):
+        tags = (C.c_int64 * cap)()
+        nd = C.c_int32()
+        nr = C.c_int32()
+        _check(lib().hot_batch_round(self.handle, tags, C.byref(nd), cap, C.byref(nr)))
+        return [tags[k] for k in range(min(nd.value, cap))], nr.value
+
+    def close(self):
+        if self.handle:
+            lib().hot_batch_destroy(self.handle)
+            self.handle = None
