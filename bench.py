@@ -1,0 +1,189 @@
+"""Benchmark: implicit MPM steps/s on the 1.5M-particle twisting-bars scene.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one full hot_step: CFL time step, binning, active grid and
+hierarchy index sets, APIC P2G, level-0 Hessian, Galerkin hierarchy, the HOT
+quasi-Newton solve (two-loop, V-cycle, line search, CN test) and G2P.  The
+scene (4 Neo-Hookean bars of 192x16x16 cells, 8 particles per cell, E in
+{1e5..1e8} Pa, grips twisting at +-2 rad/s, 256x64x64 grid, dx = 1/64, 5
+Galerkin levels, L-BFGS window 8, CN tolerance 1e-6) is resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "implicit MPM steps/s @1.5M particles, FP64 vs mixed; served p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# CPU-baseline sample: same scene family, 4 bars of 24x6x6 cells
+SAMPLE = dict(side=6, length=24)
+
+
+def workload_name(side):
+    n = 4 * 192 * side * side * 8
+    return (f"twisting_bars: 4 Neo-Hookean bars 192x{side}x{side} cells, {n} particles, "
+            f"256x64x64 grid dx=1/64, 5-level Galerkin MG, L-BFGS w=8, CN eps=1e-6")
+
+
+def cpu_worker():
+    """Oracle timing on the bounded sample (run in a single-threaded child)."""
+    import hot_scenes as hs
+    import oracle as O
+    sc = hs.twisting_bars(**SAMPLE, n_steps=1)
+    t0 = time.perf_counter()
+    out, info = O.step(sc)
+    t1 = time.perf_counter()
+    print(json.dumps(dict(seconds=t1 - t0, n=sc.n, iters=info["iters"])))
+
+
+def cpu_baseline(n_full):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["HIP_VISIBLE_DEVICES"] = ""
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker"], env=env,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        return dict(error=r.stderr[-500:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    sec_full = d["seconds"] * n_full / d["n"]
+    return {"value": 1.0 / sec_full, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle step of 4 bars 24x6x6 cells ({d['n']} particles, "
+                       f"{d['iters']} L-BFGS iterations) took {d['seconds']:.1f} s on 1 core; "
+                       f"scaled linearly by particle count to {n_full}")}
+
+
+def run(precision, steps, warmup, side, profile=True):
+    import numpy as np
+    import torch
+
+    import hot_scenes as hs
+    from paper_1911_07913_amd import hot
+
+    sc = hs.twisting_bars(side=side)
+    stream = torch.cuda.Stream()
+    alloc = hot.TorchAllocator(0)
+    g = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream, allocator=alloc)
+    for _ in range(warmup):
+        g.step()
+    torch.cuda.synchronize()
+    if profile:
+        g.profile(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step()
+        stats.append(dict(g.stats))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read() if profile else {}
+    g.profile(False)
+    n = g.n
+    g.close()
+    return dict(seconds=t1 - t0, stats=stats, prof=prof, n=n)
+
+
+def roofline_of(prof):
+    # the dominant traced kernel by total time
+    name, (ms, launches, nbytes) = max(prof.items(), key=lambda kv: kv[1][0])
+    if launches == 0:
+        return None
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_ms": ms / launches, "launches": launches,
+            "algorithmic_bytes_per_launch": nbytes / launches}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side", type=int, default=16, help="bar cross-section (16: 1.5M particles)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-worker", action="store_true")
+    a = ap.parse_args()
+    if a.cpu_worker:
+        cpu_worker()
+        return 0
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
+              "(the step is a single-GPU solver; see the sharding notes in DESIGN.md)",
+              file=sys.stderr)
+        return 2
+    # torch first: libhot then binds to the HIP runtime torch already loaded,
+    # so torch's streams and allocations are valid inside the library
+    import torch
+    from paper_1911_07913_amd import hot
+    hot.lib()
+    assert torch.cuda.is_available(), "no HIP device"
+    torch.cuda.set_device(0)
+    precs = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
+             "both": [hot.HOT_FP64, hot.HOT_MIXED]}[a.precision]
+    results = {}
+    for p in precs:
+        results[p] = run(p, a.steps, a.warmup, a.side)
+    main_p = precs[0]
+    r = results[main_p]
+    value = a.steps / r["seconds"]
+    stats = r["stats"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1000.0 * r["seconds"] / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_p == hot.HOT_FP64 else "f64+f32/bf16",
+        "data": "synthetic",
+        "config": {"workload": workload_name(a.side), "particles": r["n"],
+                   "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed"},
+        "roofline": roofline_of(r["prof"]),
+        "per_step": {
+            "iters": [s["iters"] for s in stats],
+            "cg_iters": [s["cg_iters_total"] for s in stats],
+            "converged": [s["converged"] for s in stats],
+            "dt": [s["dt"] for s in stats],
+            "n_nodes": [s["n_nodes"] for s in stats],
+            "ms_prepare": [round(s["ms_prepare"], 3) for s in stats],
+            "ms_hierarchy": [round(s["ms_hierarchy"], 3) for s in stats],
+            "ms_solve": [round(s["ms_solve"], 3) for s in stats],
+            "ms_g2p": [round(s["ms_g2p"], 3) for s in stats],
+        },
+        "kernels": {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                        "gbs": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                    for k, v in r["prof"].items()},
+    }
+    if hot.HOT_MIXED in results and main_p != hot.HOT_MIXED:
+        rm = results[hot.HOT_MIXED]
+        line["mixed"] = {"value": a.steps / rm["seconds"], "unit": "steps/s",
+                         "ms_per_step": 1000.0 * rm["seconds"] / a.steps,
+                         "iters": [s["iters"] for s in rm["stats"]],
+                         "roofline": roofline_of(rm["prof"])}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(r["n"])
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -18,7 +18,7 @@
  *     given at creation (NULL: hipMalloc/hipFree) and released by
  *     hot_destroy_scene;
  *   - all device work of a scene is issued on the HIP stream given at
- *     creation (NULL: the default stream);
+ *     creation (NULL: a non-blocking stream created and owned by the scene);
  *   - SI units; particle arrays are row-major, n rows, in the caller's order;
  *   - a scene is not thread-safe; distinct scenes may be used from distinct
  *     host threads;
@@ -181,6 +181,27 @@ hot_status hot_batch_add(hot_batch* batch, hot_scene* scene, int32_t n_steps, in
 hot_status hot_batch_round(hot_batch* batch, int64_t* done_tags, int32_t* n_done, int32_t cap,
                            int32_t* n_resident);
 void hot_batch_destroy(hot_batch* batch);
+
+/* ---- tracing: HIP-event timing of individual kernels ---------------------
+ * When enabled, the library records a pair of HIP events on the scene's
+ * stream around every launch of the kernels below and accumulates, per
+ * kernel, the summed launch durations, the launch count and the algorithmic
+ * bytes those launches had to move (structural matrix blocks plus the node
+ * vectors each launch reads and writes once; padding and re-reads are not
+ * counted).  Enabling resets the counters. */
+enum {
+  HOT_PROF_SMOOTH0 = 0,    /* level-0 smoothing sweep (fused SpMV + update) */
+  HOT_PROF_RESIDUAL0 = 1,  /* level-0 residual b - H u */
+  HOT_PROF_ASSEMBLE = 2,   /* level-0 Hessian assembly */
+  HOT_PROF_RAP0 = 3,       /* Galerkin product level 0 -> 1 */
+  HOT_PROF_EVAL = 4,       /* per-particle energy / stress evaluation */
+  HOT_PROF_GRAD = 5,       /* gradient gather */
+  HOT_PROF_PHESS = 6,      /* per-particle projected stress derivative */
+  HOT_PROF_COUNT = 7
+};
+hot_status hot_profile_enable(hot_scene* scene, int32_t enable);
+hot_status hot_profile_read(const hot_scene* scene, int32_t kernel, double* total_ms,
+                            int64_t* launches, double* total_bytes);
 
 /* ---- test hooks (parity checks against an independent implementation) --- */
 enum {

@@ -173,6 +173,76 @@ __global__ void k_fine_pattern(LevelView L, const int* __restrict__ counts) {
   L.pat[t] = bits;
 }
 
+// Number of structurally present blocks of a level (popcount of its pattern),
+// written as a double.  One work-group of 1024 threads.
+__global__ void k_pattern_count(LevelView L, double* out) {
+  __shared__ unsigned long long sh[16];
+  unsigned long long c = 0;
+  long long nw = (long long)L.n * 4;
+  for (long long k = threadIdx.x; k < nw; k += 1024) c += __popc(L.pat[k]);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < 16; ++w) t += sh[w];
+    *out = (double)t;
+  }
+}
+
+// ---- work lists for the row-strip and cell-brick kernels
+// Segment = up to kSegRows consecutive active nodes of one x-line (same y, z)
+// whose x lies in one aligned window of kSegRows; nodes are sorted by linear
+// index, so a segment is a contiguous range of the node list.
+__global__ void k_seg_flags(LevelView L, int* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  int f = 1;
+  if (i > 0) {
+    int x0, y0, z0, x1, y1, z1;
+    unpidx(L.g, L.nodes[i - 1], x0, y0, z0);
+    unpidx(L.g, L.nodes[i], x1, y1, z1);
+    f = (y0 != y1 || z0 != z1 || ((x0 + 2) / kSegRows) != ((x1 + 2) / kSegRows)) ? 1 : 0;
+  }
+  flags[i] = f;
+}
+__global__ void k_seg_compact(int n, const int* __restrict__ flags, const int* __restrict__ scan,
+                              int* __restrict__ seg_begin) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == n) {
+    seg_begin[scan[n]] = n;
+    return;
+  }
+  if (flags[i]) seg_begin[scan[i]] = i;
+}
+
+// Cell bricks: kBrick^3 cells (in padded cell coordinates) holding particles.
+__global__ void k_mark_bricks(GridGeom g, BrickGeom bg, const int* __restrict__ counts,
+                              int* __restrict__ bflags) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ptotal) return;
+  if (counts[c] == 0) return;
+  int x = (int)(c % g.pd[0]);
+  long long r = c / g.pd[0];
+  int y = (int)(r % g.pd[1]);
+  int z = (int)(r / g.pd[1]);
+  bflags[(x / kBrick) + (long long)bg.bd[0] * ((y / kBrick) + (long long)bg.bd[1] * (z / kBrick))] = 1;
+}
+__global__ void k_brick_compact(long long total, const int* __restrict__ flags,
+                                const int* __restrict__ scan, int* __restrict__ bmap,
+                                int* __restrict__ blist) {
+  long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= total) return;
+  if (flags[b]) {
+    int id = scan[b];
+    bmap[b] = id;
+    blist[id] = (int)b;
+  } else {
+    bmap[b] = -1;
+  }
+}
+
 // ---- exclusive scan (three passes over tiles of 2048 ints)
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kTpb * kScanItems;
@@ -271,6 +341,25 @@ void launch_fill_int(long long n, int* p, int v, hipStream_t st) {
 }
 void launch_fine_pattern(const LevelView& L, const int* counts, hipStream_t st) {
   if (L.n > 0) k_fine_pattern<<<blocks_for((long long)L.n * 4), kTpb, 0, st>>>(L, counts);
+}
+
+void launch_seg_flags(const LevelView& L, int* flags, hipStream_t st) {
+  if (L.n > 0) k_seg_flags<<<blocks_for(L.n), kTpb, 0, st>>>(L, flags);
+}
+void launch_seg_compact(int n, const int* flags, const int* scan, int* seg_begin, hipStream_t st) {
+  k_seg_compact<<<blocks_for((long long)n + 1), kTpb, 0, st>>>(n, flags, scan, seg_begin);
+}
+void launch_mark_bricks(const GridGeom& g, const BrickGeom& bg, const int* counts, int* bflags,
+                        hipStream_t st) {
+  k_mark_bricks<<<blocks_for(g.ptotal), kTpb, 0, st>>>(g, bg, counts, bflags);
+}
+void launch_brick_compact(long long total, const int* flags, const int* scan, int* bmap, int* blist,
+                          hipStream_t st) {
+  k_brick_compact<<<blocks_for(total), kTpb, 0, st>>>(total, flags, scan, bmap, blist);
+}
+
+void launch_pattern_count(const LevelView& L, double* out, hipStream_t st) {
+  k_pattern_count<<<1, 1024, 0, st>>>(L, out);
 }
 
 size_t scan_temp_bytes(long long n) {

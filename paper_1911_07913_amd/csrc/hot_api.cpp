@@ -70,7 +70,8 @@ enum {
   S_CN = 6,
   S_E0 = 7,
   S_VMAX = 8,
-  NSCAL = 16
+  S_NNZ = 9,  // structural block count of levels 0..kMaxLevels-1 (slots 9..16)
+  NSCAL = 24
 };
 
 struct LevelH {
@@ -112,6 +113,10 @@ struct hot_scene {
   DBuf dv, dvt, g, gnew, q, r, pcg_work, pcg_iters, vin, vout;
   std::vector<DBuf> Sh, Yh;
   DBuf ddot, dalpha, dcoef, drho, dscal, partial, tables;
+  // work lists: row segments (assembly) and cell bricks (particle-to-node sums)
+  DBuf seg_begin, bmap, blist, bpartial;
+  int n_seg = 0;
+  Bricks bricks;
   double* hscal = nullptr;
   int* herr = nullptr;
   int node_cap = 0;
@@ -122,6 +127,14 @@ struct hot_scene {
   hipEvent_t ev[5];
   bool prepared = false;
   double dt_prepared = 0.0;
+  // kernel tracing
+  bool prof = false;
+  double prof_ms[HOT_PROF_COUNT] = {0};
+  int64_t prof_n[HOT_PROF_COUNT] = {0};
+  double prof_bytes[HOT_PROF_COUNT] = {0};
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;
+  size_t prof_used = 0;
 };
 
 namespace {
@@ -169,6 +182,37 @@ hot_status read_int(hot_scene* s, const int* dptr, int* out) {
   *out = *s->herr;
   return HOT_OK;
 }
+
+// ---- kernel tracing: event pairs around selected launches
+hot_status prof_begin(hot_scene* s, int kind, size_t* slot) {
+  *slot = (size_t)-1;
+  if (!s->prof) return HOT_OK;
+  if (s->prof_used + 2 > s->prof_ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      s->prof_ev.push_back(e);
+    }
+    s->prof_kind.resize(s->prof_ev.size() / 2 + 1, 0);
+  }
+  *slot = s->prof_used;
+  s->prof_kind[s->prof_used / 2] = kind;
+  s->prof_used += 2;
+  HIPCHK(hipEventRecord(s->prof_ev[*slot], s->stream));
+  return HOT_OK;
+}
+hot_status prof_end(hot_scene* s, size_t slot) {
+  if (slot == (size_t)-1) return HOT_OK;
+  HIPCHK(hipEventRecord(s->prof_ev[slot + 1], s->stream));
+  return HOT_OK;
+}
+#define PROF(s, kind, call)                    \
+  do {                                         \
+    size_t ps_;                                \
+    TRY(prof_begin((s), (kind), &ps_));        \
+    call;                                      \
+    TRY(prof_end((s), ps_));                   \
+  } while (0)
 
 LevelView view(hot_scene* s, int m) {
   LevelH& L = s->L[m];
@@ -351,6 +395,22 @@ hot_status prepare(hot_scene* s, double dt) {
   int errv = 0;
   TRY(read_int(s, P<int>(s->err), &errv));
   if (errv) return fail(HOT_E_INVALID, "a particle left the valid grid region");
+  // -- cell bricks holding particles
+  {
+    Bricks& B = s->bricks;
+    launch_fill_int(B.bg.total, P<int>(s->flags), 0, st);
+    launch_mark_bricks(g0, B.bg, P<int>(s->counts), P<int>(s->flags), st);
+    launch_scan(B.bg.total, P<int>(s->flags), P<int>(s->scan), s->scan_temp.p, st);
+    int nb = 0;
+    TRY(read_int(s, P<int>(s->scan) + B.bg.total, &nb));
+    TRY(ensure(s, s->blist, (size_t)nb * 4));
+    TRY(ensure(s, s->bpartial, (size_t)nb * kBrickWin * 5 * 8));
+    launch_brick_compact(B.bg.total, P<int>(s->flags), P<int>(s->scan), P<int>(s->bmap),
+                         P<int>(s->blist), st);
+    B.n = nb;
+    B.list = P<int>(s->blist);
+    B.map = P<int>(s->bmap);
+  }
   launch_fill_int(g0.ptotal, P<int>(s->cursor), 0, st);
   launch_scatter_sorted(n, P<int>(s->keys), P<int>(s->start), P<int>(s->cursor), P<int>(s->tmp), st);
   launch_sort_segments(g0.ptotal, P<int>(s->start), P<int>(s->counts), src.id, P<int>(s->tmp), st);
@@ -376,17 +436,38 @@ hot_status prepare(hot_scene* s, double dt) {
   }
   LevelView L0 = view(s, 0);
   launch_fine_pattern(L0, P<int>(s->counts), st);
+  // -- row segments of the level-0 assembly
+  {
+    launch_seg_flags(L0, P<int>(s->flags), st);
+    launch_scan(L0.n, P<int>(s->flags), P<int>(s->scan), s->scan_temp.p, st);
+    int ns = 0;
+    TRY(read_int(s, P<int>(s->scan) + L0.n, &ns));
+    TRY(ensure(s, s->seg_begin, (size_t)(ns + 1) * 4));
+    launch_seg_compact(L0.n, P<int>(s->flags), P<int>(s->scan), P<int>(s->seg_begin), st);
+    s->n_seg = ns;
+  }
   // -- P2G, gravity, boundary velocities
-  launch_p2g(s->sd, L0, P<double>(s->f), pt.v, pt.C, pt.vol, pt.mat, P<int>(s->start),
-             P<int>(s->counts), dt, s->t + dt, P<double>(s->mass), P<double>(s->vstar),
-             P<double>(s->xi), P<int>(s->fixed), st);
+  launch_p2g(s->sd, L0, s->bricks, P<double>(s->f), pt.v, pt.C, pt.vol, pt.mat, P<int>(s->start),
+             P<int>(s->counts), P<double>(s->bpartial), dt, s->t + dt, P<double>(s->mass),
+             P<double>(s->vstar), P<double>(s->xi), P<int>(s->fixed), st);
   HIPCHK(hipEventRecord(s->ev[1], st));
   // -- level-0 Hessian at dv = 0 and the Galerkin hierarchy
-  launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol, pt.mat,
-                          P<double>(s->vstar), dt, P<double>(s->Cp), st);
-  launch_assemble_h0(s->sd, L0, P<double>(s->f), pt.F, P<double>(s->Cp), P<int>(s->start),
-                     P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), st);
-  for (int m = 0; m + 1 < s->levels; ++m) launch_rap(view(s, m), view(s, m + 1), st);
+  PROF(s, HOT_PROF_PHESS,
+       launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
+                               pt.mat, P<double>(s->vstar), dt, P<double>(s->Cp), st));
+  PROF(s, HOT_PROF_ASSEMBLE,
+       launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, P<double>(s->f), pt.F,
+                          P<double>(s->Cp), P<int>(s->start), P<int>(s->counts),
+                          P<double>(s->mass), P<int>(s->fixed), st));
+  for (int m = 0; m + 1 < s->levels; ++m) {
+    if (m == 0)
+      PROF(s, HOT_PROF_RAP0, launch_rap(view(s, m), view(s, m + 1), st));
+    else
+      launch_rap(view(s, m), view(s, m + 1), st);
+  }
+  if (s->prof)
+    for (int m = 0; m < s->levels; ++m)
+      launch_pattern_count(view(s, m), P<double>(s->dscal) + S_NNZ + m, st);
   if (s->mixed)
     for (int m = 0; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
   size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
@@ -425,11 +506,17 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
     LevelView Lm = view(s, m);
     launch_jacobi_first(Lm, mx, bs[m], us[m], st);
     for (int k = 1; k < sweeps; ++k) {
-      launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
+      if (m == 0)
+        PROF(s, HOT_PROF_SMOOTH0, launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st));
+      else
+        launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
       std::swap(s->L[m].u, s->L[m].t);
       us[m] = s->L[m].u.p;
     }
-    launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st);
+    if (m == 0)
+      PROF(s, HOT_PROF_RESIDUAL0, launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st));
+    else
+      launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st);
     launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], st);
   }
   int slot = std::min(s->vcycles, s->prm.max_iters * 3 + 15);
@@ -440,7 +527,10 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
     LevelView Lm = view(s, m);
     launch_prolong_add(Lm, view(s, m + 1), mx, us[m + 1], us[m], st);
     for (int k = 0; k < sweeps; ++k) {
-      launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
+      if (m == 0)
+        PROF(s, HOT_PROF_SMOOTH0, launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st));
+      else
+        launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st);
       std::swap(s->L[m].u, s->L[m].t);
       us[m] = s->L[m].u.p;
     }
@@ -454,17 +544,54 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
 }
 
 // ---------------------------------------------------------------- solve
-void eval_trial(hot_scene* s, const double* dv, const double* p, double alpha, int out) {
+hot_status eval_trial(hot_scene* s, const double* dv, const double* p, double alpha, int out) {
   Particles& pt = s->P[s->cur];
-  launch_particle_eval(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
-                       pt.mat, P<double>(s->vstar), dv, p, alpha, s->dt_prepared,
-                       P<double>(s->psi[out]), P<double>(s->S[out]), s->stream);
+  PROF(s, HOT_PROF_EVAL,
+       launch_particle_eval(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.F,
+                            pt.vol, pt.mat, P<double>(s->vstar), dv, p, alpha, s->dt_prepared,
+                            P<double>(s->psi[out]), P<double>(s->S[out]), s->stream));
+  return HOT_OK;
 }
 
-void gradient(hot_scene* s, const double* dv, int sbuf, double* g) {
-  launch_gradient(s->sd, view(s, 0), P<double>(s->f), P<double>(s->S[sbuf]), P<int>(s->start),
-                  P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), dv, s->dt_prepared, g,
-                  s->stream);
+hot_status gradient(hot_scene* s, const double* dv, int sbuf, double* g) {
+  PROF(s, HOT_PROF_GRAD,
+       launch_gradient(s->sd, view(s, 0), s->bricks, P<double>(s->f), P<double>(s->S[sbuf]),
+                       P<int>(s->start), P<int>(s->counts), P<double>(s->bpartial),
+                       P<double>(s->mass), P<int>(s->fixed), dv, s->dt_prepared, g, s->stream));
+  return HOT_OK;
+}
+
+// Algorithmic bytes one launch of a traced kernel must move (structural
+// blocks and node/particle vectors read or written once).
+double prof_launch_bytes(hot_scene* s, int kind) {
+  double n0 = s->L[0].n, np = s->n;
+  double nnz0 = s->hscal[S_NNZ], nnz1 = s->levels > 1 ? s->hscal[S_NNZ + 1] : 0.0;
+  double n1 = s->levels > 1 ? s->L[1].n : 0.0;
+  bool mx = s->mixed;
+  switch (kind) {
+    case HOT_PROF_SMOOTH0: return mx ? 18.0 * nnz0 + 79.0 * n0 : 72.0 * nnz0 + 151.0 * n0;
+    case HOT_PROF_RESIDUAL0: return mx ? 18.0 * nnz0 + 40.0 * n0 : 72.0 * nnz0 + 76.0 * n0;
+    case HOT_PROF_ASSEMBLE: return 72.0 * nnz0 + 456.0 * np + 111.0 * n0;
+    case HOT_PROF_RAP0: return 72.0 * nnz0 + 23.0 * n0 + 72.0 * nnz1 + 111.0 * n1;
+    case HOT_PROF_EVAL: return 192.0 * np + 72.0 * n0;
+    case HOT_PROF_GRAD: return 96.0 * np + 64.0 * n0;
+    case HOT_PROF_PHESS: return 472.0 * np + 24.0 * n0;
+  }
+  return 0.0;
+}
+
+hot_status prof_flush(hot_scene* s) {
+  if (!s->prof) return HOT_OK;
+  for (size_t k = 0; k + 1 < s->prof_used; k += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[k], s->prof_ev[k + 1]));
+    int kind = s->prof_kind[k / 2];
+    s->prof_ms[kind] += ms;
+    s->prof_n[kind] += 1;
+    s->prof_bytes[kind] += prof_launch_bytes(s, kind);
+  }
+  s->prof_used = 0;
+  return HOT_OK;
 }
 
 // HOT quasi-Newton solve (Alg. HOT): L-BFGS two-loop with the V-cycle as the
@@ -492,9 +619,9 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
   s->log_cn.clear();
   launch_fill_double(N, dv, 0.0, st);
   s->pc = 0;
-  eval_trial(s, dv, nullptr, 0.0, s->pc);
+  TRY(eval_trial(s, dv, nullptr, 0.0, s->pc));
   launch_sum(s->n, P<double>(s->psi[s->pc]), partial, dscal + S_E0, st);
-  gradient(s, dv, s->pc, g);
+  TRY(gradient(s, dv, s->pc, g));
   launch_cn_sq(n0, g, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
   TRY(readback(s));
   double E = s->hscal[S_E0];
@@ -533,7 +660,7 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     // -- descent check and the first trial in one readback
     int trial = 1 - s->pc;
     launch_dot(N, g, r, partial, dscal + S_GP, st);
-    eval_trial(s, dv, r, 1.0, trial);
+    TRY(eval_trial(s, dv, r, 1.0, trial));
     launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
     launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
     TRY(readback(s));
@@ -554,7 +681,7 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
         TRY(readback(s));
         gp = s->hscal[S_GP];
       }
-      eval_trial(s, dv, r, 1.0, trial);
+      TRY(eval_trial(s, dv, r, 1.0, trial));
       launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
       launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
       TRY(readback(s));
@@ -566,7 +693,7 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     double dE = 0.0;
     for (halvings = 0; halvings <= 30; ++halvings) {
       if (halvings > 0) {
-        eval_trial(s, dv, r, alpha, trial);
+        TRY(eval_trial(s, dv, r, alpha, trial));
         launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial,
                         dscal + S_DEP, st);
         launch_kinetic_delta(n0, P<double>(s->mass), dv, r, alpha, partial, dscal + S_DEK, st);
@@ -599,7 +726,7 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     dv = P<double>(s->dv);
     dvt = P<double>(s->dvt);
     s->pc = trial;
-    gradient(s, dv, s->pc, gnew);
+    TRY(gradient(s, dv, s->pc, gnew));
     launch_sub(N, gnew, g, P<double>(s->Yh[slot]), st);
     launch_dots3(N, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), partial, dscal + S_YS, st);
     launch_cn_sq(n0, gnew, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
@@ -682,6 +809,7 @@ hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
   HIPCHK(hipEventRecord(s->ev[4], st));
   HIPCHK(hipEventSynchronize(s->ev[4]));
   HIPCHK(hipGetLastError());
+  TRY(prof_flush(s));
   s->t += dt;
   s->prepared = false;
   if (stats) {
@@ -705,7 +833,8 @@ void destroy(hot_scene* s) {
                  &s->cursor, &s->flags, &s->scan, &s->scan_temp, &s->err, &s->mass,
                  &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
                  &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
-                 &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables};
+                 &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
+                 &s->bmap, &s->blist, &s->bpartial};
   for (DBuf* b : all) release(s, *b);
   for (auto& b : s->Sh) release(s, b);
   for (auto& b : s->Yh) release(s, b);
@@ -719,6 +848,7 @@ void destroy(hot_scene* s) {
   if (s->herr) (void)hipHostFree(s->herr);
   for (int k = 0; k < 5; ++k)
     if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -894,6 +1024,12 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     return bail(rc);
   for (int m = 0; m < s->levels; ++m)
     if ((rc = ensure(s, s->L[m].map, s->L[m].g.ptotal * 4)) < 0) return bail(rc);
+  {
+    BrickGeom& bg = s->bricks.bg;
+    for (int a = 0; a < 3; ++a) bg.bd[a] = (sd.g0.pd[a] + kBrick - 1) / kBrick;
+    bg.total = (long long)bg.bd[0] * bg.bd[1] * bg.bd[2];
+    if ((rc = ensure(s, s->bmap, bg.total * 4)) < 0) return bail(rc);
+  }
   int W = params->lbfgs_history + 1;
   if ((rc = ensure(s, s->ddot, W * 8)) < 0 || (rc = ensure(s, s->dalpha, W * 8)) < 0 ||
       (rc = ensure(s, s->dcoef, W * 8)) < 0 || (rc = ensure(s, s->drho, W * 8)) < 0 ||
@@ -965,6 +1101,29 @@ hot_status hot_scene_info(const hot_scene* scene, int64_t* n, double* t) {
 
 void hot_destroy_scene(hot_scene* scene) { destroy(scene); }
 
+// ---------------------------------------------------------------- tracing
+hot_status hot_profile_enable(hot_scene* scene, int32_t enable) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  scene->prof = enable != 0;
+  scene->prof_used = 0;
+  for (int k = 0; k < HOT_PROF_COUNT; ++k) {
+    scene->prof_ms[k] = 0.0;
+    scene->prof_n[k] = 0;
+    scene->prof_bytes[k] = 0.0;
+  }
+  return HOT_OK;
+}
+
+hot_status hot_profile_read(const hot_scene* scene, int32_t kernel, double* total_ms,
+                            int64_t* launches, double* total_bytes) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (kernel < 0 || kernel >= HOT_PROF_COUNT) return fail(HOT_E_INVALID, "bad kernel id");
+  if (total_ms) *total_ms = scene->prof_ms[kernel];
+  if (launches) *launches = scene->prof_n[kernel];
+  if (total_bytes) *total_bytes = scene->prof_bytes[kernel];
+  return HOT_OK;
+}
+
 // ---------------------------------------------------------------- debug
 hot_status hot_debug_prepare(hot_scene* scene, double dt) {
   if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
@@ -987,10 +1146,10 @@ hot_status hot_debug_apply(hot_scene* scene, int32_t op, const double* in, doubl
   if (op == 0) {
     TRY(vcycle(s, vin, vout));
   } else if (op == 1) {
-    eval_trial(s, vin, nullptr, 0.0, 0);
-    gradient(s, vin, 0, vout);
+    TRY(eval_trial(s, vin, nullptr, 0.0, 0));
+    TRY(gradient(s, vin, 0, vout));
   } else if (op == 2) {
-    eval_trial(s, vin, nullptr, 0.0, 0);
+    TRY(eval_trial(s, vin, nullptr, 0.0, 0));
     launch_sum(s->n, P<double>(s->psi[0]), P<double>(s->partial), P<double>(s->dscal) + S_E0, st);
     launch_kinetic_delta(s->L[0].n, P<double>(s->mass), vin, vin, -1.0, P<double>(s->partial),
                          P<double>(s->dscal) + S_DEK, st);

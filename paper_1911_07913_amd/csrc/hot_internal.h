@@ -48,6 +48,24 @@ struct GridGeom {
   long long ptotal;
 };
 
+// Cell bricks of kBrick^3 cells over the padded cell grid (for the two-pass
+// particle-to-node reductions) and row segments of kSegRows nodes along x
+// (for the level-0 Hessian assembly).
+constexpr int kBrick = 4;
+constexpr int kBrickNodes = kBrick + 2;  // node window per axis
+constexpr int kBrickWin = kBrickNodes * kBrickNodes * kBrickNodes;  // 216
+constexpr int kSegRows = 16;
+struct BrickGeom {
+  int bd[3];  // bricks per axis
+  long long total;
+};
+struct Bricks {
+  BrickGeom bg;
+  int n;             // non-empty bricks
+  const int* list;   // [n] dense brick index
+  const int* map;    // [total] brick id or -1
+};
+
 // Everything the particle/grid kernels of level 0 need (passed by value).
 struct SceneDev {
   double dx, inv_dx;
@@ -121,14 +139,21 @@ size_t scan_temp_bytes(long long n);
 void launch_scan(long long n, const int* in, int* out, void* temp, hipStream_t st);
 void launch_fill_int(long long n, int* p, int v, hipStream_t st);
 void launch_fine_pattern(const LevelView& L, const int* counts, hipStream_t st);
+void launch_pattern_count(const LevelView& L, double* out, hipStream_t st);
+void launch_seg_flags(const LevelView& L, int* flags, hipStream_t st);
+void launch_seg_compact(int n, const int* flags, const int* scan, int* seg_begin, hipStream_t st);
+void launch_mark_bricks(const GridGeom& g, const BrickGeom& bg, const int* counts, int* bflags,
+                        hipStream_t st);
+void launch_brick_compact(long long total, const int* flags, const int* scan, int* bmap, int* blist,
+                          hipStream_t st);
 
 // particles.hip
 void launch_particle_frac(const SceneDev& s, int n, const double* x, double* f, int* key,
                           hipStream_t st);
-void launch_p2g(const SceneDev& s, const LevelView& L0, const double* f, const double* v,
-                const double* C, const double* vol, const int* mat, const int* cstart,
-                const int* ccount, double dt, double t_end, double* mass, double* vstar,
-                double* xi, int* fixed, hipStream_t st);
+void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
+                const double* v, const double* C, const double* vol, const int* mat,
+                const int* cstart, const int* ccount, double* partial, double dt, double t_end,
+                double* mass, double* vstar, double* xi, int* fixed, hipStream_t st);
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
                              const double* vstar, double dt, double* Cp, hipStream_t st);
@@ -137,15 +162,16 @@ void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const d
                           const int* key, const double* F, const double* vol, const int* mat,
                           const double* vstar, const double* dv, const double* p, double alpha,
                           double dt, double* psi_out, double* S_out, hipStream_t st);
-void launch_gradient(const SceneDev& s, const LevelView& L0, const double* f, const double* S,
-                     const int* cstart, const int* ccount, const double* mass, const int* fixed,
-                     const double* dv, double dt, double* g, hipStream_t st);
+void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
+                     const double* S, const int* cstart, const int* ccount, double* partial,
+                     const double* mass, const int* fixed, const double* dv, double dt, double* g,
+                     hipStream_t st);
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
                 const double* dv, double dt, hipStream_t st);
-void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const double* f, const double* F,
-                        const double* Cp, const int* cstart, const int* ccount,
-                        const double* mass, const int* fixed, hipStream_t st);
+void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
+                        const double* f, const double* F, const double* Cp, const int* cstart,
+                        const int* ccount, const double* mass, const int* fixed, hipStream_t st);
 
 // matrix.hip
 void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);

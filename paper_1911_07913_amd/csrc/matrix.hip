@@ -55,32 +55,44 @@ struct MatOf<float> {
 };
 
 // y = H_i . x for one row, computed by a whole wave; result valid in all lanes.
+// Lane l handles values e = l + 64k of the row (slot e/9, entry e%9).  All
+// matrix values and neighbour indices of the row are loaded first, then the
+// x entries, so each row costs two dependent memory round trips; slots the
+// symbolic pattern marks absent are not read at all.
+constexpr int kRowIt = (kRowVals + 63) / 64;  // 18
+
+__device__ inline uint32_t pick_word(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int k) {
+  return k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
+}
+
 template <typename V>
 __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict__ x, int lane,
                                   V* y) {
   typedef typename MatOf<V>::type M;
   const M* Hrow = MatOf<V>::H(L) + (long long)i * kRowVals;
-  long long pn = L.nodes[i];
+  const long long pn = L.nodes[i];
+  const uint32_t w0 = L.pat[4 * i], w1 = L.pat[4 * i + 1], w2 = L.pat[4 * i + 2],
+                 w3 = L.pat[4 * i + 3];
+  V h[kRowIt];
+  int jn[kRowIt];
+#pragma unroll
+  for (int k = 0; k < kRowIt; ++k) {
+    const int e = lane + 64 * k;
+    const int s = e / 9;
+    const bool present = (e < kRowVals) && ((pick_word(w0, w1, w2, w3, s >> 5) >> (s & 31)) & 1u);
+    h[k] = present ? ldm<V, M>(Hrow + e) : (V)0;
+    jn[k] = present ? L.map[pn + slot_offset(L.g, s)] : -1;
+  }
   V a0 = 0, a1 = 0, a2 = 0;
-  int s = lane / 9, c = lane % 9;
-  for (int e = lane; e < kRowVals; e += 64) {
-    V h = ldm<V, M>(Hrow + e);
-    if (h != (V)0) {
-      int j = L.map[pn + slot_offset(L.g, s)];
-      if (j >= 0) {
-        int g = c / 3, d = c - 3 * g;
-        V pr = h * x[3 * j + d];
-        a0 += (g == 0) ? pr : (V)0;
-        a1 += (g == 1) ? pr : (V)0;
-        a2 += (g == 2) ? pr : (V)0;
-      }
-    }
-    c += 1;
-    s += 7;
-    if (c == 9) {
-      c = 0;
-      s += 1;
-    }
+#pragma unroll
+  for (int k = 0; k < kRowIt; ++k) {
+    const int e = lane + 64 * k;
+    const int c = e % 9;
+    const int g = c / 3, d = c - 3 * g;
+    V pr = (jn[k] >= 0) ? h[k] * x[3 * jn[k] + d] : (V)0;
+    a0 += (g == 0) ? pr : (V)0;
+    a1 += (g == 1) ? pr : (V)0;
+    a2 += (g == 2) ? pr : (V)0;
   }
   y[0] = wave_sum_t(a0);
   y[1] = wave_sum_t(a1);

@@ -1,9 +1,9 @@
 // Particle-grid kernels of the implicit MPM step (Sec. 3.1) and the level-0
 // system matrix (Sec. 4.1, Alg. HOT initialisation).
 //
-// All transfers are written as gathers over the binned particle order, so no
-// floating-point atomics are used: a node sums the particles of the 27 base
-// cells whose stencil covers it, in a fixed order.
+// Particle-to-node sums are computed without global floating-point atomics
+// and in a fixed order (see the brick and row-segment kernels below), so the
+// results are reproducible run to run.
 #include "mpm_math.h"
 
 namespace hot {
@@ -77,49 +77,132 @@ __device__ inline bool apply_bcs(const SceneDev& s, int x, int y, int z, double 
   return fixed;
 }
 
+// ---- two-pass particle-to-node sums over cell bricks
+// Pass 1: one wave per brick of 4^3 cells; lane l owns one cell and walks its
+// particles, adding each particle's contribution to the 27 stencil nodes of
+// its cell into the brick's 6^3-node window in LDS.  For a fixed stencil
+// offset the 64 cells hit 64 distinct nodes, so no two lanes of one LDS add
+// collide; the adds are LDS atomics so the one wave's instructions apply in
+// program order and the sums are reproducible.  The window is written to a
+// per-brick partial.
+// Pass 2: every node sums the partials of the (at most 8) bricks whose window
+// holds it, in a fixed order.  No floating-point atomics; deterministic.
+// Lane `lane` of brick b owns cell (lx, ly, lz) of the brick; returns its
+// particle range [st, st + cnt) in the binned order.
+__device__ inline void brick_cell(const SceneDev& s, const Bricks& B, int b, int lane,
+                                  const int* __restrict__ cstart, const int* __restrict__ ccount,
+                                  int& cnt, int& st, int& lx, int& ly, int& lz) {
+  int bid = B.list[b];
+  int bx = bid % B.bg.bd[0], by = (bid / B.bg.bd[0]) % B.bg.bd[1], bz = bid / (B.bg.bd[0] * B.bg.bd[1]);
+  lx = lane % kBrick;
+  ly = (lane / kBrick) % kBrick;
+  lz = lane / (kBrick * kBrick);
+  int cx = bx * kBrick + lx, cy = by * kBrick + ly, cz = bz * kBrick + lz;  // padded cell coords
+  cnt = 0;
+  st = 0;
+  if (cx < s.g0.pd[0] && cy < s.g0.pd[1] && cz < s.g0.pd[2]) {
+    long long c = (long long)cx + (long long)s.g0.pd[0] * ((long long)cy + (long long)s.g0.pd[1] * cz);
+    cnt = ccount[c];
+    st = cstart[c];
+  }
+}
+
+// Sum over the bricks whose node window holds padded node (px, py, pz).
+template <int V>
+__device__ inline void brick_gather(const Bricks& B, const double* __restrict__ partial, int px,
+                                    int py, int pz, double* out) {
+  for (int v = 0; v < V; ++v) out[v] = 0.0;
+  int lo[3], hi[3], pp[3] = {px, py, pz};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = pp[a] >= kBrickNodes - 1 ? (pp[a] - (kBrickNodes - 1) + kBrick - 1) / kBrick : 0;
+    hi[a] = min(pp[a] / kBrick, B.bg.bd[a] - 1);
+  }
+  for (int bz = lo[2]; bz <= hi[2]; ++bz)
+    for (int by = lo[1]; by <= hi[1]; ++by)
+      for (int bx = lo[0]; bx <= hi[0]; ++bx) {
+        int id = B.map[bx + (long long)B.bg.bd[0] * (by + (long long)B.bg.bd[1] * bz)];
+        if (id < 0) continue;
+        int loc = (px - bx * kBrick) + kBrickNodes * ((py - by * kBrick) + kBrickNodes * (pz - bz * kBrick));
+        const double* q = partial + ((long long)id * kBrickWin + loc) * V;
+        for (int v = 0; v < V; ++v) out[v] += q[v];
+      }
+}
+
 // APIC particle-to-grid (Sec. 3.1) plus the mass-weighted CN stiffness field
-// (Sec. 5.2), gravity and boundary velocities.  One thread per active node.
-__global__ void k_p2g(SceneDev s, LevelView L, const double* __restrict__ f,
-                      const double* __restrict__ v, const double* __restrict__ C,
-                      const double* __restrict__ vol, const int* __restrict__ mat,
-                      const int* __restrict__ cstart, const int* __restrict__ ccount, double dt,
-                      double t_end, double* __restrict__ mass, double* __restrict__ vstar,
-                      double* __restrict__ xi, int* __restrict__ fixed) {
+// (Sec. 5.2), pass 1: per brick, m w, m w (v_p + C_p (x_i - x_p)), m w xi_p.
+__global__ __launch_bounds__(64) void k_p2g_brick(SceneDev s, Bricks B, const double* __restrict__ f,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ C,
+                                                  const double* __restrict__ vol,
+                                                  const int* __restrict__ mat,
+                                                  const int* __restrict__ cstart,
+                                                  const int* __restrict__ ccount,
+                                                  double* __restrict__ partial) {
+  __shared__ double win[kBrickWin * 5];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  for (int e = lane; e < kBrickWin * 5; e += 64) win[e] = 0.0;
+  int cnt, st, lx, ly, lz;
+  brick_cell(s, B, b, lane, cstart, ccount, cnt, st, lx, ly, lz);
+  wave_sync();
+  for (int t = 0;; ++t) {
+    bool act = t < cnt;
+    if (!__any(act)) break;
+    if (act) {
+      int p = st + t;
+      double f0 = f[3 * p], f1 = f[3 * p + 1], f2 = f[3 * p + 2];
+      double wx[3], wy[3], wz[3];
+      for (int k = 0; k < 3; ++k) {
+        wx[k] = bsw(k, f0);
+        wy[k] = bsw(k, f1);
+        wz[k] = bsw(k, f2);
+      }
+      const MaterialDev& md = s.mats[mat[p]];
+      double mp = md.density * vol[p], xip = md.xi;
+      double vp0 = v[3 * p], vp1 = v[3 * p + 1], vp2 = v[3 * p + 2];
+      const double* Cp = C + 9 * (long long)p;
+      double c0 = Cp[0], c1 = Cp[1], c2 = Cp[2], c3 = Cp[3], c4 = Cp[4], c5 = Cp[5], c6 = Cp[6],
+             c7 = Cp[7], c8 = Cp[8];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) {
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        double w = wx[kx] * wy[ky] * wz[kz];
+        double d0 = (kx - f0) * s.dx, d1 = (ky - f1) * s.dx, d2 = (kz - f2) * s.dx;
+        double va0 = vp0 + (c0 * d0 + c1 * d1 + c2 * d2);
+        double va1 = vp1 + (c3 * d0 + c4 * d1 + c5 * d2);
+        double va2 = vp2 + (c6 * d0 + c7 * d1 + c8 * d2);
+        double wm = w * mp;
+        double* q = win + 5 * ((lx + kx) + kBrickNodes * ((ly + ky) + kBrickNodes * (lz + kz)));
+        atomicAdd(q, wm);
+        atomicAdd(q + 1, wm * va0);
+        atomicAdd(q + 2, wm * va1);
+        atomicAdd(q + 3, wm * va2);
+        atomicAdd(q + 4, wm * xip);
+      }
+    }
+  }
+  wave_sync();
+  double* out = partial + (long long)b * kBrickWin * 5;
+  for (int e = lane; e < kBrickWin * 5; e += 64) out[e] = win[e];
+}
+
+// P2G pass 2: velocities, CN field, gravity and boundary velocities.
+__global__ void k_p2g_nodes(SceneDev s, LevelView L, Bricks B, const double* __restrict__ partial,
+                            double dt, double t_end, double* __restrict__ mass,
+                            double* __restrict__ vstar, double* __restrict__ xi,
+                            int* __restrict__ fixed) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   int x, y, z;
   unpidx(L.g, L.nodes[i], x, y, z);
-  double m = 0.0, mv0 = 0.0, mv1 = 0.0, mv2 = 0.0, mxi = 0.0;
-  for (int k = 0; k < 27; ++k) {
-    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    long long cell = pidx(L.g, x - kx, y - ky, z - kz);
-    int cnt = ccount[cell];
-    if (cnt == 0) continue;
-    int st = cstart[cell];
-    for (int p = st; p < st + cnt; ++p) {
-      double f0 = f[3 * p], f1 = f[3 * p + 1], f2 = f[3 * p + 2];
-      double w = bsw(kx, f0) * bsw(ky, f1) * bsw(kz, f2);
-      const MaterialDev& md = s.mats[mat[p]];
-      double mp = md.density * vol[p];
-      double d0 = (kx - f0) * s.dx, d1 = (ky - f1) * s.dx, d2 = (kz - f2) * s.dx;
-      const double* Cp = C + 9 * p;
-      double va0 = v[3 * p] + (Cp[0] * d0 + Cp[1] * d1 + Cp[2] * d2);
-      double va1 = v[3 * p + 1] + (Cp[3] * d0 + Cp[4] * d1 + Cp[5] * d2);
-      double va2 = v[3 * p + 2] + (Cp[6] * d0 + Cp[7] * d1 + Cp[8] * d2);
-      double wm = w * mp;
-      m += wm;
-      mv0 += wm * va0;
-      mv1 += wm * va1;
-      mv2 += wm * va2;
-      mxi += wm * md.xi;
-    }
-  }
+  double q[5];
+  brick_gather<5>(B, partial, x + 2, y + 2, z + 2, q);
+  double m = q[0];
   double vs[3];
   if (m > 0.0) {
-    vs[0] = mv0 / m + dt * s.gravity[0];
-    vs[1] = mv1 / m + dt * s.gravity[1];
-    vs[2] = mv2 / m + dt * s.gravity[2];
-    xi[i] = mxi / m;
+    vs[0] = q[1] / m + dt * s.gravity[0];
+    vs[1] = q[2] / m + dt * s.gravity[1];
+    vs[2] = q[3] / m + dt * s.gravity[2];
+    xi[i] = q[4] / m;
   } else {
     vs[0] = vs[1] = vs[2] = 0.0;
     xi[i] = 0.0;
@@ -211,13 +294,59 @@ __global__ void k_particle_eval(SceneDev s, LevelView L, int n, const double* __
   }
 }
 
-// g_i = m_i dv_i + dt sum_p S_p grad w_ip, zero on constrained nodes
-// (Sec. 4.1 nodal forces; gradient of Eq. 1).  One thread per node.
-__global__ void k_gradient(SceneDev s, LevelView L, const double* __restrict__ f,
-                           const double* __restrict__ S, const int* __restrict__ cstart,
-                           const int* __restrict__ ccount, const double* __restrict__ mass,
-                           const int* __restrict__ fixed, const double* __restrict__ dv, double dt,
-                           double* __restrict__ g) {
+// Gradient pass 1 (Sec. 4.1 nodal forces): per brick, sum_p S_p grad w_ip
+// with S_p = V_p P(F_p) F_p^n^T.
+__global__ __launch_bounds__(64) void k_grad_brick(SceneDev s, Bricks B, const double* __restrict__ f,
+                                                   const double* __restrict__ S,
+                                                   const int* __restrict__ cstart,
+                                                   const int* __restrict__ ccount,
+                                                   double* __restrict__ partial) {
+  __shared__ double win[kBrickWin * 3];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  for (int e = lane; e < kBrickWin * 3; e += 64) win[e] = 0.0;
+  int cnt, st, lx, ly, lz;
+  brick_cell(s, B, b, lane, cstart, ccount, cnt, st, lx, ly, lz);
+  wave_sync();
+  for (int t = 0;; ++t) {
+    bool act = t < cnt;
+    if (!__any(act)) break;
+    if (act) {
+      long long p = st + t;
+      double f0 = f[3 * p], f1 = f[3 * p + 1], f2 = f[3 * p + 2];
+      double wx[3], wy[3], wz[3], dx[3], dy[3], dz[3];
+      for (int k = 0; k < 3; ++k) {
+        wx[k] = bsw(k, f0);
+        wy[k] = bsw(k, f1);
+        wz[k] = bsw(k, f2);
+        dx[k] = bsdw(k, f0, s.inv_dx);
+        dy[k] = bsdw(k, f1, s.inv_dx);
+        dz[k] = bsdw(k, f2, s.inv_dx);
+      }
+      const double* Sp = S + 9 * p;
+      double s0 = Sp[0], s1 = Sp[1], s2 = Sp[2], s3 = Sp[3], s4 = Sp[4], s5 = Sp[5], s6 = Sp[6],
+             s7 = Sp[7], s8 = Sp[8];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) {
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        double gx = dx[kx] * wy[ky] * wz[kz];
+        double gy = wx[kx] * dy[ky] * wz[kz];
+        double gz = wx[kx] * wy[ky] * dz[kz];
+        double* q = win + 3 * ((lx + kx) + kBrickNodes * ((ly + ky) + kBrickNodes * (lz + kz)));
+        atomicAdd(q, s0 * gx + s1 * gy + s2 * gz);
+        atomicAdd(q + 1, s3 * gx + s4 * gy + s5 * gz);
+        atomicAdd(q + 2, s6 * gx + s7 * gy + s8 * gz);
+      }
+    }
+  }
+  wave_sync();
+  double* out = partial + (long long)b * kBrickWin * 3;
+  for (int e = lane; e < kBrickWin * 3; e += 64) out[e] = win[e];
+}
+
+// Gradient pass 2: g_i = m_i dv_i + dt sum, zero on constrained nodes.
+__global__ void k_grad_nodes(LevelView L, Bricks B, const double* __restrict__ partial,
+                             const double* __restrict__ mass, const int* __restrict__ fixed,
+                             const double* __restrict__ dv, double dt, double* __restrict__ g) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   if (fixed[i]) {
@@ -226,29 +355,12 @@ __global__ void k_gradient(SceneDev s, LevelView L, const double* __restrict__ f
   }
   int x, y, z;
   unpidx(L.g, L.nodes[i], x, y, z);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = 0; k < 27; ++k) {
-    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    long long cell = pidx(L.g, x - kx, y - ky, z - kz);
-    int cnt = ccount[cell];
-    if (cnt == 0) continue;
-    int st = cstart[cell];
-    for (int p = st; p < st + cnt; ++p) {
-      double f0 = f[3 * p], f1 = f[3 * p + 1], f2 = f[3 * p + 2];
-      double wx = bsw(kx, f0), wy = bsw(ky, f1), wz = bsw(kz, f2);
-      double gx = bsdw(kx, f0, s.inv_dx) * wy * wz;
-      double gy = wx * bsdw(ky, f1, s.inv_dx) * wz;
-      double gz = wx * wy * bsdw(kz, f2, s.inv_dx);
-      const double* Sp = S + 9 * (long long)p;
-      a0 += Sp[0] * gx + Sp[1] * gy + Sp[2] * gz;
-      a1 += Sp[3] * gx + Sp[4] * gy + Sp[5] * gz;
-      a2 += Sp[6] * gx + Sp[7] * gy + Sp[8] * gz;
-    }
-  }
+  double q[3];
+  brick_gather<3>(B, partial, x + 2, y + 2, z + 2, q);
   double m = mass[i];
-  g[3 * i] = m * dv[3 * i] + dt * a0;
-  g[3 * i + 1] = m * dv[3 * i + 1] + dt * a1;
-  g[3 * i + 2] = m * dv[3 * i + 2] + dt * a2;
+  g[3 * i] = m * dv[3 * i] + dt * q[0];
+  g[3 * i + 1] = m * dv[3 * i + 1] + dt * q[1];
+  g[3 * i + 2] = m * dv[3 * i + 2] + dt * q[2];
 }
 
 // Von Mises return mapping on the Hencky strain (lagged plasticity).
@@ -326,87 +438,188 @@ __global__ void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__
   }
 }
 
-// Level-0 Hessian rows, one wave per row i (Sec. 4.1 / Alg. HOT):
+// Level-0 Hessian (Sec. 4.1 / Alg. HOT initialisation):
 //   H_ij = m_i delta_ij I + sum_p a_ip^T C_p a_jp,  a_ip = F_p^n^T grad w_ip,
 // with C_p the particle's projected stress derivative already scaled by
-// dt^2 V_p.  The particles touching row i are those of the 27 base cells
-// b = i - k, k in {0,1,2}^3; all particles of one cell share the stencil
-// b + {0,1,2}^3, so lane l (0..26) accumulates block (i, b + l) in registers
-// while the two half-waves take alternate particles, and the per-cell sums
-// are added into the row held in LDS.  The row is then finalised (mass,
-// Dirichlet projection, smoother inverse) and written once.
-constexpr int kAsmWaves = 4;
+// dt^2 V_p (45 upper-triangle entries).
+//
+// One work-group per row segment: up to 16 consecutive rows (x, y, z) of one
+// x-line.  The group sweeps the base cells c = x_first - 2 .. x_last of the 9
+// cell columns (c, y - ky, z - kz), ky, kz in {0,1,2}; a particle of column
+// (ky, kz) in cell c touches rows c + r, r in {0,1,2}, of this segment, with
+// stencil offset k = (r, ky, kz).  Thread (r, l, g) owns block row g of block
+// (row c + r, stencil node l) and accumulates it in registers over the cell's
+// particles; per cell the sums go to a 3-row sliding window in LDS.  After
+// cell c, row c receives nothing more: it is finalised (mass, Dirichlet
+// projection, smoother inverse) and written once.  Every block of every
+// particle is computed exactly once; no atomics.
+constexpr int kAsmChunk = 8;   // particles staged per pass
+constexpr int kPData = 57;     // f (3), F (9), C (45)
 
-__global__ __launch_bounds__(256) void k_assemble_h0(SceneDev s, LevelView L,
-                                                      const double* __restrict__ f,
-                                                      const double* __restrict__ Fn,
-                                                      const double* __restrict__ Cp,
-                                                      const int* __restrict__ cstart,
-                                                      const int* __restrict__ ccount,
-                                                      const double* __restrict__ mass,
-                                                      const int* __restrict__ fixed) {
-  __shared__ double acc_all[kAsmWaves][kRowVals];
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = blockIdx.x * kAsmWaves + wave;
-  if (i >= L.n) return;
-  double* acc = acc_all[wave];
-  for (int e = lane; e < kRowVals; e += 64) acc[e] = 0.0;
-  wave_sync();
-  int x, y, z;
-  unpidx(L.g, L.nodes[i], x, y, z);
-  const int half = lane >> 5, l = lane & 31;
-  const bool lane_ok = l < 27;
-  const int lx = l % 3, ly = (l / 3) % 3, lz = l / 9;
-  // Z entry owned by this lane: e = 9*gamma + (3*delta + eps)
-  const int zg = l / 9, zde = l % 9;
-  for (int k = 0; k < 27; ++k) {
-    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    long long cell = pidx(L.g, x - kx, y - ky, z - kz);
-    int cnt = ccount[cell];
-    if (cnt == 0) continue;
-    int st = cstart[cell];
-    double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = 0; t < cnt; t += 2) {
-      int pi = t + half;
-      bool valid = pi < cnt;
-      long long p = st + (valid ? pi : 0);
-      double fp[3] = {f[3 * p], f[3 * p + 1], f[3 * p + 2]};
-      Weights W;
-      bspline_weights(fp, s.inv_dx, W);
-      double gi[3], gl[3];
-      node_grad(W, kx, ky, kz, gi);
-      node_grad(W, lx < 3 ? lx : 0, ly, lz < 3 ? lz : 0, gl);
-      const double* F = Fn + 9 * p;
-      double ai[3], al[3];
-      for (int b = 0; b < 3; ++b) {
-        ai[b] = F[b] * gi[0] + F[3 + b] * gi[1] + F[6 + b] * gi[2];
-        al[b] = (valid && lane_ok) ? (F[b] * gl[0] + F[3 + b] * gl[1] + F[6 + b] * gl[2]) : 0.0;
-      }
-      double zv = 0.0;
-      if (lane_ok) {
-        const double* Cq = Cp + 45 * p;
-        for (int b = 0; b < 3; ++b) zv += ai[b] * Cq[tri9(3 * zg + b, zde)];
-      }
-      const int src0 = half << 5;
-#pragma unroll
-      for (int g = 0; g < 3; ++g)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          double sacc = 0.0;
-#pragma unroll
-          for (int e = 0; e < 3; ++e) sacc += __shfl(zv, src0 + 9 * g + 3 * d + e, 64) * al[e];
-          blk[3 * g + d] += sacc;
-        }
+__device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
+  double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
+  double w0 = 0.5 * (a * a), w1 = 0.75 - b * b, w2 = 0.5 * (c * c);
+  double d0 = (f - 1.5) * inv_dx, d1 = -2.0 * b * inv_dx, d2 = c * inv_dx;
+  w = (k == 0) ? w0 : ((k == 1) ? w1 : w2);
+  dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
+}
+
+// Block-level version of finalize_row (256 threads).
+__device__ inline void finalize_row_block(double* acc, int i, const LevelView& L,
+                                          const int* __restrict__ fixed, double mass_i,
+                                          double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool row_fixed = fixed[i] != 0;
+  if (row_fixed) {
+    for (int e = tid; e < kRowVals; e += 256) acc[e] = 0.0;
+  } else {
+    long long pn = L.nodes[i];
+    for (int e = tid; e < kRowVals; e += 256) {
+      int s = e / 9;
+      if (s == kCenter) continue;
+      int j = L.map[pn + slot_offset(L.g, s)];
+      if (j >= 0 && fixed[j]) acc[e] = 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) blk[c] += __shfl_down(blk[c], 32, 64);
-    if (lane < 27) {
-      int sl = (lx - kx + 2) + 5 * (ly - ky + 2) + 25 * (lz - kz + 2);
-      for (int c = 0; c < 9; ++c) acc[sl * 9 + c] += blk[c];
-    }
-    wave_sync();
   }
-  finalize_row(acc, i, L, fixed, mass[i], lane);
+  __syncthreads();
+  if (tid == 0) {
+    for (int g = 0; g < 3; ++g) {
+      double d = acc[kCenter * 9 + 4 * g] + mass_i;
+      bool zero = (d == 0.0);
+      acc[kCenter * 9 + 4 * g] = zero ? 1.0 : d;
+      L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
+      L.diag[3 * i + g] = zero ? 1.0 : d;
+    }
+  }
+  __syncthreads();
+  double l1[3] = {0.0, 0.0, 0.0};
+  for (int e = tid; e < kRowVals; e += 256) {
+    double v = acc[e];
+    L.H[(long long)i * kRowVals + e] = v;
+    if (e / 9 != kCenter) {
+      int g = (e % 9) / 3;
+      double av = fabs(v);
+      l1[0] += (g == 0) ? av : 0.0;
+      l1[1] += (g == 1) ? av : 0.0;
+      l1[2] += (g == 2) ? av : 0.0;
+    }
+  }
+  for (int g = 0; g < 3; ++g) {
+    double t = wave_sum(l1[g]);
+    if (lane == 0) red[wave * 3 + g] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double Dt[9];
+    for (int k = 0; k < 9; ++k) Dt[k] = acc[kCenter * 9 + k];
+    for (int g = 0; g < 3; ++g) Dt[4 * g] += red[g] + red[3 + g] + red[6 + g] + red[9 + g];
+    double Di[9];
+    inv3(Dt, Di);
+    for (int k = 0; k < 9; ++k) L.Dinv[(long long)i * 9 + k] = Di[k];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
+                                                         const int* __restrict__ seg_begin,
+                                                         const double* __restrict__ f,
+                                                         const double* __restrict__ Fn,
+                                                         const double* __restrict__ Cp,
+                                                         const int* __restrict__ cstart,
+                                                         const int* __restrict__ ccount,
+                                                         const double* __restrict__ mass,
+                                                         const int* __restrict__ fixed) {
+  __shared__ double win[3][kRowVals];
+  __shared__ double pd[kAsmChunk][kPData];
+  __shared__ double av[kAsmChunk][27][3];
+  __shared__ double zv[kAsmChunk][3][27];
+  __shared__ double red[12];
+  const int tid = threadIdx.x;
+  const int rb = seg_begin[blockIdx.x], re = seg_begin[blockIdx.x + 1];
+  int xa, ys, zs, xb, yy, zz;
+  unpidx(L.g, L.nodes[rb], xa, ys, zs);
+  unpidx(L.g, L.nodes[re - 1], xb, yy, zz);
+  for (int e = tid; e < 3 * kRowVals; e += 256) (&win[0][0])[e] = 0.0;
+  // block-phase role of this thread: row offset r, stencil node l, block row g
+  const bool blk_thread = tid < 243;
+  const int br = tid / 81, bl = (tid / 3) % 27, bg = tid % 3;
+  const int blx = bl % 3, bly = (bl / 3) % 3, blz = bl / 9;
+  int next = rb;
+  __syncthreads();
+  for (int c = xa - 2; c <= xb; ++c) {
+    const int rlo = max(0, xa - c), rhi = min(2, xb - c);
+    for (int col = 0; col < 9; ++col) {
+      const int ky = col % 3, kz = col / 3;
+      const long long cell = pidx(L.g, c, ys - ky, zs - kz);
+      const int cnt = ccount[cell];
+      if (cnt == 0) continue;
+      const int st = cstart[cell];
+      double acc3[3] = {0.0, 0.0, 0.0};
+      for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
+        const int np = min(kAsmChunk, cnt - t0);
+        for (int v = tid; v < np * kPData; v += 256) {
+          int q = v / kPData, w = v - q * kPData;
+          long long p = st + t0 + q;
+          pd[q][w] = (w < 3) ? f[3 * p + w] : ((w < 12) ? Fn[9 * p + (w - 3)] : Cp[45 * p + (w - 12)]);
+        }
+        __syncthreads();
+        // a_l = F^T grad w_l for the 27 stencil nodes of each staged particle
+        for (int v = tid; v < np * 27; v += 256) {
+          int q = v / 27, l = v - 27 * q;
+          int lx = l % 3, ly = (l / 3) % 3, lz = l / 9;
+          double w0, d0, w1, d1, w2, d2;
+          wdw(lx, pd[q][0], s.inv_dx, w0, d0);
+          wdw(ly, pd[q][1], s.inv_dx, w1, d1);
+          wdw(lz, pd[q][2], s.inv_dx, w2, d2);
+          double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
+          const double* F = &pd[q][3];
+          for (int b = 0; b < 3; ++b) av[q][l][b] = F[b] * gx + F[3 + b] * gy + F[6 + b] * gz;
+        }
+        __syncthreads();
+        // Z_r[gamma][delta eps] = sum_beta a_k,beta C[3 gamma + beta][3 delta + eps], k = (r, ky, kz)
+        for (int v = tid; v < np * 81; v += 256) {
+          int q = v / 81, rr = (v / 27) % 3, e = v % 27;
+          if (rr < rlo || rr > rhi) continue;
+          int gm = e / 9, de = e % 9;
+          const double* a = av[q][rr + 3 * ky + 9 * kz];
+          const double* Cq = &pd[q][12];
+          zv[q][rr][e] = a[0] * Cq[tri9(3 * gm, de)] + a[1] * Cq[tri9(3 * gm + 1, de)] +
+                         a[2] * Cq[tri9(3 * gm + 2, de)];
+        }
+        __syncthreads();
+        if (blk_thread && br >= rlo && br <= rhi) {
+          for (int q = 0; q < np; ++q) {
+            const double* z = &zv[q][br][9 * bg];
+            const double* al = av[q][bl];
+            double a0 = al[0], a1 = al[1], a2 = al[2];
+            acc3[0] += z[0] * a0 + z[1] * a1 + z[2] * a2;
+            acc3[1] += z[3] * a0 + z[4] * a1 + z[5] * a2;
+            acc3[2] += z[6] * a0 + z[7] * a1 + z[8] * a2;
+          }
+        }
+        __syncthreads();
+      }
+      if (blk_thread && br >= rlo && br <= rhi) {
+        int sl = (blx - br + 2) + 5 * (bly - ky + 2) + 25 * (blz - kz + 2);
+        double* wrow = win[(c + br + 3) % 3] + sl * 9 + 3 * bg;
+        wrow[0] += acc3[0];
+        wrow[1] += acc3[1];
+        wrow[2] += acc3[2];
+      }
+    }
+    __syncthreads();
+    if (next < re) {
+      int nx, ny, nz;
+      unpidx(L.g, L.nodes[next], nx, ny, nz);
+      if (nx == c) {
+        finalize_row_block(win[(c + 3) % 3], next, L, fixed, mass[next], red);
+        ++next;
+      }
+    }
+    double* wz = win[(c + 3) % 3];
+    for (int e = tid; e < kRowVals; e += 256) wz[e] = 0.0;
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -416,13 +629,15 @@ void launch_particle_frac(const SceneDev& s, int n, const double* x, double* f, 
   if (n > 0) k_frac<<<blocks_for(n), kTpb, 0, st>>>(s, n, x, f, key);
 }
 
-void launch_p2g(const SceneDev& s, const LevelView& L0, const double* f, const double* v,
-                const double* C, const double* vol, const int* mat, const int* cstart,
-                const int* ccount, double dt, double t_end, double* mass, double* vstar,
-                double* xi, int* fixed, hipStream_t st) {
+void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
+                const double* v, const double* C, const double* vol, const int* mat,
+                const int* cstart, const int* ccount, double* partial, double dt, double t_end,
+                double* mass, double* vstar, double* xi, int* fixed, hipStream_t st) {
+  if (B.n > 0)
+    k_p2g_brick<<<B.n, 64, 0, st>>>(s, B, f, v, C, vol, mat, cstart, ccount, partial);
   if (L0.n > 0)
-    k_p2g<<<blocks_for(L0.n), kTpb, 0, st>>>(s, L0, f, v, C, vol, mat, cstart, ccount, dt, t_end,
-                                             mass, vstar, xi, fixed);
+    k_p2g_nodes<<<blocks_for(L0.n), kTpb, 0, st>>>(s, L0, B, partial, dt, t_end, mass, vstar, xi,
+                                                   fixed);
 }
 
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
@@ -442,12 +657,13 @@ void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const d
                                                     alpha, dt, psi_out, S_out);
 }
 
-void launch_gradient(const SceneDev& s, const LevelView& L0, const double* f, const double* S,
-                     const int* cstart, const int* ccount, const double* mass, const int* fixed,
-                     const double* dv, double dt, double* g, hipStream_t st) {
+void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
+                     const double* S, const int* cstart, const int* ccount, double* partial,
+                     const double* mass, const int* fixed, const double* dv, double dt, double* g,
+                     hipStream_t st) {
+  if (B.n > 0) k_grad_brick<<<B.n, 64, 0, st>>>(s, B, f, S, cstart, ccount, partial);
   if (L0.n > 0)
-    k_gradient<<<blocks_for(L0.n), kTpb, 0, st>>>(s, L0, f, S, cstart, ccount, mass, fixed, dv,
-                                                  dt, g);
+    k_grad_nodes<<<blocks_for(L0.n), kTpb, 0, st>>>(L0, B, partial, mass, fixed, dv, dt, g);
 }
 
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
@@ -457,12 +673,12 @@ void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, 
     k_g2p<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, x, v, C, F, mat, vstar, dv, dt);
 }
 
-void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const double* f, const double* F,
-                        const double* Cp, const int* cstart, const int* ccount,
-                        const double* mass, const int* fixed, hipStream_t st) {
-  if (L0.n > 0)
-    k_assemble_h0<<<(unsigned)((L0.n + kAsmWaves - 1) / kAsmWaves), 256, 0, st>>>(
-        s, L0, f, F, Cp, cstart, ccount, mass, fixed);
+void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
+                        const double* f, const double* F, const double* Cp, const int* cstart,
+                        const int* ccount, const double* mass, const int* fixed, hipStream_t st) {
+  if (n_seg > 0)
+    k_assemble_strip<<<n_seg, 256, 0, st>>>(s, L0, seg_begin, f, F, Cp, cstart, ccount, mass,
+                                            fixed);
 }
 
 }  // namespace hot

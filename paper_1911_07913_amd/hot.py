@@ -40,7 +40,10 @@ DBG_COUNTS = 50
 EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_particles",
            "hot_scene_info", "hot_destroy_scene", "hot_last_error", "hot_batch_create",
            "hot_batch_add", "hot_batch_round", "hot_batch_destroy", "hot_debug_read",
-           "hot_debug_prepare", "hot_debug_apply"]
+           "hot_debug_prepare", "hot_debug_apply", "hot_profile_enable", "hot_profile_read"]
+
+PROF_KERNELS = {0: "smooth0", 1: "residual0", 2: "assemble_h0", 3: "rap0", 4: "particle_eval",
+                5: "gradient", 6: "particle_hessian"}
 
 
 class hot_material(C.Structure):
@@ -118,12 +121,34 @@ def lib():
     L.hot_debug_read.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.hot_debug_prepare.argtypes = [vp, C.c_double]
     L.hot_debug_apply.argtypes = [vp, C.c_int32, dp, dp]
+    L.hot_profile_enable.argtypes = [vp, C.c_int32]
+    L.hot_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("hot_destroy_scene", "hot_batch_destroy", "hot_last_error"):
             f.restype = C.c_int32
     _lib = L
     return L
+
+
+def hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(line.split()[-1])
+    except OSError:
+        pass
+    return paths
+
+
+def _require_single_runtime():
+    rt = hip_runtimes()
+    if len(rt) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (%s): import torch before the first call "
+                           "into libhot when passing torch streams or allocators" % sorted(rt))
 
 
 def _check(st, ok_warn=True):
@@ -206,6 +231,8 @@ class Scene:
             cb[k].kind = int(b["kind"])
             for j, val in enumerate(np.asarray(b["p"], dtype=np.float64)[:16]):
                 cb[k].p[j] = float(val)
+        if stream or allocator is not None:
+            _require_single_runtime()
         self.params = params
         self.n = n
         self._allocator = allocator
@@ -261,6 +288,20 @@ class Scene:
         vec = np.ascontiguousarray(vec, dtype=np.float64)
         out = np.empty_like(vec)
         _check(lib().hot_debug_apply(self.handle, op, _dp(vec), _dp(out)))
+        return out
+
+    def profile(self, enable=True):
+        _check(lib().hot_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches, total_algorithmic_bytes)}"""
+        out = {}
+        for k, name in PROF_KERNELS.items():
+            ms = C.c_double()
+            n = C.c_int64()
+            b = C.c_double()
+            _check(lib().hot_profile_read(self.handle, k, C.byref(ms), C.byref(n), C.byref(b)))
+            out[name] = (ms.value, n.value, b.value)
         return out
 
     def close(self):
