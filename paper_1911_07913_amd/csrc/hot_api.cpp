@@ -338,13 +338,13 @@ hot_status alloc_level(hot_scene* s, int m, int n) {
   LevelH& L = s->L[m];
   size_t vsz = s->mixed ? 4 : 8;
   TRY(ensure(s, L.nodes, (size_t)n * 4));
-  TRY(ensure(s, L.H, (size_t)n * kRowVals * 8));
+  TRY(ensure(s, L.H, (size_t)n * kRowStride * 8));
   TRY(ensure(s, L.Dinv, (size_t)n * 72));
   TRY(ensure(s, L.diag, (size_t)n * 24));
   TRY(ensure(s, L.freed, (size_t)n * 3));
   TRY(ensure(s, L.pat, (size_t)n * 16));
   if (s->mixed) {
-    TRY(ensure(s, L.Hb, (size_t)n * kRowVals * 2));
+    TRY(ensure(s, L.Hb, (size_t)n * kRowStride * 2));
     TRY(ensure(s, L.Dinv32, (size_t)n * 36));
     TRY(ensure(s, L.diag32, (size_t)n * 12));
   }
@@ -1181,7 +1181,7 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
     case HOT_DBG_PERM: src = s->P[s->cur].id; sz = (size_t)s->n * 4; break;
     case HOT_DBG_LEVEL_NODES: src = L.nodes.p; sz = (size_t)L.n * 4; break;
     case HOT_DBG_LEVEL_PATTERN: src = L.pat.p; sz = (size_t)L.n * 16; break;
-    case HOT_DBG_LEVEL_MATRIX: src = L.H.p; sz = (size_t)L.n * kRowVals * 8; break;
+    case HOT_DBG_LEVEL_MATRIX: src = L.H.p; sz = (size_t)L.n * kRowVals * 8; break;  // reordered below
     case HOT_DBG_LEVEL_FREE: src = L.freed.p; sz = (size_t)L.n * 3; break;
     case HOT_DBG_NODE_MASS: src = s->mass.p; sz = (size_t)s->L[0].n * 8; break;
     case HOT_DBG_NODE_VSTAR: src = s->vstar.p; sz = (size_t)s->L[0].n * 24; break;
@@ -1209,6 +1209,18 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
   if (sz == 0) return HOT_OK;
   if (host) {
     std::memcpy(dst, src, sz);
+    return HOT_OK;
+  }
+  if (what == HOT_DBG_LEVEL_MATRIX) {
+    // device rows are [entry][slot padded to 128]; hand out [slot][3][3]
+    std::vector<double> tmpv((size_t)L.n * kRowStride);
+    HIPCHK(hipMemcpyAsync(tmpv.data(), src, tmpv.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    double* o = (double*)dst;
+    for (int i = 0; i < L.n; ++i)
+      for (int sl = 0; sl < kSlots; ++sl)
+        for (int c = 0; c < 9; ++c)
+          o[(size_t)i * kRowVals + sl * 9 + c] = tmpv[(size_t)i * kRowStride + c * kSlotPad + sl];
     return HOT_OK;
   }
   if (what == HOT_DBG_LEVEL_NODES) {

@@ -11,8 +11,11 @@
 //              order (x fastest).
 //   matrices   "diagonal storage": every row keeps 125 3x3 blocks, one per
 //              neighbour offset (dx,dy,dz) in [-2,2]^3, slot s = (dx+2) +
-//              5(dy+2) + 25(dz+2); row i occupies 1125 consecutive values
-//              [i][slot][3][3].  FP64, or BF16 in the mixed-precision V-cycle.
+//              5(dy+2) + 25(dz+2).  Row i occupies kRowStride consecutive
+//              values laid out [i][entry 0..8][slot, padded to 128], so 64
+//              lanes that each own one block read every entry with one fully
+//              coalesced 512-byte load.  FP64, or BF16 in the mixed-precision
+//              V-cycle.
 //   vectors    node vectors interleaved [n][3].
 #pragma once
 
@@ -25,7 +28,9 @@ namespace hot {
 
 constexpr int kSlots = 125;
 constexpr int kBlock = 9;
-constexpr int kRowVals = kSlots * kBlock;  // 1125
+constexpr int kRowVals = kSlots * kBlock;  // 1125 structural values per row
+constexpr int kSlotPad = 128;                // slots per entry plane (padded)
+constexpr int kRowStride = kBlock * kSlotPad;  // 1152 stored values per row
 constexpr int kCenter = 62;                // slot of offset (0,0,0)
 constexpr int kMaxLevels = 8;
 constexpr int kMaxMats = 64;
@@ -113,6 +118,16 @@ inline GridGeom make_geom(int nx, int ny, int nz) {
   g.pd[0] = nx + 4; g.pd[1] = ny + 4; g.pd[2] = nz + 4;
   g.ptotal = (long long)g.pd[0] * g.pd[1] * g.pd[2];
   return g;
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remap the hardware block index so every XCD processes one contiguous
+// range of logical blocks: neighbouring rows (which share vector entries,
+// fine rows or particles) then share an L2.
+__device__ inline int xcd_block(int bid, int nblocks) {
+  const int q = nblocks / 8, r = nblocks % 8;
+  const int x = bid % 8, idx = bid / 8;
+  return x * q + (x < r ? x : r) + idx;
 }
 
 // ---------------------------------------------------------------- launchers

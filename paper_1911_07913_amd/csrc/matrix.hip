@@ -1,9 +1,10 @@
 // Galerkin coarsening and the multigrid V-cycle (Sec. 4, Alg. V-cycle).
 //
 // Matrices use 125-slot diagonal storage (Sec. 6): row i holds the 3x3 blocks
-// of its neighbours at offsets [-2,2]^3.  Every row kernel is one wave per
-// row: the 1125 values of a row are contiguous, so a wave reads them with
-// coalesced loads and reduces its three output components with shuffles.
+// of its neighbours at offsets [-2,2]^3, stored entry-major ([entry][slot]).
+// Every row kernel is one wave per row: each lane owns whole blocks, reads
+// their entries with coalesced loads and the three output components are
+// reduced with shuffles.
 // The FP64 path stores blocks as double; the mixed path stores BF16 blocks and
 // runs the V-cycle vectors and accumulation in FP32.
 #include "mpm_math.h"
@@ -55,44 +56,41 @@ struct MatOf<float> {
 };
 
 // y = H_i . x for one row, computed by a whole wave; result valid in all lanes.
-// Lane l handles values e = l + 64k of the row (slot e/9, entry e%9).  All
-// matrix values and neighbour indices of the row are loaded first, then the
-// x entries, so each row costs two dependent memory round trips; slots the
-// symbolic pattern marks absent are not read at all.
-constexpr int kRowIt = (kRowVals + 63) / 64;  // 18
-
-__device__ inline uint32_t pick_word(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int k) {
-  return k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
+// Lane l owns the blocks of slots l and l + 64: it reads their 9 entries with
+// coalesced loads (entry-major row layout) and the neighbour's 3 vector
+// entries, so a row costs two dependent memory round trips.  Slots the
+// symbolic pattern marks absent are not read.
+__device__ inline bool slot_present(const uint32_t* w, int s) {
+  return s < kSlots && ((w[s >> 5] >> (s & 31)) & 1u);
 }
 
 template <typename V>
 __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict__ x, int lane,
                                   V* y) {
   typedef typename MatOf<V>::type M;
-  const M* Hrow = MatOf<V>::H(L) + (long long)i * kRowVals;
+  const M* Hrow = MatOf<V>::H(L) + (long long)i * kRowStride;
   const long long pn = L.nodes[i];
-  const uint32_t w0 = L.pat[4 * i], w1 = L.pat[4 * i + 1], w2 = L.pat[4 * i + 2],
-                 w3 = L.pat[4 * i + 3];
-  V h[kRowIt];
-  int jn[kRowIt];
+  const uint32_t w[4] = {L.pat[4 * i], L.pat[4 * i + 1], L.pat[4 * i + 2], L.pat[4 * i + 3]};
+  V h[2][9];
+  int jn[2];
 #pragma unroll
-  for (int k = 0; k < kRowIt; ++k) {
-    const int e = lane + 64 * k;
-    const int s = e / 9;
-    const bool present = (e < kRowVals) && ((pick_word(w0, w1, w2, w3, s >> 5) >> (s & 31)) & 1u);
-    h[k] = present ? ldm<V, M>(Hrow + e) : (V)0;
-    jn[k] = present ? L.map[pn + slot_offset(L.g, s)] : -1;
+  for (int ps = 0; ps < 2; ++ps) {
+    const int s = lane + 64 * ps;
+    const bool pr = slot_present(w, s);
+    jn[ps] = pr ? L.map[pn + slot_offset(L.g, s)] : -1;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) h[ps][c] = pr ? ldm<V, M>(Hrow + c * kSlotPad + s) : (V)0;
   }
   V a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
-  for (int k = 0; k < kRowIt; ++k) {
-    const int e = lane + 64 * k;
-    const int c = e % 9;
-    const int g = c / 3, d = c - 3 * g;
-    V pr = (jn[k] >= 0) ? h[k] * x[3 * jn[k] + d] : (V)0;
-    a0 += (g == 0) ? pr : (V)0;
-    a1 += (g == 1) ? pr : (V)0;
-    a2 += (g == 2) ? pr : (V)0;
+  for (int ps = 0; ps < 2; ++ps) {
+    if (jn[ps] >= 0) {
+      const V* xj = x + 3 * (long long)jn[ps];
+      V x0 = xj[0], x1 = xj[1], x2 = xj[2];
+      a0 += h[ps][0] * x0 + h[ps][1] * x1 + h[ps][2] * x2;
+      a1 += h[ps][3] * x0 + h[ps][4] * x1 + h[ps][5] * x2;
+      a2 += h[ps][6] * x0 + h[ps][7] * x1 + h[ps][8] * x2;
+    }
   }
   y[0] = wave_sum_t(a0);
   y[1] = wave_sum_t(a1);
@@ -104,54 +102,71 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
 // node embedding: the fine children of I are 2I + a, a in {-1,0,1}^3, weight
 // prod(1 or 1/2); each fine block (i, j) is spread to the coarse parents J of
 // j.  P~ = Pi P drops constrained fine DOFs.  The symbolic coarse pattern is
-// the structure of R pattern P.  Accumulation in LDS, one wave per coarse row.
+// the structure of R pattern P.  Accumulation in LDS, one wave per coarse
+// row; lane l handles fine slots l and l + 64 of each child row.
 constexpr int kRapWaves = 4;
 
 __global__ __launch_bounds__(256) void k_rap(LevelView F, LevelView C) {
-  __shared__ double acc_all[kRapWaves][kRowVals];
+  __shared__ double acc_all[kRapWaves][kRowStride];
   __shared__ uint32_t pat_all[kRapWaves][4];
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int I = blockIdx.x * kRapWaves + wave;
+  int I = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
   if (I >= C.n) return;
   double* acc = acc_all[wave];
   uint32_t* pat = pat_all[wave];
-  for (int e = lane; e < kRowVals; e += 64) acc[e] = 0.0;
+  for (int e = lane; e < kRowStride; e += 64) acc[e] = 0.0;
   if (lane < 4) pat[lane] = 0u;
   wave_sync();
   int X, Y, Z;
   unpidx(C.g, C.nodes[I], X, Y, Z);
+  // the 27 fine children's indices, one per lane
+  int ichild = -1;
+  if (lane < 27)
+    ichild = F.map[pidx(F.g, 2 * X + lane % 3 - 1, 2 * Y + (lane / 3) % 3 - 1, 2 * Z + lane / 9 - 1)];
   for (int a = 0; a < 27; ++a) {
+    int i = __shfl(ichild, a, 64);
+    if (i < 0) continue;
     int ax = a % 3 - 1, ay = (a / 3) % 3 - 1, az = a / 9 - 1;
     int cx = 2 * X + ax, cy = 2 * Y + ay, cz = 2 * Z + az;
-    int i = F.map[pidx(F.g, cx, cy, cz)];
-    if (i < 0) continue;
     double wa = (ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0);
-    double fi[3] = {(double)F.free_dof[3 * i], (double)F.free_dof[3 * i + 1],
-                    (double)F.free_dof[3 * i + 2]};
-    uint32_t pw[4] = {F.pat[4 * i], F.pat[4 * i + 1], F.pat[4 * i + 2], F.pat[4 * i + 3]};
-    const double* Hrow = F.H + (long long)i * kRowVals;
-    for (int e = lane; e < kRowVals; e += 64) {
-      int s = e / 9, c = e - 9 * (e / 9);
-      if (!((pw[s >> 5] >> (s & 31)) & 1u)) continue;
-      int jx = cx + s % 5 - 2, jy = cy + (s / 5) % 5 - 2, jz = cz + s / 25 - 2;
-      int j = F.map[pidx(F.g, jx, jy, jz)];
-      int g = c / 3, d = c - 3 * g;
-      double val = Hrow[e] * wa * fi[g] * (j >= 0 ? (double)F.free_dof[3 * j + d] : 0.0);
-      int Px[2], Py[2], Pz[2];
-      double wx[2], wy[2], wz[2];
-      int nx, ny, nz;
-      if (jx & 1) { Px[0] = (jx - 1) >> 1; Px[1] = (jx + 1) >> 1; wx[0] = wx[1] = 0.5; nx = 2; }
-      else { Px[0] = jx >> 1; wx[0] = 1.0; nx = 1; }
-      if (jy & 1) { Py[0] = (jy - 1) >> 1; Py[1] = (jy + 1) >> 1; wy[0] = wy[1] = 0.5; ny = 2; }
-      else { Py[0] = jy >> 1; wy[0] = 1.0; ny = 1; }
-      if (jz & 1) { Pz[0] = (jz - 1) >> 1; Pz[1] = (jz + 1) >> 1; wz[0] = wz[1] = 0.5; nz = 2; }
-      else { Pz[0] = jz >> 1; wz[0] = 1.0; nz = 1; }
+    const double fi0 = (double)F.free_dof[3 * i], fi1 = (double)F.free_dof[3 * i + 1],
+                 fi2 = (double)F.free_dof[3 * i + 2];
+    const uint32_t w[4] = {F.pat[4 * i], F.pat[4 * i + 1], F.pat[4 * i + 2], F.pat[4 * i + 3]};
+    const double* Hrow = F.H + (long long)i * kRowStride;
+    const long long pni = F.nodes[i];
+    double h[2][9];
+    int jn[2];
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      const int s = lane + 64 * ps;
+      const bool pr = slot_present(w, s);
+      jn[ps] = pr ? F.map[pni + slot_offset(F.g, s)] : -1;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) h[ps][c] = pr ? Hrow[c * kSlotPad + s] : 0.0;
+    }
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      if (jn[ps] < 0) continue;
+      const int s = lane + 64 * ps;
+      const int j = jn[ps];
+      const double fj0 = (double)F.free_dof[3 * j], fj1 = (double)F.free_dof[3 * j + 1],
+                   fj2 = (double)F.free_dof[3 * j + 2];
+      double v[9];
+      v[0] = h[ps][0] * fi0 * fj0; v[1] = h[ps][1] * fi0 * fj1; v[2] = h[ps][2] * fi0 * fj2;
+      v[3] = h[ps][3] * fi1 * fj0; v[4] = h[ps][4] * fi1 * fj1; v[5] = h[ps][5] * fi1 * fj2;
+      v[6] = h[ps][6] * fi2 * fj0; v[7] = h[ps][7] * fi2 * fj1; v[8] = h[ps][8] * fi2 * fj2;
+      const int jx = cx + s % 5 - 2, jy = cy + (s / 5) % 5 - 2, jz = cz + s / 25 - 2;
+      const int Px0 = jx >> 1, Py0 = jy >> 1, Pz0 = jz >> 1;
+      const int nx = (jx & 1) + 1, ny = (jy & 1) + 1, nz = (jz & 1) + 1;
+      const double wj = wa * ((jx & 1) ? 0.5 : 1.0) * ((jy & 1) ? 0.5 : 1.0) * ((jz & 1) ? 0.5 : 1.0);
       for (int u = 0; u < nx; ++u)
-        for (int v = 0; v < ny; ++v)
-          for (int w = 0; w < nz; ++w) {
-            int S = (Px[u] - X + 2) + 5 * (Py[v] - Y + 2) + 25 * (Pz[w] - Z + 2);
-            if (val != 0.0) atomicAdd(&acc[S * 9 + c], val * (wx[u] * wy[v] * wz[w]));
-            if (c == 0) atomicOr(&pat[S >> 5], 1u << (S & 31));
+        for (int vv = 0; vv < ny; ++vv)
+          for (int ww = 0; ww < nz; ++ww) {
+            const int S = (Px0 + u - X + 2) + 5 * (Py0 + vv - Y + 2) + 25 * (Pz0 + ww - Z + 2);
+            atomicOr(&pat[S >> 5], 1u << (S & 31));
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+              if (v[c] != 0.0) atomicAdd(&acc[c * kSlotPad + S], v[c] * wj);
           }
     }
   }
@@ -162,7 +177,7 @@ __global__ __launch_bounds__(256) void k_rap(LevelView F, LevelView C) {
 
 __global__ void k_to_bf16(LevelView L) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long nv = (long long)L.n * kRowVals;
+  long long nv = (long long)L.n * kRowStride;
   if (k < nv) L.Hb[k] = f32_to_bf16((float)L.H[k]);
   if (k < (long long)L.n * 9) L.Dinv32[k] = (float)L.Dinv[k];
   if (k < (long long)L.n * 3) L.diag32[k] = (float)L.diag[k];
@@ -186,7 +201,7 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_residual(LevelView L, const V* __restrict__ b,
                                                   const V* __restrict__ u, V* __restrict__ r) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = blockIdx.x * kRowWaves + wave;
+  int i = xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave;
   if (i >= L.n) return;
   V y[3];
   row_matvec<V>(L, i, u, lane, y);
@@ -198,7 +213,7 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict__ b,
                                                 const V* __restrict__ u, V* __restrict__ uo) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = blockIdx.x * kRowWaves + wave;
+  int i = xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave;
   if (i >= L.n) return;
   V y[3];
   row_matvec<V>(L, i, u, lane, y);
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(LevelView L, const V
 __global__ __launch_bounds__(256) void k_spmv(LevelView L, const double* __restrict__ x,
                                               double* __restrict__ y) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = blockIdx.x * kRowWaves + wave;
+  int i = xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave;
   if (i >= L.n) return;
   double v[3];
   row_matvec<double>(L, i, x, lane, v);
@@ -357,7 +372,7 @@ void launch_rap(const LevelView& F, const LevelView& C, hipStream_t st) {
   if (C.n > 0) k_rap<<<(unsigned)((C.n + kRapWaves - 1) / kRapWaves), 256, 0, st>>>(F, C);
 }
 void launch_to_bf16(const LevelView& L, hipStream_t st) {
-  long long nv = (long long)L.n * kRowVals;
+  long long nv = (long long)L.n * kRowStride;
   if (nv > 0) k_to_bf16<<<blocks_for(nv), kTpb, 0, st>>>(L);
 }
 

@@ -376,7 +376,8 @@ __device__ inline void inv3(const double* A, double* B) {
     for (int c = 0; c < 3; ++c) B[3 * r + c] = K[3 * c + r] * id;
 }
 
-// Finalise one block row held in LDS (acc[1125]) of a level:
+// Finalise one block row held in LDS (acc[kRowStride], [entry][slot]) of a
+// level:
 //  * level 0 (fixed != null): add the lumped mass m_i I on the diagonal, then
 //    project Dirichlet rows/columns (constrained rows become m_i I, blocks
 //    coupling to a constrained neighbour vanish), Sec. 4.1;
@@ -384,53 +385,55 @@ __device__ inline void inv3(const double* A, double* B) {
 //    constrained with diagonal 1;
 //  * write the row, the per-DOF free flags, the scalar diagonal and the l1
 //    block-Jacobi inverse D~^{-1} = (H_ii + diag(sum_{j != i} |H_ij| row sums))^{-1}.
-// Executed by one full wave.
+// Executed by one full wave; lane l owns slots l and l + 64.
 __device__ inline void finalize_row(double* acc, int i, const LevelView& L, const int* fixed,
                                     double mass_i, int lane) {
   bool row_fixed = false;
   if (fixed != nullptr) {
     row_fixed = fixed[i] != 0;
-    if (row_fixed) {
-      for (int e = lane; e < kRowVals; e += 64) acc[e] = 0.0;
-    } else {
-      long long pn = L.nodes[i];
-      for (int e = lane; e < kRowVals; e += 64) {
-        int s = e / 9;
-        if (s == kCenter) continue;
+    long long pn = L.nodes[i];
+    for (int s = lane; s < kSlots; s += 64) {
+      bool z = row_fixed;
+      if (!z && s != kCenter) {
         int j = L.map[pn + slot_offset(L.g, s)];
-        if (j >= 0 && fixed[j]) acc[e] = 0.0;
+        z = (j >= 0 && fixed[j]);
       }
+      if (z)
+        for (int c = 0; c < 9; ++c) acc[c * kSlotPad + s] = 0.0;
     }
     wave_sync();
-    if (lane < 3) acc[kCenter * 9 + 4 * lane] += mass_i;
+    if (lane < 3) acc[(4 * lane) * kSlotPad + kCenter] += mass_i;
     wave_sync();
   }
   if (lane == 0) {
     for (int g = 0; g < 3; ++g) {
-      double d = acc[kCenter * 9 + 4 * g];
+      double d = acc[(4 * g) * kSlotPad + kCenter];
       bool zero = (d == 0.0);
-      if (zero) acc[kCenter * 9 + 4 * g] = 1.0;
+      if (zero) acc[(4 * g) * kSlotPad + kCenter] = 1.0;
       L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
       L.diag[3 * i + g] = zero ? 1.0 : d;
     }
   }
   wave_sync();
   double l1[3] = {0.0, 0.0, 0.0};
-  for (int e = lane; e < kRowVals; e += 64) {
-    double v = acc[e];
-    L.H[(long long)i * kRowVals + e] = v;
-    if (e / 9 != kCenter) {
-      int g = (e % 9) / 3;
-      double av = fabs(v);
-      l1[0] += (g == 0) ? av : 0.0;
-      l1[1] += (g == 1) ? av : 0.0;
-      l1[2] += (g == 2) ? av : 0.0;
+  double* Hrow = L.H + (long long)i * kRowStride;
+  for (int s = lane; s < kSlots; s += 64) {
+    for (int c = 0; c < 9; ++c) {
+      double v = acc[c * kSlotPad + s];
+      Hrow[c * kSlotPad + s] = v;
+      if (s != kCenter) {
+        double av = fabs(v);
+        int g = c / 3;
+        l1[0] += (g == 0) ? av : 0.0;
+        l1[1] += (g == 1) ? av : 0.0;
+        l1[2] += (g == 2) ? av : 0.0;
+      }
     }
   }
   for (int g = 0; g < 3; ++g) l1[g] = wave_sum(l1[g]);
   if (lane == 0) {
     double Dt[9];
-    for (int k = 0; k < 9; ++k) Dt[k] = acc[kCenter * 9 + k];
+    for (int k = 0; k < 9; ++k) Dt[k] = acc[k * kSlotPad + kCenter];
     for (int g = 0; g < 3; ++g) Dt[4 * g] += l1[g];
     double Di[9];
     inv3(Dt, Di);

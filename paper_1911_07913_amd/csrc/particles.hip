@@ -464,40 +464,43 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
   dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
 }
 
-// Block-level version of finalize_row (256 threads).
-__device__ inline void finalize_row_block(double* acc, int i, const LevelView& L,
-                                          const int* __restrict__ fixed, double mass_i,
-                                          double* red) {
+// Block-level finalisation of level-0 row i held in LDS (256 threads): mass
+// on the diagonal, Dirichlet projection (constrained row -> m_i I, blocks to
+// constrained neighbours -> 0), exact-zero diagonal rule, write-out, scalar
+// diagonal and the l1 block-Jacobi inverse.  nbf holds the constrained flags
+// of the 5x5 y-z neighbourhood of the segment's x-line, x-major from xw0.
+__device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0, int nxw,
+                                          const LevelView& L, const uint8_t* nbf,
+                                          bool row_fixed, double mass_i, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool row_fixed = fixed[i] != 0;
-  if (row_fixed) {
-    for (int e = tid; e < kRowVals; e += 256) acc[e] = 0.0;
-  } else {
-    long long pn = L.nodes[i];
-    for (int e = tid; e < kRowVals; e += 256) {
-      int s = e / 9;
-      if (s == kCenter) continue;
-      int j = L.map[pn + slot_offset(L.g, s)];
-      if (j >= 0 && fixed[j]) acc[e] = 0.0;
+  for (int e = tid; e < kBlock * kSlots; e += 256) {
+    int c = e / kSlots, s = e - c * kSlots;
+    bool z = row_fixed;
+    if (!z && s != kCenter) {
+      int dx = s % 5 - 2, dy = (s / 5) % 5 - 2, dz = s / 25 - 2;
+      z = nbf[(xi + dx - xw0) + nxw * ((dy + 2) + 5 * (dz + 2))] != 0;
     }
+    if (z) acc[c * kSlotPad + s] = 0.0;
   }
   __syncthreads();
   if (tid == 0) {
     for (int g = 0; g < 3; ++g) {
-      double d = acc[kCenter * 9 + 4 * g] + mass_i;
+      double d = acc[(4 * g) * kSlotPad + kCenter] + mass_i;
       bool zero = (d == 0.0);
-      acc[kCenter * 9 + 4 * g] = zero ? 1.0 : d;
+      acc[(4 * g) * kSlotPad + kCenter] = zero ? 1.0 : d;
       L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
       L.diag[3 * i + g] = zero ? 1.0 : d;
     }
   }
   __syncthreads();
   double l1[3] = {0.0, 0.0, 0.0};
-  for (int e = tid; e < kRowVals; e += 256) {
-    double v = acc[e];
-    L.H[(long long)i * kRowVals + e] = v;
-    if (e / 9 != kCenter) {
-      int g = (e % 9) / 3;
+  double* Hrow = L.H + (long long)i * kRowStride;
+  for (int e = tid; e < kBlock * kSlots; e += 256) {
+    int c = e / kSlots, s = e - c * kSlots;
+    double v = acc[c * kSlotPad + s];
+    Hrow[c * kSlotPad + s] = v;
+    if (s != kCenter) {
+      int g = c / 3;
       double av = fabs(v);
       l1[0] += (g == 0) ? av : 0.0;
       l1[1] += (g == 1) ? av : 0.0;
@@ -511,7 +514,7 @@ __device__ inline void finalize_row_block(double* acc, int i, const LevelView& L
   __syncthreads();
   if (tid == 0) {
     double Dt[9];
-    for (int k = 0; k < 9; ++k) Dt[k] = acc[kCenter * 9 + k];
+    for (int k = 0; k < 9; ++k) Dt[k] = acc[k * kSlotPad + kCenter];
     for (int g = 0; g < 3; ++g) Dt[4 * g] += red[g] + red[3 + g] + red[6 + g] + red[9 + g];
     double Di[9];
     inv3(Dt, Di);
@@ -529,43 +532,107 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
                                                          const int* __restrict__ ccount,
                                                          const double* __restrict__ mass,
                                                          const int* __restrict__ fixed) {
-  __shared__ double win[3][kRowVals];
+  constexpr int kMaxCx = kSegRows + 2;
+  __shared__ double win[3][kRowStride];
   __shared__ double pd[kAsmChunk][kPData];
   __shared__ double av[kAsmChunk][27][3];
   __shared__ double zv[kAsmChunk][3][27];
   __shared__ double red[12];
+  __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
+  __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
+  __shared__ double rmass[kSegRows];
+  __shared__ int rx[kSegRows];
   const int tid = threadIdx.x;
-  const int rb = seg_begin[blockIdx.x], re = seg_begin[blockIdx.x + 1];
+  const int seg = xcd_block(blockIdx.x, gridDim.x);
+  const int rb = seg_begin[seg], re = seg_begin[seg + 1];
   int xa, ys, zs, xb, yy, zz;
   unpidx(L.g, L.nodes[rb], xa, ys, zs);
   unpidx(L.g, L.nodes[re - 1], xb, yy, zz);
-  for (int e = tid; e < 3 * kRowVals; e += 256) (&win[0][0])[e] = 0.0;
-  // block-phase role of this thread: row offset r, stencil node l, block row g
+  const int ncx = xb - xa + 3;
+  // particle ranges of the 9 cell columns over the whole sweep, in one trip
+  for (int v = tid; v < ncx * 9; v += 256) {
+    int ci = v / 9, col = v - 9 * ci;
+    long long cell = pidx(L.g, xa - 2 + ci, ys - col % 3, zs - col / 3);
+    mcnt[v] = ccount[cell];
+    mst[v] = cstart[cell];
+  }
+  // constrained flags of the rows' neighbourhood, the rows' masses and x
+  const int xw0 = xa - 2, nxw = ncx + 2;
+  for (int v = tid; v < nxw * 25; v += 256) {
+    int xo = v % nxw, r = v / nxw;
+    int j = L.map[pidx(L.g, xw0 + xo, ys + r % 5 - 2, zs + r / 5 - 2)];
+    nbf[v] = (j >= 0 && fixed[j]) ? 1 : 0;
+  }
+  for (int v = tid; v < re - rb; v += 256) {
+    int x0, y0, z0;
+    unpidx(L.g, L.nodes[rb + v], x0, y0, z0);
+    rx[v] = x0;
+    rmass[v] = mass[rb + v];
+  }
+  for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
   const bool blk_thread = tid < 243;
   const int br = tid / 81, bl = (tid / 3) % 27, bg = tid % 3;
   const int blx = bl % 3, bly = (bl / 3) % 3, blz = bl / 9;
-  int next = rb;
   __syncthreads();
-  for (int c = xa - 2; c <= xb; ++c) {
+  // job = (cell v = ci*9 + col, chunk start t0); jobs run in sweep order
+  auto next_job = [&](int v, int t0, int& nv, int& nt) {
+    if (v >= 0 && t0 + kAsmChunk < mcnt[v]) {
+      nv = v;
+      nt = t0 + kAsmChunk;
+      return;
+    }
+    for (int w = v + 1; w < ncx * 9; ++w)
+      if (mcnt[w] > 0) {
+        nv = w;
+        nt = 0;
+        return;
+      }
+    nv = -1;
+    nt = 0;
+  };
+  auto fetch = [&](int v, int t0, double* r) {
+    if (v < 0) return;
+    int np = min(kAsmChunk, mcnt[v] - t0);
+    long long st = mst[v] + t0;
+    for (int k = 0; k < 2; ++k) {
+      int e = tid + 256 * k;
+      if (e < np * kPData) {
+        int q = e / kPData, w = e - q * kPData;
+        long long pp = st + q;
+        r[k] = (w < 3) ? f[3 * pp + w] : ((w < 12) ? Fn[9 * pp + (w - 3)] : Cp[45 * pp + (w - 12)]);
+      }
+    }
+  };
+  double regs[2] = {0.0, 0.0};
+  int jv, jt;
+  next_job(-1, 0, jv, jt);
+  fetch(jv, jt, regs);
+  int next_row = rb;
+  for (int ci = 0; ci < ncx; ++ci) {
+    const int c = xa - 2 + ci;
     const int rlo = max(0, xa - c), rhi = min(2, xb - c);
     for (int col = 0; col < 9; ++col) {
-      const int ky = col % 3, kz = col / 3;
-      const long long cell = pidx(L.g, c, ys - ky, zs - kz);
-      const int cnt = ccount[cell];
+      const int v = ci * 9 + col;
+      const int cnt = mcnt[v];
       if (cnt == 0) continue;
-      const int st = cstart[cell];
+      const int ky = col % 3, kz = col / 3;
       double acc3[3] = {0.0, 0.0, 0.0};
       for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
         const int np = min(kAsmChunk, cnt - t0);
-        for (int v = tid; v < np * kPData; v += 256) {
-          int q = v / kPData, w = v - q * kPData;
-          long long p = st + t0 + q;
-          pd[q][w] = (w < 3) ? f[3 * p + w] : ((w < 12) ? Fn[9 * p + (w - 3)] : Cp[45 * p + (w - 12)]);
+        for (int k = 0; k < 2; ++k) {
+          int e = tid + 256 * k;
+          if (e < np * kPData) {
+            int q = e / kPData;
+            pd[q][e - q * kPData] = regs[k];
+          }
         }
         __syncthreads();
-        // a_l = F^T grad w_l for the 27 stencil nodes of each staged particle
-        for (int v = tid; v < np * 27; v += 256) {
-          int q = v / 27, l = v - 27 * q;
+        // prefetch the next chunk while this one is processed
+        int nv, nt;
+        next_job(v, t0, nv, nt);
+        fetch(nv, nt, regs);
+        for (int u = tid; u < np * 27; u += 256) {
+          int q = u / 27, l = u - 27 * q;
           int lx = l % 3, ly = (l / 3) % 3, lz = l / 9;
           double w0, d0, w1, d1, w2, d2;
           wdw(lx, pd[q][0], s.inv_dx, w0, d0);
@@ -576,9 +643,8 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
           for (int b = 0; b < 3; ++b) av[q][l][b] = F[b] * gx + F[3 + b] * gy + F[6 + b] * gz;
         }
         __syncthreads();
-        // Z_r[gamma][delta eps] = sum_beta a_k,beta C[3 gamma + beta][3 delta + eps], k = (r, ky, kz)
-        for (int v = tid; v < np * 81; v += 256) {
-          int q = v / 81, rr = (v / 27) % 3, e = v % 27;
+        for (int u = tid; u < np * 81; u += 256) {
+          int q = u / 81, rr = (u / 27) % 3, e = u % 27;
           if (rr < rlo || rr > rhi) continue;
           int gm = e / 9, de = e % 9;
           const double* a = av[q][rr + 3 * ky + 9 * kz];
@@ -597,27 +663,24 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
             acc3[2] += z[6] * a0 + z[7] * a1 + z[8] * a2;
           }
         }
-        __syncthreads();
       }
       if (blk_thread && br >= rlo && br <= rhi) {
         int sl = (blx - br + 2) + 5 * (bly - ky + 2) + 25 * (blz - kz + 2);
-        double* wrow = win[(c + br + 3) % 3] + sl * 9 + 3 * bg;
+        double* wrow = win[(c + br + 3) % 3] + (3 * bg) * kSlotPad + sl;
         wrow[0] += acc3[0];
-        wrow[1] += acc3[1];
-        wrow[2] += acc3[2];
+        wrow[kSlotPad] += acc3[1];
+        wrow[2 * kSlotPad] += acc3[2];
       }
     }
     __syncthreads();
-    if (next < re) {
-      int nx, ny, nz;
-      unpidx(L.g, L.nodes[next], nx, ny, nz);
-      if (nx == c) {
-        finalize_row_block(win[(c + 3) % 3], next, L, fixed, mass[next], red);
-        ++next;
-      }
+    if (next_row < re && rx[next_row - rb] == c) {
+      int ro = next_row - rb;
+      bool rf = nbf[(c - xw0) + nxw * (2 + 5 * 2)] != 0;
+      finalize_row_block(win[(c + 3) % 3], next_row, c, xw0, nxw, L, nbf, rf, rmass[ro], red);
+      ++next_row;
     }
     double* wz = win[(c + 3) % 3];
-    for (int e = tid; e < kRowVals; e += 256) wz[e] = 0.0;
+    for (int e = tid; e < kRowStride; e += 256) wz[e] = 0.0;
     __syncthreads();
   }
 }
