@@ -115,39 +115,30 @@ __device__ inline void svd3(const double* F, double* U, double* s, double* V) {
   double nrm[3];
   for (int k = 0; k < 3; ++k)
     nrm[k] = sqrt(B[k] * B[k] + B[3 + k] * B[3 + k] + B[6 + k] * B[6 + k]);
-  // sort columns by decreasing norm; each swap negates one column of both B
-  // and V so V stays a rotation and B V^T is unchanged.
-  int ord[3] = {0, 1, 2};
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2 - a; ++b)
-      if (nrm[ord[b]] < nrm[ord[b + 1]]) {
-        int tmp = ord[b];
-        ord[b] = ord[b + 1];
-        ord[b + 1] = tmp;
+  // sort columns by decreasing norm with a 3-comparator network; each swap
+  // also negates the second column of both B and V, so V stays a rotation and
+  // B V^T is unchanged.  Indices are compile-time constants (no spills).
+  auto cswap = [&](const int a, const int b) {
+    if (nrm[a] < nrm[b]) {
+      double t = nrm[a];
+      nrm[a] = nrm[b];
+      nrm[b] = t;
+      for (int r = 0; r < 3; ++r) {
+        double ba = B[3 * r + a], bb = B[3 * r + b];
+        B[3 * r + a] = bb;
+        B[3 * r + b] = -ba;
+        double va = V[3 * r + a], vb = V[3 * r + b];
+        V[3 * r + a] = vb;
+        V[3 * r + b] = -va;
       }
-  double Bs[9], Vs[9], ns[3];
-  int perm_sign = 1;
-  {
-    // parity of the permutation
-    int inv = 0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = a + 1; b < 3; ++b)
-        if (ord[a] > ord[b]) ++inv;
-    perm_sign = (inv & 1) ? -1 : 1;
-  }
-  for (int k = 0; k < 3; ++k) {
-    ns[k] = nrm[ord[k]];
-    for (int r = 0; r < 3; ++r) {
-      Bs[3 * r + k] = B[3 * r + ord[k]];
-      Vs[3 * r + k] = V[3 * r + ord[k]];
     }
-  }
-  if (perm_sign < 0)
-    for (int r = 0; r < 3; ++r) {
-      Bs[3 * r + 2] = -Bs[3 * r + 2];
-      Vs[3 * r + 2] = -Vs[3 * r + 2];
-    }
-  for (int i = 0; i < 9; ++i) V[i] = Vs[i];
+  };
+  cswap(0, 1);
+  cswap(1, 2);
+  cswap(0, 1);
+  double Bs[9], ns[3];
+  for (int i = 0; i < 9; ++i) Bs[i] = B[i];
+  for (int k = 0; k < 3; ++k) ns[k] = nrm[k];
   double u0[3], u1[3], u2[3];
   if (ns[0] > 0.0) {
     for (int r = 0; r < 3; ++r) u0[r] = Bs[3 * r] / ns[0];
@@ -161,10 +152,9 @@ __device__ inline void svd3(const double* F, double* U, double* s, double* V) {
     for (int r = 0; r < 3; ++r) u1[r] /= n1;
   } else {
     // any unit vector orthogonal to u0
-    double e[3] = {0.0, 0.0, 0.0};
     int m = (fabs(u0[0]) < fabs(u0[1])) ? ((fabs(u0[0]) < fabs(u0[2])) ? 0 : 2)
                                         : ((fabs(u0[1]) < fabs(u0[2])) ? 1 : 2);
-    e[m] = 1.0;
+    double e[3] = {m == 0 ? 1.0 : 0.0, m == 1 ? 1.0 : 0.0, m == 2 ? 1.0 : 0.0};
     double dd = u0[0] * e[0] + u0[1] * e[1] + u0[2] * e[2];
     for (int r = 0; r < 3; ++r) u1[r] = e[r] - dd * u0[r];
     double nn = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);

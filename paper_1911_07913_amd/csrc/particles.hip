@@ -221,8 +221,9 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
   Weights W;
   bspline_weights(fp, s.inv_dx, W);
   double gv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
   for (int k = 0; k < 27; ++k) {
-    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
     int j = L.map[pidx_key + stencil_offset(L.g, k)];
     double g[3];
     node_grad(W, kx, ky, kz, g);
@@ -252,7 +253,7 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
 // Per-particle projected stress derivative at dv = 0, scaled by dt^2 V_p
 // (the particle's contribution to the level-0 Hessian, Alg. HOT
 // projectHessian).  45 upper-triangle entries per particle.
-__global__ void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
+__global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                    const int* __restrict__ key, const double* __restrict__ Fn,
                                    const double* __restrict__ vol, const int* __restrict__ mat,
                                    const double* __restrict__ vstar, double dt,
@@ -269,7 +270,7 @@ __global__ void k_particle_hessian(SceneDev s, LevelView L, int n, const double*
 
 // Energy density and stress at the trial point: psi_out[p] = V_p psi(F_p),
 // S_out[p] = V_p P(F_p) F_p^n^T (the particle's force tensor, Sec. 4.1).
-__global__ void k_particle_eval(SceneDev s, LevelView L, int n, const double* __restrict__ f,
+__global__ __launch_bounds__(256) void k_particle_eval(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                 const int* __restrict__ key, const double* __restrict__ Fn,
                                 const double* __restrict__ vol, const int* __restrict__ mat,
                                 const double* __restrict__ vstar, const double* __restrict__ dv,
@@ -388,7 +389,7 @@ __device__ inline void von_mises(double* F, double mu, double ys) {
 
 // Grid-to-particle APIC transfer, deformation update, lagged plasticity and
 // advection (Sec. 3.1).
-__global__ void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
+__global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                       const int* __restrict__ key, double* __restrict__ x,
                       double* __restrict__ v, double* __restrict__ C, double* __restrict__ Fn,
                       const int* __restrict__ mat, const double* __restrict__ vstar,
@@ -400,8 +401,9 @@ __global__ void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__
   bspline_weights(fp, s.inv_dx, W);
   double vp[3] = {0, 0, 0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int kp = key[p];
+#pragma unroll
   for (int k = 0; k < 27; ++k) {
-    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
     int j = L.map[kp + stencil_offset(L.g, k)];
     double vel[3];
     for (int a = 0; a < 3; ++a) vel[a] = vstar[3 * j + a] + dv[3 * j + a];
@@ -455,6 +457,7 @@ __global__ void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__
 // particle is computed exactly once; no atomics.
 constexpr int kAsmChunk = 8;   // particles staged per pass
 constexpr int kPData = 57;     // f (3), F (9), C (45)
+constexpr int kStageRegs = (kAsmChunk * kPData + 255) / 256;
 
 __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
   double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
@@ -535,8 +538,9 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
   constexpr int kMaxCx = kSegRows + 2;
   __shared__ double win[3][kRowStride];
   __shared__ double pd[kAsmChunk][kPData];
-  __shared__ double av[kAsmChunk][27][3];
-  __shared__ double zv[kAsmChunk][3][27];
+  // a_l padded to 4 and Z rows padded to 12 so both are read with 16-byte loads
+  __shared__ __attribute__((aligned(16))) double av[kAsmChunk][27][4];
+  __shared__ __attribute__((aligned(16))) double zv[kAsmChunk][3][3][12];
   __shared__ double red[12];
   __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
   __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
@@ -570,11 +574,29 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
     rmass[v] = mass[rb + v];
   }
   for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
+  // fixed roles: a phase (particle a_q, node a_l); Z phase items; block phase (r, l, g)
+  const int a_q = (tid < kAsmChunk * 27) ? tid / 27 : kAsmChunk, a_l = tid % 27;
+  const int a_lx = a_l % 3, a_ly = (a_l / 3) % 3, a_lz = a_l / 9;
+  constexpr int kZItems = (kAsmChunk * 81 + 255) / 256;
+  int z_q[kZItems], z_r[kZItems], z_g[kZItems], z_de[kZItems], z_c0[kZItems], z_c1[kZItems],
+      z_c2[kZItems];
+#pragma unroll
+  for (int k = 0; k < kZItems; ++k) {
+    int u = tid + 256 * k;
+    z_q[k] = (u < kAsmChunk * 81) ? u / 81 : kAsmChunk;
+    int rem = u % 81;
+    z_r[k] = rem / 27;
+    int e = rem % 27;
+    z_g[k] = e / 9;
+    z_de[k] = e % 9;
+    z_c0[k] = tri9(3 * z_g[k], z_de[k]);
+    z_c1[k] = tri9(3 * z_g[k] + 1, z_de[k]) - z_c0[k];
+    z_c2[k] = tri9(3 * z_g[k] + 2, z_de[k]) - z_c0[k];
+  }
   const bool blk_thread = tid < 243;
   const int br = tid / 81, bl = (tid / 3) % 27, bg = tid % 3;
   const int blx = bl % 3, bly = (bl / 3) % 3, blz = bl / 9;
   __syncthreads();
-  // job = (cell v = ci*9 + col, chunk start t0); jobs run in sweep order
   auto next_job = [&](int v, int t0, int& nv, int& nt) {
     if (v >= 0 && t0 + kAsmChunk < mcnt[v]) {
       nv = v;
@@ -590,20 +612,32 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
     nv = -1;
     nt = 0;
   };
+  // staging roles: value e = tid + 256k of a chunk is entry w of particle q
+  int sq[kStageRegs], sw[kStageRegs];
+#pragma unroll
+  for (int k = 0; k < kStageRegs; ++k) {
+    int e = tid + 256 * k;
+    sq[k] = e / kPData;
+    sw[k] = e - sq[k] * kPData;
+  }
   auto fetch = [&](int v, int t0, double* r) {
     if (v < 0) return;
-    int np = min(kAsmChunk, mcnt[v] - t0);
-    long long st = mst[v] + t0;
-    for (int k = 0; k < 2; ++k) {
-      int e = tid + 256 * k;
-      if (e < np * kPData) {
-        int q = e / kPData, w = e - q * kPData;
-        long long pp = st + q;
-        r[k] = (w < 3) ? f[3 * pp + w] : ((w < 12) ? Fn[9 * pp + (w - 3)] : Cp[45 * pp + (w - 12)]);
+    const int np = min(kAsmChunk, mcnt[v] - t0);
+    const long long st = mst[v] + t0;
+#pragma unroll
+    for (int k = 0; k < kStageRegs; ++k) {
+      if (sq[k] < np) {
+        const long long pp = st + sq[k];
+        const int w = sw[k];
+        const double* src = (w < 3) ? (f + 3 * pp + w)
+                                    : ((w < 12) ? (Fn + 9 * pp + (w - 3)) : (Cp + 45 * pp + (w - 12)));
+        r[k] = *src;
       }
     }
   };
-  double regs[2] = {0.0, 0.0};
+  double regs[kStageRegs];
+#pragma unroll
+  for (int k = 0; k < kStageRegs; ++k) regs[k] = 0.0;
   int jv, jt;
   next_job(-1, 0, jv, jt);
   fetch(jv, jt, regs);
@@ -611,6 +645,7 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
   for (int ci = 0; ci < ncx; ++ci) {
     const int c = xa - 2 + ci;
     const int rlo = max(0, xa - c), rhi = min(2, xb - c);
+    const bool blk_active = blk_thread && br >= rlo && br <= rhi;
     for (int col = 0; col < 9; ++col) {
       const int v = ci * 9 + col;
       const int cnt = mcnt[v];
@@ -619,52 +654,53 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
       double acc3[3] = {0.0, 0.0, 0.0};
       for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
         const int np = min(kAsmChunk, cnt - t0);
-        for (int k = 0; k < 2; ++k) {
-          int e = tid + 256 * k;
-          if (e < np * kPData) {
-            int q = e / kPData;
-            pd[q][e - q * kPData] = regs[k];
-          }
-        }
+#pragma unroll
+        for (int k = 0; k < kStageRegs; ++k)
+          if (sq[k] < np) pd[sq[k]][sw[k]] = regs[k];
         __syncthreads();
         // prefetch the next chunk while this one is processed
         int nv, nt;
         next_job(v, t0, nv, nt);
         fetch(nv, nt, regs);
-        for (int u = tid; u < np * 27; u += 256) {
-          int q = u / 27, l = u - 27 * q;
-          int lx = l % 3, ly = (l / 3) % 3, lz = l / 9;
+        // a_l = F^T grad w_l for the 27 stencil nodes of each staged particle
+        if (a_q < np) {
           double w0, d0, w1, d1, w2, d2;
-          wdw(lx, pd[q][0], s.inv_dx, w0, d0);
-          wdw(ly, pd[q][1], s.inv_dx, w1, d1);
-          wdw(lz, pd[q][2], s.inv_dx, w2, d2);
+          wdw(a_lx, pd[a_q][0], s.inv_dx, w0, d0);
+          wdw(a_ly, pd[a_q][1], s.inv_dx, w1, d1);
+          wdw(a_lz, pd[a_q][2], s.inv_dx, w2, d2);
           double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
-          const double* F = &pd[q][3];
-          for (int b = 0; b < 3; ++b) av[q][l][b] = F[b] * gx + F[3 + b] * gy + F[6 + b] * gz;
+          const double* F = &pd[a_q][3];
+          double* o = av[a_q][a_l];
+          o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
+          o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
+          o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
         }
         __syncthreads();
-        for (int u = tid; u < np * 81; u += 256) {
-          int q = u / 81, rr = (u / 27) % 3, e = u % 27;
-          if (rr < rlo || rr > rhi) continue;
-          int gm = e / 9, de = e % 9;
-          const double* a = av[q][rr + 3 * ky + 9 * kz];
-          const double* Cq = &pd[q][12];
-          zv[q][rr][e] = a[0] * Cq[tri9(3 * gm, de)] + a[1] * Cq[tri9(3 * gm + 1, de)] +
-                         a[2] * Cq[tri9(3 * gm + 2, de)];
+        // Z_r[gamma][delta eps] = sum_beta a_k,beta C[3 gamma + beta][3 delta + eps], k = (r, ky, kz)
+#pragma unroll
+        for (int k = 0; k < kZItems; ++k) {
+          if (z_q[k] < np && z_r[k] >= rlo && z_r[k] <= rhi) {
+            const double* a = av[z_q[k]][z_r[k] + 3 * ky + 9 * kz];
+            const double* Cq = &pd[z_q[k]][12];
+            zv[z_q[k]][z_r[k]][z_g[k]][z_de[k]] =
+                a[0] * Cq[z_c0[k]] + a[1] * Cq[z_c0[k] + z_c1[k]] + a[2] * Cq[z_c0[k] + z_c2[k]];
+          }
         }
         __syncthreads();
-        if (blk_thread && br >= rlo && br <= rhi) {
+        if (blk_active) {
           for (int q = 0; q < np; ++q) {
-            const double* z = &zv[q][br][9 * bg];
-            const double* al = av[q][bl];
-            double a0 = al[0], a1 = al[1], a2 = al[2];
-            acc3[0] += z[0] * a0 + z[1] * a1 + z[2] * a2;
-            acc3[1] += z[3] * a0 + z[4] * a1 + z[5] * a2;
-            acc3[2] += z[6] * a0 + z[7] * a1 + z[8] * a2;
+            const double2* z2 = reinterpret_cast<const double2*>(&zv[q][br][bg][0]);
+            const double2* a2 = reinterpret_cast<const double2*>(&av[q][bl][0]);
+            double2 z01 = z2[0], z23 = z2[1], z45 = z2[2], z67 = z2[3], z89 = z2[4];
+            double2 a01 = a2[0], a2x = a2[1];
+            double al0 = a01.x, al1 = a01.y, al2 = a2x.x;
+            acc3[0] += z01.x * al0 + z01.y * al1 + z23.x * al2;
+            acc3[1] += z23.y * al0 + z45.x * al1 + z45.y * al2;
+            acc3[2] += z67.x * al0 + z67.y * al1 + z89.x * al2;
           }
         }
       }
-      if (blk_thread && br >= rlo && br <= rhi) {
+      if (blk_active) {
         int sl = (blx - br + 2) + 5 * (bly - ky + 2) + 25 * (blz - kz + 2);
         double* wrow = win[(c + br + 3) % 3] + (3 * bg) * kSlotPad + sl;
         wrow[0] += acc3[0];
