@@ -96,6 +96,45 @@ def run(precision, steps, warmup, side, profile=True):
     return dict(seconds=t1 - t0, stats=stats, prof=prof, n=n)
 
 
+class ServingRequests:
+    """The serving request stream, generated on demand (host memory holds only
+    requests not yet admitted)."""
+
+    def __init__(self, n, seed_base=4000):
+        self.n, self.seed_base, self.cache = n, seed_base, {}
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, k):
+        import hot_scenes as hs
+        if k not in self.cache:
+            self.cache[k] = hs.serving_scene(k, seed_base=self.seed_base)
+        return self.cache[k]
+
+    def release(self, k):
+        self.cache.pop(k, None)
+
+
+def run_serving(n_req, slots, budget_gb, precision, load=0.7, n_sat=64):
+    """Closed-loop run of the first n_sat requests for the saturated step
+    rate, then the whole stream with Poisson arrivals at ``load`` times it."""
+    from paper_1911_07913_amd import serving
+    budget = int(budget_gb * (1 << 30))
+    n_sat = min(n_sat, n_req)
+    _, sat, _ = serving.serve(ServingRequests(n_sat), [0.0] * n_sat, budget, slots, precision)
+    steps_per_req = 10
+    rate = load * sat["steps_per_s"] / steps_per_req
+    arrivals = serving.poisson_arrivals(n_req, rate, seed=4000)
+    records, summary, trace = serving.serve(ServingRequests(n_req), arrivals, budget, slots,
+                                            precision)
+    summary.update(precision="fp64" if precision == 0 else "mixed", slots=slots,
+                   budget_gb=budget_gb, load=load, arrival_rate_req_per_s=rate,
+                   saturated_steps_per_s=sat["steps_per_s"],
+                   saturated_step_latency_ms=sat["step_latency_ms"], **trace)
+    return summary
+
+
 def roofline_of(prof):
     # the dominant traced kernel by total time
     name, (ms, launches, nbytes) = max(prof.items(), key=lambda kv: kv[1][0])
@@ -116,6 +155,10 @@ def main():
     ap.add_argument("--side", type=int, default=16, help="bar cross-section (16: 1.5M particles)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-slots", type=int, default=12)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serving-precision", default="mixed", choices=["fp64", "mixed", "both"])
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -179,6 +222,14 @@ def main():
                          "ms_per_step": 1000.0 * rm["seconds"] / a.steps,
                          "iters": [s["iters"] for s in rm["stats"]],
                          "roofline": roofline_of(rm["prof"])}
+    if a.serving_requests > 0:
+        sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
+              "both": [hot.HOT_MIXED, hot.HOT_FP64]}[a.serving_precision]
+        line["serving"] = run_serving(a.serving_requests, a.serving_slots, a.serving_budget_gb,
+                                      sp[0])
+        if len(sp) > 1:
+            line["serving_fp64"] = run_serving(a.serving_requests, a.serving_slots,
+                                               a.serving_budget_gb, sp[1])
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["n"])
     print(json.dumps(line), flush=True)

@@ -167,19 +167,46 @@ hot_status hot_scene_info(const hot_scene* scene, int64_t* n, double* t);
 void hot_destroy_scene(hot_scene* scene);
 const char* hot_last_error(void);
 
+/* Device bytes the scene holds now and the working-size estimate made at
+ * init (the hot_scene_footprint figure). */
+hot_status hot_scene_memory(const hot_scene* scene, size_t* live_bytes, size_t* estimate_bytes);
+
 /* ---- serving: continuous batching of independent scenes ------------------
- * A batch owns an HBM budget and a set of slots.  Scenes join with a number
- * of steps to run (HOT_E_NOMEM when their footprint does not fit now: defer
- * and retry).  Each hot_batch_round advances every resident scene by one
- * step, issuing the scenes' work back to back on the batch's stream so the
- * device overlaps their small kernels; scenes that have finished their steps
- * leave the batch and their tags are reported.  A scene's arithmetic does not
- * depend on what else is resident. */
+ * Steps of many independent scenes (the paper's per-frame solve applied to
+ * a stream of requests) share one GPU.  A batch owns an HBM budget and
+ * max_slots slots, each served by one host thread.  hot_batch_add admits a
+ * scene with a number of steps to run when a slot is free and the larger of
+ * the scene's live bytes and its footprint estimate fits in the budget that
+ * resident scenes leave; otherwise it returns HOT_E_NOMEM and the caller
+ * defers the request.  An admitted scene starts at once and runs its steps
+ * back to back (dt from the CFL rule) on its own stream from its slot's
+ * thread, so the device interleaves the kernels of all resident scenes.  A
+ * scene's arithmetic does not depend on what else is resident.
+ * A scene's slot is free again as soon as its last step ends; its budget
+ * stays reserved until hot_batch_poll hands it out (all steps done, or
+ * stopped by an error; waiting up to wait_ms for one), since its device
+ * memory lives until the caller, who still owns each hot_scene, destroys it.  While a scene is
+ * resident the caller must not use it.  Times are seconds on a steady clock
+ * started by hot_batch_create.  hot_batch_destroy lets each resident scene
+ * finish its current step, then stops the slot threads. */
+#define HOT_BATCH_MAX_STEPS 64
+typedef struct {
+  int64_t tag;
+  int32_t status;     /* worst step status (HOT_OK, a warning, or the error that stopped it) */
+  int32_t steps;      /* steps completed */
+  int32_t iters;      /* quasi-Newton iterations summed over the steps */
+  int32_t reserved;
+  double t_admit;     /* admission time */
+  double t_step_end[HOT_BATCH_MAX_STEPS]; /* completion time of each of the first 64 steps */
+  char message[160];  /* error text when status < 0 */
+} hot_batch_result;
 typedef struct hot_batch hot_batch;
 hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out);
+hot_status hot_batch_capacity(hot_batch* batch, size_t* free_bytes, int32_t* free_slots);
 hot_status hot_batch_add(hot_batch* batch, hot_scene* scene, int32_t n_steps, int64_t tag);
-hot_status hot_batch_round(hot_batch* batch, int64_t* done_tags, int32_t* n_done, int32_t cap,
-                           int32_t* n_resident);
+hot_status hot_batch_poll(hot_batch* batch, hot_batch_result* results, int32_t cap,
+                          int32_t* n_done, int32_t* n_resident, int32_t wait_ms);
+double hot_batch_clock(const hot_batch* batch);
 void hot_batch_destroy(hot_batch* batch);
 
 /* ---- tracing: HIP-event timing of individual kernels ---------------------
@@ -211,6 +238,8 @@ enum {
                                 structurally present (s = dx+2 + 5(dy+2) + 25(dz+2)) */
   HOT_DBG_LEVEL_MATRIX = 12,  /* double [n_m][125][3][3] block rows (FP64 copy) */
   HOT_DBG_LEVEL_FREE = 13,    /* uint8 [n_m][3]: 1 = free DOF, 0 = constrained */
+  HOT_DBG_LEVEL_MATRIX_BF16 = 14, /* uint16 [n_m][125][3][3] BF16 bit patterns of the
+                                 blocks the mixed V-cycle reads (HOT_MIXED only) */
   HOT_DBG_NODE_MASS = 20,     /* double [n_0] */
   HOT_DBG_NODE_VSTAR = 21,    /* double [n_0][3]: v after gravity and BCs */
   HOT_DBG_NODE_XI = 22,       /* double [n_0]: CN stiffness field */

@@ -5,6 +5,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -95,6 +99,8 @@ struct hot_scene {
   std::vector<hot_bc> bcs;
   double bc_speed = 0.0;
   size_t bytes_live = 0;
+  size_t est_bytes = 0;  // footprint estimate at init (admission)
+  int device = 0;
   std::vector<DBuf*> owned;
   bool mixed = false;
   int levels = 1;
@@ -296,41 +302,114 @@ hot_status validate_positions(const hot_params* p, int64_t n, const double* x) {
   return HOT_OK;
 }
 
-// Active fine nodes of a particle set, counted on the host (footprint).
-long long count_active_nodes(const hot_params* p, int64_t n, const double* x) {
-  long long nx = p->grid_cells[0] + 1, ny = p->grid_cells[1] + 1, nz = p->grid_cells[2] + 1;
-  std::vector<uint8_t> mark((size_t)(nx * ny * nz), 0);
-  long long cnt = 0;
+// Node counts of every level and the number of occupied cell bricks for a
+// particle set, counted on the host (footprint estimate).  Level m+1 holds the
+// parents of level m's nodes: even index i -> i/2, odd i -> (i-1)/2, (i+1)/2.
+struct SetCounts {
+  long long nodes[kMaxLevels] = {0};
+  long long bricks = 0;
+};
+
+SetCounts count_sets(const hot_params* p, int64_t n, const double* x) {
+  SetCounts c;
+  int dims[3] = {p->grid_cells[0] + 1, p->grid_cells[1] + 1, p->grid_cells[2] + 1};
+  std::vector<uint8_t> mark((size_t)dims[0] * dims[1] * dims[2], 0);
+  int bd[3];
+  for (int a = 0; a < 3; ++a) bd[a] = (dims[a] + 4 + kBrick - 1) / kBrick;
+  std::vector<uint8_t> bmark((size_t)bd[0] * bd[1] * bd[2], 0);
   for (int64_t i = 0; i < n; ++i) {
     long long b[3];
     for (int a = 0; a < 3; ++a) {
       double t = (x[3 * i + a] - p->origin[a]) / p->dx;
-      b[a] = (long long)std::floor(t - 0.5);
-      if (b[a] < 0) b[a] = 0;
+      b[a] = std::min(std::max((long long)std::floor(t - 0.5), 0LL), (long long)dims[a] - 3);
+    }
+    size_t bi = (size_t)((b[0] + 2) / kBrick + bd[0] * ((b[1] + 2) / kBrick + bd[1] * ((b[2] + 2) / kBrick)));
+    if (!bmark[bi]) {
+      bmark[bi] = 1;
+      ++c.bricks;
     }
     for (int k = 0; k < 27; ++k) {
-      long long X = std::min(b[0] + k % 3, nx - 1), Y = std::min(b[1] + (k / 3) % 3, ny - 1),
-                Z = std::min(b[2] + k / 9, nz - 1);
-      size_t id = (size_t)(X + nx * (Y + ny * Z));
+      size_t id = (size_t)(b[0] + k % 3 + dims[0] * (b[1] + (k / 3) % 3 + (size_t)dims[1] * (b[2] + k / 9)));
       if (!mark[id]) {
         mark[id] = 1;
-        ++cnt;
+        ++c.nodes[0];
       }
     }
   }
-  return cnt;
+  for (int m = 1; m < p->mg_levels; ++m) {
+    int cd[3] = {dims[0] / 2 + 1, dims[1] / 2 + 1, dims[2] / 2 + 1};
+    std::vector<uint8_t> cm((size_t)cd[0] * cd[1] * cd[2], 0);
+    for (int z = 0; z < dims[2]; ++z)
+      for (int y = 0; y < dims[1]; ++y)
+        for (int xx = 0; xx < dims[0]; ++xx) {
+          if (!mark[(size_t)xx + dims[0] * ((size_t)y + (size_t)dims[1] * z)]) continue;
+          int lo[3] = {xx / 2, y / 2, z / 2};
+          int hi[3] = {(xx + 1) / 2, (y + 1) / 2, (z + 1) / 2};
+          for (int Z = lo[2]; Z <= hi[2]; ++Z)
+            for (int Y = lo[1]; Y <= hi[1]; ++Y)
+              for (int X = lo[0]; X <= hi[0]; ++X) {
+                size_t id = (size_t)X + cd[0] * ((size_t)Y + (size_t)cd[1] * Z);
+                if (!cm[id]) {
+                  cm[id] = 1;
+                  ++c.nodes[m];
+                }
+              }
+        }
+    mark.swap(cm);
+    for (int a = 0; a < 3; ++a) dims[a] = cd[a];
+  }
+  return c;
 }
 
-size_t estimate_bytes(const hot_params* p, int64_t n, long long nodes) {
-  long long g0 = (long long)(p->grid_cells[0] + 5) * (p->grid_cells[1] + 5) * (p->grid_cells[2] + 5);
-  size_t per_particle = 8 * (2 * 25 + 3 + 45 + 2 + 18) + 4 * 6;
-  size_t w = (size_t)p->lbfgs_history + 1;
-  size_t per_node = 9000 + 72 + 24 + 3 + 16 + 8 * 3 * (10 + 2 * w) + 4 * 3 * 4 * 2 + 40;
-  if (p->precision == HOT_MIXED) per_node += 2250 + 36 + 12;
-  double lev = 1.0 + 1.0 / 8 + 1.0 / 64 + 1.0 / 512;
-  size_t bytes = (size_t)n * per_particle + (size_t)(g0 * 4 * 8 * 1.2) +
-                 (size_t)(nodes * 1.3 * per_node * lev) + (1 << 20);
-  return bytes;
+// Device bytes a scene allocates for a particle set of this shape: every
+// buffer the step uses, with the 25% growth headroom each allocation takes.
+// Exact for the initial configuration; a scene whose active grid grows later
+// allocates more.
+size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
+  double tot = 0.0;
+  auto A = [&](double bytes) { tot += std::max(bytes, 8.0) * 1.25; };
+  const double N = (double)n;
+  // particle state (two sets), per-particle work arrays, keys
+  A(N * 208); A(N * 208);
+  A(N * 24); A(N * 360); A(N * 8); A(N * 8); A(N * 72); A(N * 72);
+  A(N * 4); A(N * 4); A(N * 4);
+  // dense maps over the padded level grids, bricks, reductions
+  int dims[3] = {p->grid_cells[0] + 1, p->grid_cells[1] + 1, p->grid_cells[2] + 1};
+  GridGeom g0 = make_geom(dims[0], dims[1], dims[2]);
+  double pt = (double)g0.ptotal;
+  A(pt * 4); A(pt * 4 + 4); A(pt * 4); A(pt * 4); A(pt * 4 + 4); A((pt / 2048 + 2) * 4); A(64);
+  GridGeom gm = g0;
+  for (int m = 0; m < p->mg_levels; ++m) {
+    if (m > 0) gm = make_geom(gm.dims[0] / 2 + 1, gm.dims[1] / 2 + 1, gm.dims[2] / 2 + 1);
+    A((double)gm.ptotal * 4);
+  }
+  double nbt = 1.0;
+  for (int a = 0; a < 3; ++a) nbt *= (double)((g0.pd[a] + kBrick - 1) / kBrick);
+  A(nbt * 4);
+  const double W = p->lbfgs_history + 1;
+  for (int k = 0; k < 4; ++k) A(W * 8);
+  A(NSCAL * 8); A(kRedBlocks * 3 * 8);  // scalars, partials
+  A((double)(sizeof(MaterialDev) * kMaxMats + sizeof(BcDev) * kMaxBcs));  // tables
+  A((double)c.bricks * 4); A((double)c.bricks * kBrickWin * 5 * 8);
+  // levels
+  const bool mx = p->precision == HOT_MIXED;
+  const double vsz = mx ? 4 : 8;
+  for (int m = 0; m < p->mg_levels; ++m) {
+    double nm = (double)c.nodes[m];
+    A(nm * 4); A(nm * kRowStride * 8); A(nm * 72); A(nm * 24); A(nm * 3); A(nm * 16);
+    if (mx) { A(nm * kRowStride * 2); A(nm * 36); A(nm * 12); }
+    for (int k = 0; k < 4; ++k) A(nm * 3 * vsz);
+  }
+  // level-0 node data, solver vectors and history, row segments
+  const double n0 = (double)c.nodes[0];
+  A(n0 * 8); A(n0 * 8); A(n0 * 4);
+  for (int k = 0; k < 9; ++k) A(n0 * 24);
+  for (int k = 0; k < 2 * W; ++k) A(n0 * 24);
+  A((n0 + 1) * 4);
+  double nc = (double)c.nodes[p->mg_levels - 1];
+  A(4 * 3 * nc * 8);
+  A((p->max_iters * 3 + 16) * 4.0);
+  return (size_t)tot + ((size_t)1 << 16);
 }
 
 // ---------------------------------------------------------------- prepare
@@ -863,8 +942,7 @@ hot_status hot_scene_footprint(const hot_params* params, int64_t n, const double
                                size_t* bytes_out) {
   TRY(validate_params(params));
   if (n <= 0 || !x || !bytes_out) return fail(HOT_E_INVALID, "bad arguments");
-  long long nodes = count_active_nodes(params, n, x);
-  *bytes_out = estimate_bytes(params, n, nodes);
+  *bytes_out = estimate_bytes(params, n, count_sets(params, n, x));
   return HOT_OK;
 }
 
@@ -920,6 +998,11 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
 
   hot_scene* s = new hot_scene();
   s->prm = *params;
+  s->est_bytes = estimate_bytes(params, n, count_sets(params, n, x));
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(HOT_E_DEVICE, "no current HIP device");
+  }
   for (int k = 0; k < 5; ++k) s->ev[k] = nullptr;
   if (alloc && alloc->alloc && alloc->free) {
     s->alloc = *alloc;
@@ -1064,6 +1147,7 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
 hot_status hot_step(hot_scene* scene, double dt, hot_step_stats* stats) {
   if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
   if (!std::isfinite(dt)) return fail(HOT_E_INVALID, "dt must be finite");
+  HIPCHK(hipSetDevice(scene->device));
   return do_step(scene, dt, stats);
 }
 
@@ -1096,6 +1180,13 @@ hot_status hot_scene_info(const hot_scene* scene, int64_t* n, double* t) {
   if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
   if (n) *n = scene->n;
   if (t) *t = scene->t;
+  return HOT_OK;
+}
+
+hot_status hot_scene_memory(const hot_scene* scene, size_t* live_bytes, size_t* estimate_bytes) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (live_bytes) *live_bytes = scene->bytes_live;
+  if (estimate_bytes) *estimate_bytes = scene->est_bytes;
   return HOT_OK;
 }
 
@@ -1182,6 +1273,11 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
     case HOT_DBG_LEVEL_NODES: src = L.nodes.p; sz = (size_t)L.n * 4; break;
     case HOT_DBG_LEVEL_PATTERN: src = L.pat.p; sz = (size_t)L.n * 16; break;
     case HOT_DBG_LEVEL_MATRIX: src = L.H.p; sz = (size_t)L.n * kRowVals * 8; break;  // reordered below
+    case HOT_DBG_LEVEL_MATRIX_BF16:
+      if (!s->mixed) return fail(HOT_E_INVALID, "BF16 blocks exist only under HOT_MIXED");
+      src = L.Hb.p;
+      sz = (size_t)L.n * kRowVals * 2;
+      break;
     case HOT_DBG_LEVEL_FREE: src = L.freed.p; sz = (size_t)L.n * 3; break;
     case HOT_DBG_NODE_MASS: src = s->mass.p; sz = (size_t)s->L[0].n * 8; break;
     case HOT_DBG_NODE_VSTAR: src = s->vstar.p; sz = (size_t)s->L[0].n * 24; break;
@@ -1223,6 +1319,17 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
           o[(size_t)i * kRowVals + sl * 9 + c] = tmpv[(size_t)i * kRowStride + c * kSlotPad + sl];
     return HOT_OK;
   }
+  if (what == HOT_DBG_LEVEL_MATRIX_BF16) {
+    std::vector<uint16_t> tmpv((size_t)L.n * kRowStride);
+    HIPCHK(hipMemcpyAsync(tmpv.data(), src, tmpv.size() * 2, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    uint16_t* o = (uint16_t*)dst;
+    for (int i = 0; i < L.n; ++i)
+      for (int sl = 0; sl < kSlots; ++sl)
+        for (int c = 0; c < 9; ++c)
+          o[(size_t)i * kRowVals + sl * 9 + c] = tmpv[(size_t)i * kRowStride + c * kSlotPad + sl];
+    return HOT_OK;
+  }
   if (what == HOT_DBG_LEVEL_NODES) {
     // convert padded indices to plain linear indices of the level's node grid
     std::vector<int> tmpv(L.n);
@@ -1244,82 +1351,161 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
 // ---------------------------------------------------------------- serving
 }  // extern "C"
 
+// A batch is a fixed pool of slots, each served by one host thread.  An
+// admitted scene runs all its steps on its own stream from its slot's thread,
+// so the device interleaves the kernels of every resident scene; the batch
+// only does admission (HBM budget, free slot) and completion bookkeeping.
 struct hot_batch {
-  size_t budget = 0;
-  int max_slots = 0;
-  size_t used = 0;
-  struct Slot {
-    hot_scene* scene;
-    int steps_left;
-    int64_t tag;
-    size_t bytes;
+  using clock = std::chrono::steady_clock;
+  struct Job {
+    hot_scene* scene = nullptr;
+    int steps = 0;
+    int64_t tag = 0;
+    size_t bytes = 0;
+    double t_admit = 0.0;
   };
-  std::vector<Slot> slots;
+  size_t budget = 0;
+  size_t used = 0;
+  int resident = 0;
+  bool stop = false;
+  clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<Job> jobs;       // per slot; scene == nullptr when free
+  // finished scenes keep their budget until the caller collects them: their
+  // device memory is still live until then
+  std::deque<std::pair<hot_batch_result, size_t>> done;
+  std::vector<std::thread> workers;
+
+  double now() const { return std::chrono::duration<double>(clock::now() - t0).count(); }
+
+  void serve(int k) {
+    for (;;) {
+      Job job;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || jobs[k].scene != nullptr; });
+        if (stop) return;
+        job = jobs[k];
+      }
+      hot_batch_result r;
+      std::memset(&r, 0, sizeof(r));
+      r.tag = job.tag;
+      r.t_admit = job.t_admit;
+      for (int i = 0; i < job.steps; ++i) {
+        hot_step_stats st;
+        hot_status rc = hot_step(job.scene, 0.0, &st);
+        double t = now();
+        if (i < HOT_BATCH_MAX_STEPS) r.t_step_end[i] = t;
+        if (rc < 0) {
+          r.status = rc;
+          std::snprintf(r.message, sizeof(r.message), "%s", g_err.c_str());
+          break;
+        }
+        if (rc > r.status) r.status = rc;
+        r.steps += 1;
+        r.iters += st.iters;
+        bool halt;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          halt = stop;
+        }
+        if (halt) break;
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        done.emplace_back(r, job.bytes);
+        resident -= 1;
+        jobs[k] = Job();
+      }
+      cv_done.notify_all();
+    }
+  }
 };
 
 extern "C" {
 
 hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out) {
-  if (!out || max_slots < 1 || hbm_budget_bytes == 0) return fail(HOT_E_INVALID, "bad arguments");
+  if (!out || max_slots < 1 || max_slots > 256 || hbm_budget_bytes == 0)
+    return fail(HOT_E_INVALID, "bad arguments");
   hot_batch* b = new hot_batch();
   b->budget = hbm_budget_bytes;
-  b->max_slots = max_slots;
+  b->t0 = hot_batch::clock::now();
+  b->jobs.resize(max_slots);
+  try {
+    for (int k = 0; k < max_slots; ++k) b->workers.emplace_back([b, k] { b->serve(k); });
+  } catch (...) {
+    hot_batch_destroy(b);
+    return fail(HOT_E_NOMEM, "could not start slot threads");
+  }
   *out = b;
+  return HOT_OK;
+}
+
+hot_status hot_batch_capacity(hot_batch* b, size_t* free_bytes, int32_t* free_slots) {
+  if (!b) return fail(HOT_E_INVALID, "batch is NULL");
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (free_bytes) *free_bytes = b->budget - b->used;
+  if (free_slots) *free_slots = (int32_t)b->jobs.size() - b->resident;
   return HOT_OK;
 }
 
 hot_status hot_batch_add(hot_batch* b, hot_scene* s, int32_t n_steps, int64_t tag) {
   if (!b || !s || n_steps < 1) return fail(HOT_E_INVALID, "bad arguments");
-  size_t need = std::max(s->bytes_live, (size_t)1);
-  // a scene's buffers grow to their working size on its first step; reserve
-  // room for the larger of what it holds and its estimate
-  if ((int)b->slots.size() >= b->max_slots || b->used + need > b->budget)
-    return fail(HOT_E_NOMEM, "batch full: %zu + %zu > %zu bytes or no free slot", b->used, need,
-                b->budget);
-  b->slots.push_back({s, n_steps, tag, need});
-  b->used += need;
+  // reserve the larger of what the scene holds and its working-size estimate
+  size_t need = std::max(std::max(s->bytes_live, s->est_bytes), (size_t)1);
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    for (const hot_batch::Job& j : b->jobs)
+      if (j.scene == s) return fail(HOT_E_BUSY, "scene is already resident");
+    if (b->resident >= (int)b->jobs.size() || b->used + need > b->budget)
+      return fail(HOT_E_NOMEM, "batch full: %zu + %zu > %zu bytes or no free slot", b->used,
+                  need, b->budget);
+    int k = 0;
+    while (b->jobs[k].scene) ++k;
+    hot_batch::Job& j = b->jobs[k];
+    j.scene = s;
+    j.steps = n_steps;
+    j.tag = tag;
+    j.bytes = need;
+    j.t_admit = b->now();
+    b->used += need;
+    b->resident += 1;
+  }
+  b->cv_work.notify_all();
   return HOT_OK;
 }
 
-hot_status hot_batch_round(hot_batch* b, int64_t* done_tags, int32_t* n_done, int32_t cap,
-                           int32_t* n_resident) {
-  if (!b || !n_done) return fail(HOT_E_INVALID, "bad arguments");
-  *n_done = 0;
-  size_t ns = b->slots.size();
-  std::vector<hot_status> rc(ns, HOT_OK);
-  std::vector<std::string> errs(ns);
-  // every resident scene runs one step; each scene drives its own stream from
-  // its own host thread so the device overlaps the scenes' kernels
-  std::vector<std::thread> th;
-  th.reserve(ns);
-  for (size_t k = 0; k < ns; ++k)
-    th.emplace_back([&, k]() {
-      rc[k] = hot_step(b->slots[k].scene, 0.0, nullptr);
-      if (rc[k] < 0) errs[k] = g_err;
-    });
-  for (auto& t : th) t.join();
-  hot_status worst = HOT_OK;
-  std::vector<hot_batch::Slot> keep;
-  for (size_t k = 0; k < ns; ++k) {
-    hot_batch::Slot sl = b->slots[k];
-    if (rc[k] < 0) {
-      worst = rc[k];
-      g_err = errs[k];
-    }
-    sl.steps_left -= 1;
-    if (sl.steps_left <= 0 || rc[k] < 0) {
-      if (*n_done < cap && done_tags) done_tags[*n_done] = sl.tag;
-      (*n_done)++;
-      b->used -= sl.bytes;
-    } else {
-      keep.push_back(sl);
-    }
+hot_status hot_batch_poll(hot_batch* b, hot_batch_result* results, int32_t cap, int32_t* n_done,
+                          int32_t* n_resident, int32_t wait_ms) {
+  if (!b || !n_done || cap < 0 || (cap > 0 && !results)) return fail(HOT_E_INVALID, "bad arguments");
+  std::unique_lock<std::mutex> lk(b->mu);
+  if (b->done.empty() && b->resident > 0 && wait_ms > 0)
+    b->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms),
+                        [&] { return !b->done.empty() || b->resident == 0; });
+  int k = 0;
+  while (k < cap && !b->done.empty()) {
+    results[k++] = b->done.front().first;
+    b->used -= b->done.front().second;
+    b->done.pop_front();
   }
-  b->slots.swap(keep);
-  if (n_resident) *n_resident = (int32_t)b->slots.size();
-  return worst;
+  *n_done = k;
+  if (n_resident) *n_resident = b->resident;
+  return HOT_OK;
 }
 
-void hot_batch_destroy(hot_batch* b) { delete b; }
+double hot_batch_clock(const hot_batch* b) { return b ? b->now() : 0.0; }
+
+void hot_batch_destroy(hot_batch* b) {
+  if (!b) return;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->stop = true;
+  }
+  b->cv_work.notify_all();
+  for (std::thread& t : b->workers)
+    if (t.joinable()) t.join();
+  delete b;
+}
 
 }  // extern "C"

@@ -28,6 +28,7 @@ DBG_LEVEL_NODES = 10
 DBG_LEVEL_PATTERN = 11
 DBG_LEVEL_MATRIX = 12
 DBG_LEVEL_FREE = 13
+DBG_LEVEL_MATRIX_BF16 = 14
 DBG_NODE_MASS = 20
 DBG_NODE_VSTAR = 21
 DBG_NODE_XI = 22
@@ -38,9 +39,12 @@ DBG_LOG_CN = 41
 DBG_COUNTS = 50
 
 EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_particles",
-           "hot_scene_info", "hot_destroy_scene", "hot_last_error", "hot_batch_create",
-           "hot_batch_add", "hot_batch_round", "hot_batch_destroy", "hot_debug_read",
-           "hot_debug_prepare", "hot_debug_apply", "hot_profile_enable", "hot_profile_read"]
+           "hot_scene_info", "hot_scene_memory", "hot_destroy_scene", "hot_last_error",
+           "hot_batch_create", "hot_batch_capacity", "hot_batch_add", "hot_batch_poll",
+           "hot_batch_clock", "hot_batch_destroy", "hot_debug_read", "hot_debug_prepare",
+           "hot_debug_apply", "hot_profile_enable", "hot_profile_read"]
+
+BATCH_MAX_STEPS = 64
 
 PROF_KERNELS = {0: "smooth0", 1: "residual0", 2: "assemble_h0", 3: "rap0", 4: "particle_eval",
                 5: "gradient", 6: "particle_hessian"}
@@ -53,6 +57,12 @@ class hot_material(C.Structure):
 
 class hot_bc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("p", C.c_double * 16)]
+
+
+class hot_batch_result(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("steps", C.c_int32),
+                ("iters", C.c_int32), ("reserved", C.c_int32), ("t_admit", C.c_double),
+                ("t_step_end", C.c_double * BATCH_MAX_STEPS), ("message", C.c_char * 160)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -112,10 +122,14 @@ def lib():
     L.hot_destroy_scene.argtypes = [vp]
     L.hot_destroy_scene.restype = None
     L.hot_last_error.restype = C.c_char_p
+    L.hot_scene_memory.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     L.hot_batch_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(vp)]
+    L.hot_batch_capacity.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]
     L.hot_batch_add.argtypes = [vp, vp, C.c_int32, C.c_int64]
-    L.hot_batch_round.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
-                                  C.POINTER(C.c_int32)]
+    L.hot_batch_poll.argtypes = [vp, C.POINTER(hot_batch_result), C.c_int32,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
+    L.hot_batch_clock.argtypes = [vp]
+    L.hot_batch_clock.restype = C.c_double
     L.hot_batch_destroy.argtypes = [vp]
     L.hot_batch_destroy.restype = None
     L.hot_debug_read.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
@@ -125,7 +139,8 @@ def lib():
     L.hot_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("hot_destroy_scene", "hot_batch_destroy", "hot_last_error"):
+        if name not in ("hot_destroy_scene", "hot_batch_destroy", "hot_last_error",
+                        "hot_batch_clock"):
             f.restype = C.c_int32
     _lib = L
     return L
@@ -266,6 +281,13 @@ class Scene:
         _check(lib().hot_read_particles(self.handle, n, _dp(x), _dp(v), _dp(Fa), _dp(Ca)))
         return dict(x=x, v=v, F=Fa, C=Ca)
 
+    def memory(self):
+        """(device bytes held now, footprint estimate made at init)"""
+        live = C.c_size_t()
+        est = C.c_size_t()
+        _check(lib().hot_scene_memory(self.handle, C.byref(live), C.byref(est)))
+        return live.value, est.value
+
     def info(self):
         n = C.c_int64()
         t = C.c_double()
@@ -324,26 +346,46 @@ def footprint(params, x):
 
 
 class Batch:
-    """Continuous batching of independent scenes (hot_batch_*)."""
+    """Continuous batching of independent scenes (hot_batch_*): admission by
+    HBM footprint, one host thread per slot, per-step completion times."""
 
     def __init__(self, budget_bytes, max_slots):
         h = C.c_void_p()
         _check(lib().hot_batch_create(budget_bytes, max_slots, C.byref(h)))
         self.handle = h
 
+    def capacity(self):
+        fb = C.c_size_t()
+        fs = C.c_int32()
+        _check(lib().hot_batch_capacity(self.handle, C.byref(fb), C.byref(fs)))
+        return fb.value, fs.value
+
     def add(self, scene: Scene, n_steps: int, tag: int) -> bool:
+        """Admit a scene; False when it does not fit now (HOT_E_NOMEM)."""
         st = lib().hot_batch_add(self.handle, scene.handle, n_steps, tag)
         if st == HOT_E_NOMEM:
             return False
         _check(st)
         return True
 
-    def round(self, cap=1024):
-        tags = (C.c_int64 * cap)()
+    def poll(self, wait_ms=0, cap=64):
+        """Finished scenes as dicts (tag, status, steps, iters, t_admit,
+        t_step_end list, message) and the number still resident."""
+        res = (hot_batch_result * cap)()
         nd = C.c_int32()
         nr = C.c_int32()
-        _check(lib().hot_batch_round(self.handle, tags, C.byref(nd), cap, C.byref(nr)))
-        return [tags[k] for k in range(min(nd.value, cap))], nr.value
+        _check(lib().hot_batch_poll(self.handle, res, cap, C.byref(nd), C.byref(nr), wait_ms))
+        out = []
+        for k in range(nd.value):
+            r = res[k]
+            m = min(r.steps + (1 if r.status < 0 else 0), BATCH_MAX_STEPS)
+            out.append(dict(tag=r.tag, status=r.status, steps=r.steps, iters=r.iters,
+                            t_admit=r.t_admit, t_step_end=[r.t_step_end[i] for i in range(m)],
+                            message=r.message.decode(errors="replace")))
+        return out, nr.value
+
+    def clock(self):
+        return lib().hot_batch_clock(self.handle)
 
     def close(self):
         if self.handle:

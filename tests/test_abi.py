@@ -14,14 +14,14 @@ LIB = os.path.join(ROOT, "paper_1911_07913_amd", "libhot.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:hot_status|void|const char\*)\s+(hot_\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:hot_status|void|double|const char\*)\s+(hot_\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("hot_init_scene", "hot_step", "hot_read_particles", "hot_destroy_scene",
-                     "hot_scene_footprint", "hot_batch_round"):
+                     "hot_scene_footprint", "hot_batch_add", "hot_batch_poll"):
         assert required in names
 
 
@@ -48,6 +48,8 @@ def test_struct_layouts_match_header_sizes():
     size_t sz_mat(void){return sizeof(hot_material);}
     size_t off_precision(void){return offsetof(hot_params, precision);}
     size_t off_ms(void){return offsetof(hot_step_stats, ms_prepare);}
+    size_t sz_result(void){return sizeof(hot_batch_result);}
+    size_t off_msg(void){return offsetof(hot_batch_result, message);}
     '''
     import subprocess
     import tempfile
@@ -57,7 +59,8 @@ def test_struct_layouts_match_header_sizes():
         open(c, "w").write(src)
         subprocess.check_call(["gcc", "-shared", "-fPIC", "-I", os.path.join(ROOT, "include"), c, "-o", so])
         t = ctypes.CDLL(so)
-        for f in ("sz_params", "sz_stats", "sz_bc", "sz_mat", "off_precision", "off_ms"):
+        for f in ("sz_params", "sz_stats", "sz_bc", "sz_mat", "off_precision", "off_ms", "sz_result",
+                  "off_msg"):
             getattr(t, f).restype = ctypes.c_size_t
         assert t.sz_params() == ctypes.sizeof(hot.hot_params)
         assert t.sz_stats() == ctypes.sizeof(hot.hot_step_stats)
@@ -65,3 +68,5 @@ def test_struct_layouts_match_header_sizes():
         assert t.sz_mat() == ctypes.sizeof(hot.hot_material)
         assert t.off_precision() == hot.hot_params.precision.offset
         assert t.off_ms() == hot.hot_step_stats.ms_prepare.offset
+        assert t.sz_result() == ctypes.sizeof(hot.hot_batch_result)
+        assert t.off_msg() == hot.hot_batch_result.message.offset

@@ -1,0 +1,93 @@
+"""Serving: continuous batching of independent scenes through hot_batch_*.
+
+A scene's result must not depend on what else is resident: each request's
+particles after its steps, run inside a stream of overlapping requests, are
+bit-identical to the same scene stepped alone (every kernel of the step is
+deterministic: fixed-order reductions, no floating-point atomics across
+waves).  Admission must respect the HBM budget, and a request larger than
+the budget is refused.
+"""
+import numpy as np
+import pytest
+
+import hot_scenes as hs
+
+pytestmark = pytest.mark.gpu
+
+N_REQ = 10
+STEPS = 3
+
+
+def _mods():
+    from paper_1911_07913_amd import hot, serving
+    hot.lib()
+    return hot, serving
+
+
+def small_requests():
+    return [hs.serving_scene(i, seed_base=4500, n_min=2000, n_max=24000) for i in range(N_REQ)]
+
+
+def alone(hot, sc, precision):
+    g = hot.Scene.from_scene(sc, precision=precision)
+    try:
+        for _ in range(STEPS):
+            g.step()
+        return g.read()
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_results_identical_alone_and_in_the_mix(precision):
+    hot, serving = _mods()
+    reqs = small_requests()
+    ref = [alone(hot, sc, precision) for sc in reqs]
+    got = {}
+
+    def collect(k, scene):
+        got[k] = scene.read()
+
+    arrivals = serving.poisson_arrivals(N_REQ, rate=200.0, seed=7)
+    records, summary, trace = serving.serve(reqs, arrivals, budget_bytes=8 << 30, max_slots=4,
+                                            precision=precision, n_steps=STEPS, collect=collect)
+    print(summary, trace)
+    assert len(records) == N_REQ and summary["failed"] == 0
+    assert trace["peak_resident"] > 1, "requests never overlapped"
+    for r in records:
+        assert r["steps"] == STEPS and r["status"] >= 0
+    for k in range(N_REQ):
+        for f in ("x", "v", "F", "C"):
+            assert np.array_equal(got[k][f], ref[k][f]), f"request {k} field {f}"
+
+
+def test_admission_respects_budget():
+    hot, serving = _mods()
+    reqs = small_requests()[:6]
+    need = [hot.footprint(hot.params_of(sc, hot.HOT_MIXED), sc.x) for sc in reqs]
+    budget = int(max(need) * 1.5)
+    records, summary, trace = serving.serve(reqs, np.zeros(len(reqs)), budget_bytes=budget,
+                                            max_slots=8, precision=hot.HOT_MIXED, n_steps=1)
+    assert len(records) == len(reqs) and summary["failed"] == 0
+    assert trace["peak_reserved_bytes"] <= budget
+    # a scene's working set stays within its admission estimate
+    for sc in reqs[:2]:
+        g = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
+        g.step()
+        live, est = g.memory()
+        g.close()
+        assert live <= est, (live, est)
+
+
+def test_oversized_request_is_refused():
+    hot, serving = _mods()
+    sc = small_requests()[0]
+    b = hot.Batch(1 << 20, 2)
+    g = hot.Scene.from_scene(sc)
+    try:
+        assert b.add(g, 1, 0) is False
+        done, resident = b.poll()
+        assert done == [] and resident == 0
+    finally:
+        b.close()
+        g.close()
