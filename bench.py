@@ -1,4 +1,5 @@
-"""Benchmark: implicit MPM steps/s on the 1.5M-particle twisting-bars scene.
+"""Benchmark: implicit MPM steps/s on the 1.5M-particle twisting-bars scene,
+FP64 and mixed precision, plus a served stream of independent scenes.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -8,7 +9,10 @@ quasi-Newton solve (two-loop, V-cycle, line search, CN test) and G2P.  The
 scene (4 Neo-Hookean bars of 192x16x16 cells, 8 particles per cell, E in
 {1e5..1e8} Pa, grips twisting at +-2 rad/s, 256x64x64 grid, dx = 1/64, 5
 Galerkin levels, L-BFGS window 8, CN tolerance 1e-6) is resident in HBM before
-the timed region.  Prints one JSON line.
+the timed region; the default K = 20 times the whole 20-step job from t = 0.
+The served stream: 512 random spinning boxes (4k-256k particles, 10 steps
+each) with Poisson arrivals at 0.7 of the closed-loop step rate.  Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -25,7 +29,29 @@ if ROOT not in sys.path:
 
 METRIC = "implicit MPM steps/s @1.5M particles, FP64 vs mixed; served p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 CUs x 64 FP64 FMA lanes per clock x 2 flop x 2.4 GHz
 FP64_PEAK_TFLOPS = 78.6
+
+# What bounds each traced kernel, and the algorithmic FP64 flops of the
+# ALU-bound ones per particle.  Level-0 assembly per particle: a_ip = F^T grad w
+# for 27 nodes (27 x 9 FMA), C+ a_jp for 27 nodes (27 x 81 FMA), and the 378
+# distinct 3x3 blocks a_ip^T (C+ a_jp) of the symmetric 27 x 27 block pattern
+# (378 x 27 FMA): 12,636 FMA = 25,272 flop.
+BOUND = {"smooth0": "hbm", "residual0": "hbm", "rap0": "hbm", "particle_eval": "hbm",
+         "gradient": "hbm", "assemble_h0": "alu", "particle_hessian": "alu"}
+FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 9 + 27 * 81 + 378 * 27)}
+
+CSRC = os.path.join(ROOT, "paper_1911_07913_amd", "csrc")
+# committed PMC summaries: per-launch HBM traffic of a kernel, valid while the
+# sources it was measured on are unchanged
+TRAFFIC = {
+    "assemble_h0": ("assemble_h0_twisting_bars_1p5M_fp64_pmc.md",
+                    ["particles.hip", "mpm_math.h", "hot_internal.h"]),
+    "smooth0": ("vcycle_level0_twisting_bars_1p5M_fp64_pmc.md",
+                ["matrix.hip", "mpm_math.h", "hot_internal.h"]),
+    "residual0": ("vcycle_level0_twisting_bars_1p5M_fp64_pmc.md",
+                  ["matrix.hip", "mpm_math.h", "hot_internal.h"]),
+}
 
 # CPU-baseline sample: same scene family, 4 bars of 24x6x6 cells
 SAMPLE = dict(side=6, length=24)
@@ -66,7 +92,9 @@ def cpu_baseline(n_full):
 
 
 def run(precision, steps, warmup, side, profile=True):
-    import numpy as np
+    """Warm up on a throwaway copy of the scene (kernels loaded, device memory
+    in torch's cache), then time ``steps`` steps of a fresh scene from t = 0:
+    with the default 20 steps, the whole twisting-bars job."""
     import torch
 
     import hot_scenes as hs
@@ -75,10 +103,14 @@ def run(precision, steps, warmup, side, profile=True):
     sc = hs.twisting_bars(side=side)
     stream = torch.cuda.Stream()
     alloc = hot.TorchAllocator(0)
+    if warmup > 0:
+        w = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream,
+                                 allocator=alloc)
+        for _ in range(warmup):
+            w.step()
+        torch.cuda.synchronize()
+        w.close()
     g = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream, allocator=alloc)
-    for _ in range(warmup):
-        g.step()
-    torch.cuda.synchronize()
     if profile:
         g.profile(True)
     stats = []
@@ -135,30 +167,106 @@ def run_serving(n_req, slots, budget_gb, precision, load=0.7, n_sat=64):
     return summary
 
 
-def roofline_of(prof):
-    # the dominant traced kernel by total time
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from
+    the committed PMC summary, or None when there is none or the kernel's
+    sources changed since it was taken."""
+    if kernel not in TRAFFIC:
+        return None
+    fname, files = TRAFFIC[kernel]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("traffic-json: "):
+                d = json.loads(ln[len("traffic-json: "):])
+                if d.get("kernel") == kernel:
+                    rec = d
+    if rec is None or rec.get("source_sha256") != source_hash(files):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def roofline_of(prof, n_particles):
+    """Roofline of the dominant traced kernel (largest summed launch time)."""
     name, (ms, launches, nbytes) = max(prof.items(), key=lambda kv: kv[1][0])
     if launches == 0:
         return None
-    achieved = nbytes / (ms * 1e-3) / 1e9
+    avg_s = ms * 1e-3 / launches
+    traffic = traffic_of(name)
+    if BOUND[name] == "alu":
+        flops = FLOP_PER_PARTICLE[name] * n_particles
+        achieved = flops / avg_s / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                "avg_launch_ms": ms / launches, "launches": launches,
+                "algorithmic_flop_per_launch": flops,
+                "algorithmic_bytes_per_launch": nbytes / launches}
+    achieved = nbytes / launches / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "avg_launch_ms": ms / launches, "launches": launches,
             "algorithmic_bytes_per_launch": nbytes / launches}
+
+
+def vcycle_roofline(prof):
+    """HBM roofline of the level-0 V-cycle sweeps (smoothing + residual), the
+    bandwidth-bound kernels each quasi-Newton iteration repeats."""
+    ms = sum(prof[k][0] for k in ("smooth0", "residual0"))
+    launches = sum(prof[k][1] for k in ("smooth0", "residual0"))
+    nbytes = sum(prof[k][2] for k in ("smooth0", "residual0"))
+    if launches == 0 or ms <= 0:
+        return None
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    out = {"kernels": ["smooth0", "residual0"], "bound": "hbm", "achieved": achieved,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+    for k in ("smooth0", "residual0"):
+        t, n, b = prof[k]
+        out[k] = {"avg_launch_ms": t / n if n else None,
+                  "algorithmic_bytes_per_launch": b / n if n else None,
+                  "traffic": traffic_of(k)}
+    return out
+
+
+def calibrate_copy(nbytes=1 << 30):
+    """One plain device-to-device copy of a known size (for scaling HBM
+    counters read under the profiler)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=16, help="bar cross-section (16: 1.5M particles)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device copy first (counter calibration under a profiler)")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serving-precision", default="mixed", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--serving-precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -176,6 +284,8 @@ def main():
     hot.lib()
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
+    if a.calibrate_copy:
+        calibrate_copy()
     precs = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
              "both": [hot.HOT_FP64, hot.HOT_MIXED]}[a.precision]
     results = {}
@@ -200,7 +310,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(a.side), "particles": r["n"],
                    "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed"},
-        "roofline": roofline_of(r["prof"]),
+        "roofline": roofline_of(r["prof"], r["n"]),
+        "vcycle_roofline": vcycle_roofline(r["prof"]),
         "per_step": {
             "iters": [s["iters"] for s in stats],
             "cg_iters": [s["cg_iters_total"] for s in stats],
@@ -221,7 +332,8 @@ def main():
         line["mixed"] = {"value": a.steps / rm["seconds"], "unit": "steps/s",
                          "ms_per_step": 1000.0 * rm["seconds"] / a.steps,
                          "iters": [s["iters"] for s in rm["stats"]],
-                         "roofline": roofline_of(rm["prof"])}
+                         "roofline": roofline_of(rm["prof"], rm["n"]),
+                         "vcycle_roofline": vcycle_roofline(rm["prof"])}
     if a.serving_requests > 0:
         sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
               "both": [hot.HOT_MIXED, hot.HOT_FP64]}[a.serving_precision]
