@@ -142,6 +142,93 @@ __global__ void k_finish(int nparts, int count, int is_max, const double* __rest
   }
 }
 
+// The fixed-order sum of k_finish, in thread 0.
+__device__ inline double finish_sum(int nparts, const double* __restrict__ partial, double* sh) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kTpb) s += partial[k];
+  return block_sum(s, sh);
+}
+
+// One step of either two-loop recursion, fused with the inner product the
+// next step needs:  v <- (init ? -init : v) + (sign * coef) x_prev, then the
+// block partials of d_next . v.  Element order, operand order and the
+// reduction tree are those of the separate scale/axpy/dot kernels, so the
+// result is bit-identical to running them one after another.
+__global__ void k_twoloop_update(long long n, const double* __restrict__ init,
+                                 const double* __restrict__ coef, double sign,
+                                 const double* __restrict__ xprev, double* __restrict__ v,
+                                 const double* __restrict__ dnext, double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  const bool write = init || xprev;
+  const double al = xprev ? sign * coef[0] : 0.0;
+  double acc = 0.0;
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+    double val = init ? -1.0 * init[k] : v[k];
+    if (xprev) val = val + al * xprev[k];
+    if (write) v[k] = val;
+    if (dnext) acc += dnext[k] * val;
+  }
+  if (dnext) {
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  }
+}
+
+// dot_out = sum of the partials; first loop: alpha_out = rho dot; second
+// loop: coef_out = alpha_in - rho dot.
+__global__ void k_finish_lbfgs(const double* __restrict__ partial, const double* __restrict__ rho,
+                               const double* __restrict__ alpha_in, double* __restrict__ dot_out,
+                               double* __restrict__ alpha_out, double* __restrict__ coef_out) {
+  __shared__ double sh[kTpb / 64];
+  double t = finish_sum(kRedBlocks, partial, sh);
+  if (threadIdx.x == 0) {
+    dot_out[0] = t;
+    if (alpha_out) alpha_out[0] = rho[0] * t;
+    if (coef_out) {
+      double beta = rho[0] * t;
+      coef_out[0] = alpha_in[0] - beta;
+    }
+  }
+}
+
+// Accepted step: dv_t = dv + alpha p and s = dv_t - dv.
+__global__ void k_step_update(long long n, const double* __restrict__ dv, double alpha,
+                              const double* __restrict__ p, double* __restrict__ dvt,
+                              double* __restrict__ sv) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double t = dv[k];
+  t = t + alpha * p[k];
+  dvt[k] = t;
+  sv[k] = t - dv[k];
+}
+
+// y = g_new - g with the partials of y.s, y.y, s.s (the k_partial3 order).
+__global__ void k_secant(long long n, const double* __restrict__ gnew, const double* __restrict__ g,
+                         double* __restrict__ y, const double* __restrict__ sv,
+                         double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+    double x = gnew[k] - g[k];
+    y[k] = x;
+    double yv = sv[k];
+    s0 += x * yv;
+    s1 += x * x;
+    s2 += yv * yv;
+  }
+  double t0 = block_sum(s0, sh);
+  __syncthreads();
+  double t1 = block_sum(s1, sh);
+  __syncthreads();
+  double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t0;
+    partial[kRedBlocks + blockIdx.x] = t1;
+    partial[2 * kRedBlocks + blockIdx.x] = t2;
+  }
+}
+
 __global__ void k_axpy_dev(long long n, const double* __restrict__ a, double sign,
                            const double* __restrict__ x, double* __restrict__ y) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,6 +330,24 @@ void launch_max_speed(int n, const double* v, double* partial, double* out, hipS
 void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
                      hipStream_t st) {
   if (n > 0) k_axpy_dev<<<blocks_for(n), kTpb, 0, st>>>(n, a_dev, sign, x, y);
+}
+void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
+                           const double* xprev, double* v, const double* dnext, double* partial,
+                           hipStream_t st) {
+  k_twoloop_update<<<kRedBlocks, kTpb, 0, st>>>(n, init, coef, sign, xprev, v, dnext, partial);
+}
+void launch_finish_lbfgs(const double* partial, const double* rho, const double* alpha_in,
+                         double* dot_out, double* alpha_out, double* coef_out, hipStream_t st) {
+  k_finish_lbfgs<<<1, kTpb, 0, st>>>(partial, rho, alpha_in, dot_out, alpha_out, coef_out);
+}
+void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
+                        double* sv, hipStream_t st) {
+  if (n > 0) k_step_update<<<blocks_for(n), kTpb, 0, st>>>(n, dv, alpha, p, dvt, sv);
+}
+void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
+                   double* partial, double* out, hipStream_t st) {
+  k_secant<<<kRedBlocks, kTpb, 0, st>>>(n, gnew, g, y, sv, partial);
+  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 3, 0, partial, out);
 }
 void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st) {
   if (n > 0) k_axpy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);

@@ -109,6 +109,7 @@ struct hot_scene {
   int cur = 0;
   DBuf pbuf[2];
   DBuf f, key, keys, tmp, Cp, psi[2], S[2];
+  DBuf wnode;  // double4 node velocities over the padded level-0 grid
   int pc = 0;  // current psi/S buffer
   // level-0 grid
   DBuf counts, start, cursor, flags, scan, scan_temp, err;
@@ -377,6 +378,7 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
   int dims[3] = {p->grid_cells[0] + 1, p->grid_cells[1] + 1, p->grid_cells[2] + 1};
   GridGeom g0 = make_geom(dims[0], dims[1], dims[2]);
   double pt = (double)g0.ptotal;
+  A(pt * 32);  // node velocities
   A(pt * 4); A(pt * 4 + 4); A(pt * 4); A(pt * 4); A(pt * 4 + 4); A((pt / 2048 + 2) * 4); A(64);
   GridGeom gm = g0;
   for (int m = 0; m < p->mg_levels; ++m) {
@@ -533,7 +535,8 @@ hot_status prepare(hot_scene* s, double dt) {
   // -- level-0 Hessian at dv = 0 and the Galerkin hierarchy
   PROF(s, HOT_PROF_PHESS,
        launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
-                               pt.mat, P<double>(s->vstar), dt, P<double>(s->Cp), st));
+                               pt.mat, P<double>(s->vstar), dt, P<double>(s->wnode),
+                               P<double>(s->Cp), st));
   PROF(s, HOT_PROF_ASSEMBLE,
        launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, P<double>(s->f), pt.F,
                           P<double>(s->Cp), P<int>(s->start), P<int>(s->counts),
@@ -599,8 +602,8 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
     launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], st);
   }
   int slot = std::min(s->vcycles, s->prm.max_iters * 3 + 15);
-  launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p,
-                    P<int>(s->pcg_iters) + slot, 500, 0.5, st);
+  HIPCHK(launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p,
+                    P<int>(s->pcg_iters) + slot, 500, 0.5, st));
   s->vcycles++;
   for (int m = M - 2; m >= 0; --m) {
     LevelView Lm = view(s, m);
@@ -628,7 +631,8 @@ hot_status eval_trial(hot_scene* s, const double* dv, const double* p, double al
   PROF(s, HOT_PROF_EVAL,
        launch_particle_eval(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.F,
                             pt.vol, pt.mat, P<double>(s->vstar), dv, p, alpha, s->dt_prepared,
-                            P<double>(s->psi[out]), P<double>(s->S[out]), s->stream));
+                            P<double>(s->wnode), P<double>(s->psi[out]), P<double>(s->S[out]),
+                            s->stream));
   return HOT_OK;
 }
 
@@ -720,25 +724,40 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
   std::vector<std::pair<int, int>> vc_range;
   while (!conv && it < s->prm.max_iters) {
     int vc0 = s->vcycles;
-    // -- two-loop recursion
-    launch_scale_copy(N, -1.0, g, q, st);
-    for (int k = (int)hist.size() - 1; k >= 0; --k) {
-      int a = hist[k];
-      launch_dot(N, P<double>(s->Sh[a]), q, partial, P<double>(s->ddot) + a, st);
-      launch_lbfgs_alpha(P<double>(s->drho) + a, P<double>(s->ddot) + a, P<double>(s->dalpha) + a, st);
-      launch_axpy_dev(N, P<double>(s->dalpha) + a, -1.0, P<double>(s->Yh[a]), q, st);
+    // -- two-loop recursion (each axpy fused with the next inner product)
+    const int K = (int)hist.size();
+    if (K == 0) {
+      launch_scale_copy(N, -1.0, g, q, st);
+    } else {
+      launch_twoloop_update(N, g, nullptr, 0.0, nullptr, q, P<double>(s->Sh[hist[K - 1]]),
+                            partial, st);
+      for (int k = K - 1; k >= 0; --k) {
+        int a = hist[k];
+        launch_finish_lbfgs(partial, P<double>(s->drho) + a, nullptr, P<double>(s->ddot) + a,
+                            P<double>(s->dalpha) + a, nullptr, st);
+        const double* dn = k > 0 ? P<double>(s->Sh[hist[k - 1]]) : nullptr;
+        launch_twoloop_update(N, nullptr, P<double>(s->dalpha) + a, -1.0, P<double>(s->Yh[a]), q,
+                              dn, partial, st);
+      }
     }
     TRY(vcycle(s, q, r));
-    for (size_t k = 0; k < hist.size(); ++k) {
-      int a = hist[k];
-      launch_dot(N, P<double>(s->Yh[a]), r, partial, P<double>(s->ddot) + a, st);
-      launch_lbfgs_coef(P<double>(s->drho) + a, P<double>(s->ddot) + a, P<double>(s->dalpha) + a,
-                        P<double>(s->dcoef) + a, st);
-      launch_axpy_dev(N, P<double>(s->dcoef) + a, 1.0, P<double>(s->Sh[a]), r, st);
+    if (K == 0) {
+      launch_dot(N, g, r, partial, dscal + S_GP, st);
+    } else {
+      launch_twoloop_update(N, nullptr, nullptr, 0.0, nullptr, r, P<double>(s->Yh[hist[0]]),
+                            partial, st);
+      for (int k = 0; k < K; ++k) {
+        int a = hist[k];
+        launch_finish_lbfgs(partial, P<double>(s->drho) + a, P<double>(s->dalpha) + a,
+                            P<double>(s->ddot) + a, nullptr, P<double>(s->dcoef) + a, st);
+        const double* dn = k + 1 < K ? P<double>(s->Yh[hist[k + 1]]) : g;
+        launch_twoloop_update(N, nullptr, P<double>(s->dcoef) + a, 1.0, P<double>(s->Sh[a]), r, dn,
+                              partial, st);
+      }
+      launch_finish_lbfgs(partial, nullptr, nullptr, dscal + S_GP, nullptr, nullptr, st);
     }
     // -- descent check and the first trial in one readback
     int trial = 1 - s->pc;
-    launch_dot(N, g, r, partial, dscal + S_GP, st);
     TRY(eval_trial(s, dv, r, 1.0, trial));
     launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
     launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
@@ -798,16 +817,14 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
         slot = a;
         break;
       }
-    HIPCHK(hipMemcpyAsync(dvt, dv, N * 8, hipMemcpyDeviceToDevice, st));
-    launch_axpy(N, alpha, r, dvt, st);
-    launch_sub(N, dvt, dv, P<double>(s->Sh[slot]), st);
+    launch_step_update(N, dv, alpha, r, dvt, P<double>(s->Sh[slot]), st);
     std::swap(s->dv, s->dvt);
     dv = P<double>(s->dv);
     dvt = P<double>(s->dvt);
     s->pc = trial;
     TRY(gradient(s, dv, s->pc, gnew));
-    launch_sub(N, gnew, g, P<double>(s->Yh[slot]), st);
-    launch_dots3(N, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), partial, dscal + S_YS, st);
+    launch_secant(N, gnew, g, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), partial,
+                  dscal + S_YS, st);
     launch_cn_sq(n0, gnew, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
     TRY(readback(s));
     double ys = s->hscal[S_YS], yy = s->hscal[S_YY], ss = s->hscal[S_SS];
@@ -836,6 +853,8 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     HIPCHK(hipMemcpyAsync(pcg.data(), s->pcg_iters.p, nv * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  for (int v = 0; v < nv; ++v)
+    if (pcg[v] < 0) return fail(HOT_E_DEVICE, "coarsest solve: grid barrier timed out");
   int cg_total = 0;
   for (size_t k = 0; k < vc_range.size() && 4 * k + 3 < s->log_int.size(); ++k) {
     int sum = 0;
@@ -884,7 +903,7 @@ hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
   HIPCHK(hipEventRecord(s->ev[3], st));
   Particles& pt = s->P[s->cur];
   launch_g2p(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.x, pt.v, pt.C, pt.F,
-             pt.mat, P<double>(s->vstar), P<double>(s->dv), dt, st);
+             pt.mat, P<double>(s->vstar), P<double>(s->dv), dt, P<double>(s->wnode), st);
   HIPCHK(hipEventRecord(s->ev[4], st));
   HIPCHK(hipEventSynchronize(s->ev[4]));
   HIPCHK(hipGetLastError());
@@ -913,7 +932,7 @@ void destroy(hot_scene* s) {
                  &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
                  &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
                  &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
-                 &s->bmap, &s->blist, &s->bpartial};
+                 &s->bmap, &s->blist, &s->bpartial, &s->wnode};
   for (DBuf* b : all) release(s, *b);
   for (auto& b : s->Sh) release(s, b);
   for (auto& b : s->Yh) release(s, b);
@@ -1100,6 +1119,7 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
   for (DBuf* b : ib)
     if ((rc = ensure(s, *b, (size_t)n * 4)) < 0) return bail(rc);
   long long pt = sd.g0.ptotal;
+  if ((rc = ensure(s, s->wnode, pt * 32)) < 0) return bail(rc);
   if ((rc = ensure(s, s->counts, pt * 4)) < 0 || (rc = ensure(s, s->start, (pt + 1) * 4)) < 0 ||
       (rc = ensure(s, s->cursor, pt * 4)) < 0 || (rc = ensure(s, s->flags, pt * 4)) < 0 ||
       (rc = ensure(s, s->scan, (pt + 1) * 4)) < 0 ||

@@ -169,21 +169,27 @@ void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const d
                 const double* v, const double* C, const double* vol, const int* mat,
                 const int* cstart, const int* ccount, double* partial, double dt, double t_end,
                 double* mass, double* vstar, double* xi, int* fixed, hipStream_t st);
+// The particle kernels below first write the node velocities they need
+// (v* + dv + alpha p) into `wnode`, a double4 array over the padded level-0
+// grid, so each particle gathers 27 nodes with two loads per node and no map
+// lookup.
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
-                             const double* vstar, double dt, double* Cp, hipStream_t st);
+                             const double* vstar, double dt, double* wnode, double* Cp,
+                             hipStream_t st);
 // energy/stress at dv + alpha*p: psi_out[n] = V_p psi, S_out[9n] = V_p P F^n^T
 void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
                           const int* key, const double* F, const double* vol, const int* mat,
                           const double* vstar, const double* dv, const double* p, double alpha,
-                          double dt, double* psi_out, double* S_out, hipStream_t st);
+                          double dt, double* wnode, double* psi_out, double* S_out,
+                          hipStream_t st);
 void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
                      const double* S, const int* cstart, const int* ccount, double* partial,
                      const double* mass, const int* fixed, const double* dv, double dt, double* g,
                      hipStream_t st);
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
-                const double* dv, double dt, hipStream_t st);
+                const double* dv, double dt, double* wnode, hipStream_t st);
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
                         const double* f, const double* F, const double* Cp, const int* cstart,
                         const int* ccount, const double* mass, const int* fixed, hipStream_t st);
@@ -202,8 +208,10 @@ void launch_restrict(const LevelView& F, const LevelView& Cv, bool mixed, const 
                      void* bc, hipStream_t st);
 void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, const void* uc,
                         void* u, hipStream_t st);
-void launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                       int* iters_out, int max_iter, double rel, hipStream_t st);
+// Coarsest solve; iters_out receives the iteration count, or -1 if a grid
+// barrier of the multi-work-group form timed out.
+hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
+                             int* iters_out, int max_iter, double rel, hipStream_t st);
 size_t coarse_pcg_work_bytes(int n);
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st);
 
@@ -229,6 +237,21 @@ void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t 
 void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st);
 void launch_sub(long long n, const double* a, const double* b, double* y, hipStream_t st);
 void launch_lbfgs_alpha(const double* rho, const double* dot, double* alpha, hipStream_t st);
+// Fused two-loop step: v <- (init ? -init : v) + sign*coef[0]*xprev; partials
+// of dnext . v (any of init, xprev, dnext may be NULL).  Bit-identical to the
+// separate kernels.
+void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
+                           const double* xprev, double* v, const double* dnext, double* partial,
+                           hipStream_t st);
+// dot_out = sum(partial); alpha_out = rho*dot; coef_out = alpha_in - rho*dot
+void launch_finish_lbfgs(const double* partial, const double* rho, const double* alpha_in,
+                         double* dot_out, double* alpha_out, double* coef_out, hipStream_t st);
+// dvt = dv + alpha p, sv = dvt - dv
+void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
+                        double* sv, hipStream_t st);
+// y = gnew - g; out = {y.s, y.y, s.s}
+void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
+                   double* partial, double* out, hipStream_t st);
 void launch_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef,
                        hipStream_t st);
 void launch_to_f32(long long n, const double* x, float* y, hipStream_t st);

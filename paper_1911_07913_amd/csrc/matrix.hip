@@ -97,6 +97,82 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
   y[2] = wave_sum_t(a2);
 }
 
+// y_r = H_{i0+r} . x for R consecutive rows, computed by one wave with all
+// of the rows' loads issued before any is consumed, so that R rows' worth of
+// bytes are in flight per wave (a single row leaves the wave waiting on three
+// dependent memory round trips).  Large levels use SweepRows<V>::R rows per
+// wave; small levels one row per wave, to keep enough waves in flight.  FP64 blocks: lane l owns slots l and l + 64
+// (512-byte coalesced loads per entry).  BF16 blocks: lane l owns slots 2l and
+// 2l + 1 and reads both with one 32-bit load per entry.  Rows at or beyond
+// L.n contribute nothing.  Results are valid in all lanes.
+template <typename V>
+struct SweepRows;
+template <>
+struct SweepRows<double> {
+  static constexpr int R = 2;
+  static __device__ inline int slot(int lane, int k) { return lane + 64 * k; }
+  static __device__ inline void load(const double* Hrow, int c, int lane, bool p0, bool p1,
+                                     double& h0, double& h1) {
+    h0 = p0 ? Hrow[c * kSlotPad + lane] : 0.0;
+    h1 = p1 ? Hrow[c * kSlotPad + lane + 64] : 0.0;
+  }
+};
+template <>
+struct SweepRows<float> {
+  static constexpr int R = 4;
+  static __device__ inline int slot(int lane, int k) { return 2 * lane + k; }
+  static __device__ inline void load(const uint16_t* Hrow, int c, int lane, bool p0, bool p1,
+                                     float& h0, float& h1) {
+    uint32_t u = (p0 || p1) ? *(const uint32_t*)(Hrow + c * kSlotPad + 2 * lane) : 0u;
+    h0 = p0 ? bf16_to_f32((uint16_t)(u & 0xFFFFu)) : 0.0f;
+    h1 = p1 ? bf16_to_f32((uint16_t)(u >> 16)) : 0.0f;
+  }
+};
+
+template <typename V, int R>
+__device__ inline void rows_matvec(const LevelView& L, int i0, const V* __restrict__ x, int lane,
+                                   V (&y)[R][3]) {
+  typedef typename MatOf<V>::type M;
+  V h[R][2][9];
+  int jn[R][2];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = i0 + r;
+    const bool live = i < L.n;
+    const M* Hrow = MatOf<V>::H(L) + (long long)(live ? i : 0) * kRowStride;
+    const long long pn = live ? L.nodes[i] : 0;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (live)
+      for (int q = 0; q < 4; ++q) w[q] = L.pat[4 * i + q];
+    bool pr[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int s = SweepRows<V>::slot(lane, k);
+      pr[k] = slot_present(w, s);
+      jn[r][k] = pr[k] ? L.map[pn + slot_offset(L.g, s)] : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) SweepRows<V>::load(Hrow, c, lane, pr[0], pr[1], h[r][0][c], h[r][1][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    V a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (jn[r][k] >= 0) {
+        const V* xj = x + 3 * (long long)jn[r][k];
+        V x0 = xj[0], x1 = xj[1], x2 = xj[2];
+        a0 += h[r][k][0] * x0 + h[r][k][1] * x1 + h[r][k][2] * x2;
+        a1 += h[r][k][3] * x0 + h[r][k][4] * x1 + h[r][k][5] * x2;
+        a2 += h[r][k][6] * x0 + h[r][k][7] * x1 + h[r][k][8] * x2;
+      }
+    }
+    y[r][0] = wave_sum_t(a0);
+    y[r][1] = wave_sum_t(a1);
+    y[r][2] = wave_sum_t(a2);
+  }
+}
+
 // ---------------------------------------------------------------- RAP
 // Coarse row I of H^{m+1} = P~^T H^m P~ (Eq. buildMultigrid) with the linear
 // node embedding: the fine children of I are 2I + a, a in {-1,0,1}^3, weight
@@ -196,56 +272,90 @@ __global__ void k_jacobi_first(LevelView L, const V* __restrict__ b, V* __restri
 
 constexpr int kRowWaves = 4;
 
-// r = b - H u (one wave per row)
-template <typename V>
+// r = b - H u (one wave per R consecutive rows)
+template <typename V, int R>
 __global__ __launch_bounds__(256) void k_residual(LevelView L, const V* __restrict__ b,
                                                   const V* __restrict__ u, V* __restrict__ r) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave;
-  if (i >= L.n) return;
-  V y[3];
-  row_matvec<V>(L, i, u, lane, y);
-  if (lane < 3) r[3 * i + lane] = b[3 * i + lane] - y[lane];
+  int i0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
+  if (i0 >= L.n) return;
+  V y[R][3];
+  rows_matvec<V, R>(L, i0, u, lane, y);
+  if (lane < 3 * R) {
+    const int rr = lane / 3, c = lane - 3 * rr;
+    const int i = i0 + rr;
+    V yv = y[0][0];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      for (int e = 0; e < 3; ++e)
+        if (q == rr && e == c) yv = y[q][e];
+    if (i < L.n) r[3 * i + c] = b[3 * i + c] - yv;
+  }
 }
 
 // l1 block-Jacobi sweep: u_out = u + D~^{-1} (b - H u), projected.
-template <typename V>
+template <typename V, int R>
 __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict__ b,
                                                 const V* __restrict__ u, V* __restrict__ uo) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int i = xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave;
-  if (i >= L.n) return;
-  V y[3];
-  row_matvec<V>(L, i, u, lane, y);
-  if (lane < 3) {
-    const V* Di = MatOf<V>::Dinv(L) + 9 * (long long)i;
-    V r0 = b[3 * i] - y[0], r1 = b[3 * i + 1] - y[1], r2 = b[3 * i + 2] - y[2];
-    V upd = Di[3 * lane] * r0 + Di[3 * lane + 1] * r1 + Di[3 * lane + 2] * r2;
-    V out = u[3 * i + lane] + upd;
-    uo[3 * i + lane] = L.free_dof[3 * i + lane] ? out : (V)0;
+  int i0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
+  if (i0 >= L.n) return;
+  V y[R][3];
+  rows_matvec<V, R>(L, i0, u, lane, y);
+  if (lane < 3 * R) {
+    const int rr = lane / 3, c = lane - 3 * rr;
+    const int i = i0 + rr;
+    V y0 = y[0][0], y1 = y[0][1], y2 = y[0][2];
+#pragma unroll
+    for (int q = 1; q < R; ++q)
+      if (q == rr) {
+        y0 = y[q][0];
+        y1 = y[q][1];
+        y2 = y[q][2];
+      }
+    if (i < L.n) {
+      const V* Di = MatOf<V>::Dinv(L) + 9 * (long long)i;
+      V r0 = b[3 * i] - y0, r1 = b[3 * i + 1] - y1, r2 = b[3 * i + 2] - y2;
+      V upd = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
+      V out = u[3 * i + c] + upd;
+      uo[3 * i + c] = L.free_dof[3 * i + c] ? out : (V)0;
+    }
   }
 }
 
-// b^{m+1}_J = sum_i P~_iJ r_i over the 27 fine children of J.
+// b^{m+1}_J = sum_i P~_iJ r_i over the 27 fine children of J.  Half a wave
+// per coarse node, one lane per child, then a fixed-order reduction over the
+// half-wave (a thread per coarse node leaves most of the device idle on the
+// small coarse grids).
 template <typename V>
-__global__ void k_restrict(LevelView F, LevelView C, const V* __restrict__ r, V* __restrict__ bc) {
-  int J = blockIdx.x * blockDim.x + threadIdx.x;
-  if (J >= C.n) return;
-  int X, Y, Z;
-  unpidx(C.g, C.nodes[J], X, Y, Z);
+__global__ __launch_bounds__(256) void k_restrict(LevelView F, LevelView C,
+                                                  const V* __restrict__ r, V* __restrict__ bc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int a = lane & 31;
+  const int J = ((blockIdx.x * 4 + wave) << 1) + (lane >> 5);
   V s0 = 0, s1 = 0, s2 = 0;
-  for (int a = 0; a < 27; ++a) {
-    int ax = a % 3 - 1, ay = (a / 3) % 3 - 1, az = a / 9 - 1;
-    int i = F.map[pidx(F.g, 2 * X + ax, 2 * Y + ay, 2 * Z + az)];
-    if (i < 0) continue;
-    V w = (V)((ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0));
-    s0 += F.free_dof[3 * i] ? w * r[3 * i] : (V)0;
-    s1 += F.free_dof[3 * i + 1] ? w * r[3 * i + 1] : (V)0;
-    s2 += F.free_dof[3 * i + 2] ? w * r[3 * i + 2] : (V)0;
+  if (J < C.n && a < 27) {
+    int X, Y, Z;
+    unpidx(C.g, C.nodes[J], X, Y, Z);
+    const int ax = a % 3 - 1, ay = (a / 3) % 3 - 1, az = a / 9 - 1;
+    const int i = F.map[pidx(F.g, 2 * X + ax, 2 * Y + ay, 2 * Z + az)];
+    if (i >= 0) {
+      const V w = (V)((ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0));
+      s0 = F.free_dof[3 * i] ? w * r[3 * i] : (V)0;
+      s1 = F.free_dof[3 * i + 1] ? w * r[3 * i + 1] : (V)0;
+      s2 = F.free_dof[3 * i + 2] ? w * r[3 * i + 2] : (V)0;
+    }
   }
-  bc[3 * J] = s0;
-  bc[3 * J + 1] = s1;
-  bc[3 * J + 2] = s2;
+  for (int off = 16; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+  }
+  if (a == 0 && J < C.n) {
+    bc[3 * J] = s0;
+    bc[3 * J + 1] = s1;
+    bc[3 * J + 2] = s2;
+  }
 }
 
 // u_i += sum_J P~_iJ u^c_J over the (at most 8) parents of fine node i.
@@ -366,6 +476,197 @@ __global__ __launch_bounds__(256) void k_spmv(LevelView L, const double* __restr
   if (lane < 3) y[3 * i + lane] = v[lane];
 }
 
+
+// Multi-work-group form of the same solve for larger coarsest levels: one
+// wave per row (rows strided over all waves of the grid), the same update
+// formulas, and fixed-order two-stage inner products (per-block partials,
+// then every block sums the partials in block order).  Blocks meet at a
+// software grid barrier, so all blocks must be resident at once.  The grid is
+// kept small (at most kCgMaxBlocks, and at most 1/16 of the device's resident
+// block capacity), so that even 16 such solves running concurrently from
+// different streams, plus any finite kernels, cannot hold all block slots
+// while a block of one of them waits to start.  Every wait is still bounded:
+// a barrier that does not complete within the spin limit raises a flag that
+// makes every block leave, and the solve reports a negative iteration count.
+constexpr int kCgWaves = 4;
+constexpr int kCgMaxBlocks = 32;
+constexpr unsigned kSpinLimit = 1u << 22;
+
+struct GridBar {
+  unsigned count;
+  unsigned gen;
+  int fail;
+  int pad;
+};
+
+__device__ inline bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& gen, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned target = gen + 1u;
+    __threadfence();
+    const unsigned arrived = atomicAdd(&bar->count, 1u) + 1u;
+    if (arrived == nblocks) {
+      atomicExch(&bar->count, 0u);
+      __threadfence();
+      atomicExch(&bar->gen, target);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(&bar->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            ++spins > kSpinLimit) {
+          atomicExch(&bar->fail, 1);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __threadfence();
+    *s_ok = ok;
+  }
+  __syncthreads();
+  gen += 1u;
+  return *s_ok != 0;
+}
+
+// Sum of the per-block partials in block order, valid in every thread.
+__device__ inline double grid_total(const double* part, int nb, double* s_val) {
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 64) t += part[k];
+    t = wave_sum_t(t);
+    if (threadIdx.x == 0) *s_val = t;
+  }
+  __syncthreads();
+  double v = *s_val;
+  __syncthreads();
+  return v;
+}
+
+// Block-level partial of per-lane values (fixed order) written to part[block].
+__device__ inline void block_partial(double loc, double* part, double* red) {
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  loc = wave_sum_t(loc);
+  if (lane == 0) red[wave] = loc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kCgWaves; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
+    LevelView L, const V* __restrict__ b, V* __restrict__ x, V* __restrict__ work,
+    double* __restrict__ part, GridBar* __restrict__ bar, int* __restrict__ iters_out,
+    int max_iter, double rel) {
+  __shared__ double red[kCgWaves];
+  __shared__ double s_val;
+  __shared__ int s_ok;
+  const int n = L.n, n3 = 3 * n;
+  V* r = work;
+  V* z = r + n3;
+  V* p = z + n3;
+  V* q = p + n3;
+  double* part_pq = part;
+  double* part_rz = part + kCgMaxBlocks;
+  const V* dg = MatOf<V>::diag(L);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nb = gridDim.x;
+  const int gw = blockIdx.x * kCgWaves + wave, nw = nb * kCgWaves;
+  unsigned gen = 0;
+  double loc = 0.0;
+  for (int row = gw; row < n; row += nw)
+    if (lane < 3) {
+      const int k = 3 * row + lane;
+      V bk = b[k];
+      x[k] = 0;
+      r[k] = bk;
+      V zk = bk / dg[k];
+      z[k] = zk;
+      p[k] = zk;
+      loc += (double)(bk * zk);
+    }
+  block_partial(loc, part_rz, red);
+  int it = 0;
+  bool ok = grid_sync(bar, nb, gen, &s_ok);
+  double rz = ok ? grid_total(part_rz, nb, &s_val) : 0.0;
+  const double stop = rel * sqrt(fmax(rz, 0.0));
+  if (ok && rz > 0.0) {
+    while (it < max_iter) {
+      loc = 0.0;
+      for (int row = gw; row < n; row += nw) {
+        V y[3];
+        row_matvec<V>(L, row, p, lane, y);
+        if (lane < 3) {
+          q[3 * row + lane] = y[lane];
+          loc += (double)(p[3 * row + lane] * y[lane]);
+        }
+      }
+      block_partial(loc, part_pq, red);
+      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+      const double pq = grid_total(part_pq, nb, &s_val);
+      if (!(pq > 0.0)) break;
+      const V alpha = (V)(rz / pq);
+      loc = 0.0;
+      for (int row = gw; row < n; row += nw)
+        if (lane < 3) {
+          const int k = 3 * row + lane;
+          x[k] += alpha * p[k];
+          V rk = r[k] - alpha * q[k];
+          r[k] = rk;
+          V zk = rk / dg[k];
+          z[k] = zk;
+          loc += (double)(rk * zk);
+        }
+      block_partial(loc, part_rz, red);
+      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+      const double rzn = grid_total(part_rz, nb, &s_val);
+      ++it;
+      if (sqrt(fmax(rzn, 0.0)) <= stop) break;
+      const V beta = (V)(rzn / rz);
+      rz = rzn;
+      for (int row = gw; row < n; row += nw)
+        if (lane < 3) {
+          const int k = 3 * row + lane;
+          p[k] = z[k] + beta * p[k];
+        }
+      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
+}
+
+__global__ void k_reset_bar(GridBar* bar) {
+  if (threadIdx.x == 0) {
+    bar->count = 0u;
+    bar->gen = 0u;
+    bar->fail = 0;
+    bar->pad = 0;
+  }
+}
+
+// Grid size of k_coarse_pcg_grid<V> on the current device: 1/16 of the
+// resident block capacity, at most kCgMaxBlocks (0 or less if unknown).
+template <typename V>
+int grid_blocks() {
+  static int cached[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+  if (cached[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_coarse_pcg_grid<V>, kCgWaves * 64,
+                                                     0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cached[dev] = -1;
+    else
+      cached[dev] = std::max(std::min(per_cu * cus / 16, kCgMaxBlocks), -1);
+  }
+  return cached[dev];
+}
+
 }  // namespace
 
 void launch_rap(const LevelView& F, const LevelView& C, hipStream_t st) {
@@ -385,29 +686,52 @@ void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u,
   else
     k_jacobi_first<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double*)b, (double*)u);
 }
+// Levels with at least this many rows run several rows per wave.
+constexpr int kMultiRowMin = 65536;
+
+template <typename V>
+void sweep_launch(bool smooth, const LevelView& L, const V* b, const V* u, V* out,
+                  hipStream_t st) {
+  constexpr int R = SweepRows<V>::R;
+  if (L.n >= kMultiRowMin) {
+    unsigned g = (unsigned)((L.n + kRowWaves * R - 1) / (kRowWaves * R));
+    if (smooth)
+      k_smooth<V, R><<<g, 256, 0, st>>>(L, b, u, out);
+    else
+      k_residual<V, R><<<g, 256, 0, st>>>(L, b, u, out);
+  } else {
+    unsigned g = (unsigned)((L.n + kRowWaves - 1) / kRowWaves);
+    if (smooth)
+      k_smooth<V, 1><<<g, 256, 0, st>>>(L, b, u, out);
+    else
+      k_residual<V, 1><<<g, 256, 0, st>>>(L, b, u, out);
+  }
+}
+
 void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,
                      hipStream_t st) {
   if (L.n == 0) return;
   if (mixed)
-    k_residual<float><<<ROWGRID(L)>>>(L, (const float*)b, (const float*)u, (float*)r);
+    sweep_launch<float>(false, L, (const float*)b, (const float*)u, (float*)r, st);
   else
-    k_residual<double><<<ROWGRID(L)>>>(L, (const double*)b, (const double*)u, (double*)r);
+    sweep_launch<double>(false, L, (const double*)b, (const double*)u, (double*)r, st);
 }
 void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u, void* uo,
                    hipStream_t st) {
   if (L.n == 0) return;
   if (mixed)
-    k_smooth<float><<<ROWGRID(L)>>>(L, (const float*)b, (const float*)u, (float*)uo);
+    sweep_launch<float>(true, L, (const float*)b, (const float*)u, (float*)uo, st);
   else
-    k_smooth<double><<<ROWGRID(L)>>>(L, (const double*)b, (const double*)u, (double*)uo);
+    sweep_launch<double>(true, L, (const double*)b, (const double*)u, (double*)uo, st);
 }
 void launch_restrict(const LevelView& F, const LevelView& C, bool mixed, const void* r, void* bc,
                      hipStream_t st) {
   if (C.n == 0) return;
   if (mixed)
-    k_restrict<float><<<blocks_for(C.n), kTpb, 0, st>>>(F, C, (const float*)r, (float*)bc);
+    k_restrict<float><<<(unsigned)((C.n + 7) / 8), 256, 0, st>>>(F, C, (const float*)r, (float*)bc);
   else
-    k_restrict<double><<<blocks_for(C.n), kTpb, 0, st>>>(F, C, (const double*)r, (double*)bc);
+    k_restrict<double><<<(unsigned)((C.n + 7) / 8), 256, 0, st>>>(F, C, (const double*)r,
+                                                                 (double*)bc);
 }
 void launch_prolong_add(const LevelView& F, const LevelView& C, bool mixed, const void* uc, void* u,
                         hipStream_t st) {
@@ -417,16 +741,42 @@ void launch_prolong_add(const LevelView& F, const LevelView& C, bool mixed, cons
   else
     k_prolong_add<double><<<blocks_for(F.n), kTpb, 0, st>>>(F, C, (const double*)uc, (double*)u);
 }
-size_t coarse_pcg_work_bytes(int n) { return (size_t)4 * 3 * n * sizeof(double); }
-void launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                       int* iters_out, int max_iter, double rel, hipStream_t st) {
+
+// Coarsest levels smaller than this run in one work-group.
+constexpr int kGridMinRows = 128;
+
+size_t coarse_pcg_work_bytes(int n) {
+  return (size_t)4 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 256;
+}
+
+hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
+                             int* iters_out, int max_iter, double rel, hipStream_t st) {
+  const size_t vec = (size_t)4 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double));
+  double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
+  GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
+  const int maxb = mixed ? grid_blocks<float>() : grid_blocks<double>();
+  const int nb = std::min((L.n + kCgWaves - 1) / kCgWaves, maxb);
+  if (L.n >= kGridMinRows && nb >= 2) {
+    k_reset_bar<<<1, 64, 0, st>>>(bar);
+    if (mixed)
+      k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float*)x,
+                                                            (float*)work, part, bar, iters_out,
+                                                            max_iter, rel);
+    else
+      k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double*)x,
+                                                             (double*)work, part, bar, iters_out,
+                                                             max_iter, rel);
+    return hipGetLastError();
+  }
   if (mixed)
     k_coarse_pcg<float><<<1, kPcgThreads, 0, st>>>(L, (const float*)b, (float*)x, (float*)work,
                                                     iters_out, max_iter, rel);
   else
     k_coarse_pcg<double><<<1, kPcgThreads, 0, st>>>(L, (const double*)b, (double*)x,
                                                      (double*)work, iters_out, max_iter, rel);
+  return hipGetLastError();
 }
+
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st) {
   if (L.n > 0) k_spmv<<<ROWGRID(L)>>>(L, x, y);
 }

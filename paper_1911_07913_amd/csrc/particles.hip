@@ -213,29 +213,39 @@ __global__ void k_p2g_nodes(SceneDev s, LevelView L, Bricks B, const double* __r
   for (int a = 0; a < 3; ++a) vstar[3 * i + a] = vs[a];
 }
 
-// F_p(dv) = (I + dt sum_i v_i grad w_ip^T) F_p^n with v_i = v*_i + dv_i + alpha p_i.
+// Node velocities of a trial point, v_i = v*_i + dv_i + alpha p_i (dv, p
+// optional), written at each active node's padded index.
+__global__ void k_node_vel(LevelView L, const double* __restrict__ vstar,
+                           const double* __restrict__ dv, const double* __restrict__ pdir,
+                           double alpha, double4* __restrict__ wn) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  double vel[3];
+  for (int a = 0; a < 3; ++a) {
+    double d = 0.0;
+    if (dv) {
+      d = dv[3 * i + a];
+      if (pdir) d = d + alpha * pdir[3 * i + a];
+    }
+    vel[a] = vstar[3 * i + a] + d;
+  }
+  wn[L.nodes[i]] = make_double4(vel[0], vel[1], vel[2], 0.0);
+}
+
+// F_p(dv) = (I + dt sum_i v_i grad w_ip^T) F_p^n with v_i from k_node_vel.
 __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pidx_key,
-                                  const double* fp, const double* Fn, const double* vstar,
-                                  const double* dv, const double* pdir, double alpha, double dt,
-                                  double* F) {
+                                  const double* fp, const double* Fn,
+                                  const double4* __restrict__ wn, double dt, double* F) {
   Weights W;
   bspline_weights(fp, s.inv_dx, W);
   double gv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    int j = L.map[pidx_key + stencil_offset(L.g, k)];
+    const double4 wv = wn[pidx_key + stencil_offset(L.g, k)];
     double g[3];
     node_grad(W, kx, ky, kz, g);
-    double vel[3];
-    for (int a = 0; a < 3; ++a) {
-      double d = 0.0;
-      if (dv) {
-        d = dv[3 * j + a];
-        if (pdir) d = d + alpha * pdir[3 * j + a];
-      }
-      vel[a] = vstar[3 * j + a] + d;
-    }
+    const double vel[3] = {wv.x, wv.y, wv.z};
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) gv[3 * a + b] += vel[a] * g[b];
   }
@@ -256,13 +266,13 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
 __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                    const int* __restrict__ key, const double* __restrict__ Fn,
                                    const double* __restrict__ vol, const int* __restrict__ mat,
-                                   const double* __restrict__ vstar, double dt,
+                                   const double4* __restrict__ wn, double dt,
                                    double* __restrict__ Cp) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
-  particle_F(s, L, key[p], f + 3 * p, fn, vstar, nullptr, nullptr, 0.0, dt, F);
+  particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
   double C45[45];
   projected_dPdF(s.mats[mat[p]], F, dt * dt * vol[p], C45);
   for (int i = 0; i < 45; ++i) Cp[45 * (long long)p + i] = C45[i];
@@ -273,14 +283,13 @@ __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView 
 __global__ __launch_bounds__(256) void k_particle_eval(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                 const int* __restrict__ key, const double* __restrict__ Fn,
                                 const double* __restrict__ vol, const int* __restrict__ mat,
-                                const double* __restrict__ vstar, const double* __restrict__ dv,
-                                const double* __restrict__ pdir, double alpha, double dt,
+                                const double4* __restrict__ wn, double dt,
                                 double* __restrict__ psi_out, double* __restrict__ S_out) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
-  particle_F(s, L, key[p], f + 3 * p, fn, vstar, dv, pdir, alpha, dt, F);
+  particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
   double P[9];
   double ps = psi_and_piola(s.mats[mat[p]], F, P);
   double V = vol[p];
@@ -392,8 +401,7 @@ __device__ inline void von_mises(double* F, double mu, double ys) {
 __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                       const int* __restrict__ key, double* __restrict__ x,
                       double* __restrict__ v, double* __restrict__ C, double* __restrict__ Fn,
-                      const int* __restrict__ mat, const double* __restrict__ vstar,
-                      const double* __restrict__ dv, double dt) {
+                      const int* __restrict__ mat, const double4* __restrict__ wn, double dt) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double fp[3] = {f[3 * p], f[3 * p + 1], f[3 * p + 2]};
@@ -404,9 +412,8 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    int j = L.map[kp + stencil_offset(L.g, k)];
-    double vel[3];
-    for (int a = 0; a < 3; ++a) vel[a] = vstar[3 * j + a] + dv[3 * j + a];
+    const double4 wv = wn[kp + stencil_offset(L.g, k)];
+    const double vel[3] = {wv.x, wv.y, wv.z};
     double w = node_weight(W, kx, ky, kz);
     double g[3];
     node_grad(W, kx, ky, kz, g);
@@ -739,21 +746,31 @@ void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const d
                                                    fixed);
 }
 
+static void node_vel(const LevelView& L0, const double* vstar, const double* dv, const double* p,
+                     double alpha, double* wnode, hipStream_t st) {
+  if (L0.n > 0)
+    k_node_vel<<<blocks_for(L0.n), kTpb, 0, st>>>(L0, vstar, dv, p, alpha, (double4*)wnode);
+}
+
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
-                             const double* vstar, double dt, double* Cp, hipStream_t st) {
+                             const double* vstar, double dt, double* wnode, double* Cp,
+                             hipStream_t st) {
+  node_vel(L0, vstar, nullptr, nullptr, 0.0, wnode, st);
   if (n > 0)
-    k_particle_hessian<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat, vstar, dt,
-                                                       Cp);
+    k_particle_hessian<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat,
+                                                       (const double4*)wnode, dt, Cp);
 }
 
 void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
                           const int* key, const double* F, const double* vol, const int* mat,
                           const double* vstar, const double* dv, const double* p, double alpha,
-                          double dt, double* psi_out, double* S_out, hipStream_t st) {
+                          double dt, double* wnode, double* psi_out, double* S_out,
+                          hipStream_t st) {
+  node_vel(L0, vstar, dv, p, alpha, wnode, st);
   if (n > 0)
-    k_particle_eval<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat, vstar, dv, p,
-                                                    alpha, dt, psi_out, S_out);
+    k_particle_eval<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat,
+                                                    (const double4*)wnode, dt, psi_out, S_out);
 }
 
 void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, const double* f,
@@ -767,9 +784,11 @@ void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, co
 
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
-                const double* dv, double dt, hipStream_t st) {
+                const double* dv, double dt, double* wnode, hipStream_t st) {
+  node_vel(L0, vstar, dv, nullptr, 0.0, wnode, st);
   if (n > 0)
-    k_g2p<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, x, v, C, F, mat, vstar, dv, dt);
+    k_g2p<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, x, v, C, F, mat,
+                                          (const double4*)wnode, dt);
 }
 
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
