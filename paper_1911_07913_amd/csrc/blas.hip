@@ -10,6 +10,12 @@ constexpr int kTpb = 256;
 inline unsigned blocks_for(long long n, int tpb = kTpb) {
   return (unsigned)((n + tpb - 1) / tpb);
 }
+// Blocks of a reduction over n terms: about two terms per thread, between 64
+// and kRedBlocks.  Fixed for a given n, so sums are reproducible.
+inline int red_blocks(long long n) {
+  long long b = (n + 2 * kTpb - 1) / (2 * kTpb);
+  return (int)std::min<long long>(kRedBlocks, std::max<long long>(64, b));
+}
 
 __device__ inline double block_sum(double v, double* sh) {
   v = wave_sum(v);
@@ -32,7 +38,7 @@ __global__ void k_partial(long long n, int kind, const double* __restrict__ a,
                           const double* __restrict__ b, double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
     double v = (kind == 0) ? a[k] * b[k] : (kind == 1 ? a[k] : a[k] - b[k]);
     s += v;
   }
@@ -44,7 +50,7 @@ __global__ void k_partial3(long long n, const double* __restrict__ a, const doub
                            double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
     double x = a[k], y = b[k];
     s0 += x * y;
     s1 += x * x;
@@ -57,8 +63,8 @@ __global__ void k_partial3(long long n, const double* __restrict__ a, const doub
   double t2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
     partial[blockIdx.x] = t0;
-    partial[kRedBlocks + blockIdx.x] = t1;
-    partial[2 * kRedBlocks + blockIdx.x] = t2;
+    partial[gridDim.x + blockIdx.x] = t1;
+    partial[2 * gridDim.x + blockIdx.x] = t2;
   }
 }
 
@@ -67,7 +73,7 @@ __global__ void k_kinetic(int n, const double* __restrict__ m, const double* __r
                           const double* __restrict__ p, double alpha, double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
-  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += (int)gridDim.x * kTpb) {
     double a2 = 0.0, b2 = 0.0;
     for (int c = 0; c < 3; ++c) {
       double d = dv[3 * i + c];
@@ -86,7 +92,7 @@ __global__ void k_cn(int n, const double* __restrict__ g, const double* __restri
                      double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
-  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += (int)gridDim.x * kTpb) {
     double d = scale * xi[i];
     for (int c = 0; c < 3; ++c) {
       double q = g[3 * i + c] / d;
@@ -100,7 +106,7 @@ __global__ void k_cn(int n, const double* __restrict__ g, const double* __restri
 __global__ void k_maxspeed(int n, const double* __restrict__ v, double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
-  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += kRedBlocks * kTpb) {
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += (int)gridDim.x * kTpb) {
     double a = v[3 * i], b = v[3 * i + 1], c = v[3 * i + 2];
     s = fmax(s, sqrt(a * a + b * b + c * c));
   }
@@ -115,7 +121,7 @@ __global__ void k_maxspeed(int n, const double* __restrict__ v, double* __restri
   }
 }
 
-// Fixed-order final reduction of kRedBlocks partials (sum or max) into out.
+// Fixed-order final reduction of nparts partials (sum or max) into out.
 __global__ void k_finish(int nparts, int count, int is_max, const double* __restrict__ partial,
                          double* __restrict__ out) {
   __shared__ double sh[kTpb / 64];
@@ -162,7 +168,7 @@ __global__ void k_twoloop_update(long long n, const double* __restrict__ init,
   const bool write = init || xprev;
   const double al = xprev ? sign * coef[0] : 0.0;
   double acc = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
     double val = init ? -1.0 * init[k] : v[k];
     if (xprev) val = val + al * xprev[k];
     if (write) v[k] = val;
@@ -176,11 +182,12 @@ __global__ void k_twoloop_update(long long n, const double* __restrict__ init,
 
 // dot_out = sum of the partials; first loop: alpha_out = rho dot; second
 // loop: coef_out = alpha_in - rho dot.
-__global__ void k_finish_lbfgs(const double* __restrict__ partial, const double* __restrict__ rho,
-                               const double* __restrict__ alpha_in, double* __restrict__ dot_out,
-                               double* __restrict__ alpha_out, double* __restrict__ coef_out) {
+__global__ void k_finish_lbfgs(int nparts, const double* __restrict__ partial,
+                               const double* __restrict__ rho, const double* __restrict__ alpha_in,
+                               double* __restrict__ dot_out, double* __restrict__ alpha_out,
+                               double* __restrict__ coef_out) {
   __shared__ double sh[kTpb / 64];
-  double t = finish_sum(kRedBlocks, partial, sh);
+  double t = finish_sum(nparts, partial, sh);
   if (threadIdx.x == 0) {
     dot_out[0] = t;
     if (alpha_out) alpha_out[0] = rho[0] * t;
@@ -209,7 +216,7 @@ __global__ void k_secant(long long n, const double* __restrict__ gnew, const dou
                          double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)kRedBlocks * kTpb) {
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
     double x = gnew[k] - g[k];
     y[k] = x;
     double yv = sv[k];
@@ -224,8 +231,8 @@ __global__ void k_secant(long long n, const double* __restrict__ gnew, const dou
   double t2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
     partial[blockIdx.x] = t0;
-    partial[kRedBlocks + blockIdx.x] = t1;
-    partial[2 * kRedBlocks + blockIdx.x] = t2;
+    partial[gridDim.x + blockIdx.x] = t1;
+    partial[2 * gridDim.x + blockIdx.x] = t2;
   }
 }
 
@@ -296,36 +303,43 @@ void launch_finish_sum(int nparts, const double* partial, double* out, hipStream
 }
 void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
                 hipStream_t st) {
-  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 0, a, b, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+  const int nb = red_blocks(n);
+  k_partial<<<nb, kTpb, 0, st>>>(n, 0, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
 void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
                   hipStream_t st) {
-  k_partial3<<<kRedBlocks, kTpb, 0, st>>>(n, a, b, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 3, 0, partial, out);
+  const int nb = red_blocks(n);
+  k_partial3<<<nb, kTpb, 0, st>>>(n, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 3, 0, partial, out);
 }
 void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st) {
-  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 1, a, nullptr, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+  const int nb = red_blocks(n);
+  k_partial<<<nb, kTpb, 0, st>>>(n, 1, a, nullptr, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
 void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
                      hipStream_t st) {
-  k_partial<<<kRedBlocks, kTpb, 0, st>>>(n, 2, a, b, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+  const int nb = red_blocks(n);
+  k_partial<<<nb, kTpb, 0, st>>>(n, 2, a, b, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
 void launch_kinetic_delta(int n, const double* mass, const double* dv, const double* p,
                           double alpha, double* partial, double* out, hipStream_t st) {
-  k_kinetic<<<kRedBlocks, kTpb, 0, st>>>(n, mass, dv, p, alpha, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+  const int nb = red_blocks(3LL * n);
+  k_kinetic<<<nb, kTpb, 0, st>>>(n, mass, dv, p, alpha, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
 void launch_cn_sq(int n, const double* g, const double* xi, double scale, double* partial,
                   double* out, hipStream_t st) {
-  k_cn<<<kRedBlocks, kTpb, 0, st>>>(n, g, xi, scale, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 0, partial, out);
+  const int nb = red_blocks(3LL * n);
+  k_cn<<<nb, kTpb, 0, st>>>(n, g, xi, scale, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
 void launch_max_speed(int n, const double* v, double* partial, double* out, hipStream_t st) {
-  k_maxspeed<<<kRedBlocks, kTpb, 0, st>>>(n, v, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 1, 1, partial, out);
+  const int nb = red_blocks(3LL * n);
+  k_maxspeed<<<nb, kTpb, 0, st>>>(n, v, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 1, partial, out);
 }
 void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
                      hipStream_t st) {
@@ -334,11 +348,13 @@ void launch_axpy_dev(long long n, const double* a_dev, double sign, const double
 void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
                            const double* xprev, double* v, const double* dnext, double* partial,
                            hipStream_t st) {
-  k_twoloop_update<<<kRedBlocks, kTpb, 0, st>>>(n, init, coef, sign, xprev, v, dnext, partial);
+  k_twoloop_update<<<red_blocks(n), kTpb, 0, st>>>(n, init, coef, sign, xprev, v, dnext, partial);
 }
-void launch_finish_lbfgs(const double* partial, const double* rho, const double* alpha_in,
-                         double* dot_out, double* alpha_out, double* coef_out, hipStream_t st) {
-  k_finish_lbfgs<<<1, kTpb, 0, st>>>(partial, rho, alpha_in, dot_out, alpha_out, coef_out);
+void launch_finish_lbfgs(long long n, const double* partial, const double* rho,
+                         const double* alpha_in, double* dot_out, double* alpha_out,
+                         double* coef_out, hipStream_t st) {
+  k_finish_lbfgs<<<1, kTpb, 0, st>>>(red_blocks(n), partial, rho, alpha_in, dot_out, alpha_out,
+                                     coef_out);
 }
 void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
                         double* sv, hipStream_t st) {
@@ -346,8 +362,9 @@ void launch_step_update(long long n, const double* dv, double alpha, const doubl
 }
 void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
                    double* partial, double* out, hipStream_t st) {
-  k_secant<<<kRedBlocks, kTpb, 0, st>>>(n, gnew, g, y, sv, partial);
-  k_finish<<<1, kTpb, 0, st>>>(kRedBlocks, 3, 0, partial, out);
+  const int nb = red_blocks(n);
+  k_secant<<<nb, kTpb, 0, st>>>(n, gnew, g, y, sv, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 3, 0, partial, out);
 }
 void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st) {
   if (n > 0) k_axpy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);

@@ -733,7 +733,7 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
                             partial, st);
       for (int k = K - 1; k >= 0; --k) {
         int a = hist[k];
-        launch_finish_lbfgs(partial, P<double>(s->drho) + a, nullptr, P<double>(s->ddot) + a,
+        launch_finish_lbfgs(N, partial, P<double>(s->drho) + a, nullptr, P<double>(s->ddot) + a,
                             P<double>(s->dalpha) + a, nullptr, st);
         const double* dn = k > 0 ? P<double>(s->Sh[hist[k - 1]]) : nullptr;
         launch_twoloop_update(N, nullptr, P<double>(s->dalpha) + a, -1.0, P<double>(s->Yh[a]), q,
@@ -748,13 +748,13 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
                             partial, st);
       for (int k = 0; k < K; ++k) {
         int a = hist[k];
-        launch_finish_lbfgs(partial, P<double>(s->drho) + a, P<double>(s->dalpha) + a,
+        launch_finish_lbfgs(N, partial, P<double>(s->drho) + a, P<double>(s->dalpha) + a,
                             P<double>(s->ddot) + a, nullptr, P<double>(s->dcoef) + a, st);
         const double* dn = k + 1 < K ? P<double>(s->Yh[hist[k + 1]]) : g;
         launch_twoloop_update(N, nullptr, P<double>(s->dcoef) + a, 1.0, P<double>(s->Sh[a]), r, dn,
                               partial, st);
       }
-      launch_finish_lbfgs(partial, nullptr, nullptr, dscal + S_GP, nullptr, nullptr, st);
+      launch_finish_lbfgs(N, partial, nullptr, nullptr, dscal + S_GP, nullptr, nullptr, st);
     }
     // -- descent check and the first trial in one readback
     int trial = 1 - s->pc;

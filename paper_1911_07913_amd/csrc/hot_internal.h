@@ -216,7 +216,7 @@ size_t coarse_pcg_work_bytes(int n);
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st);
 
 // blas.hip: deterministic reductions and vector updates on FP64 node vectors.
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;  // most partials a reduction writes
 void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
                 hipStream_t st);
 void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
@@ -244,8 +244,9 @@ void launch_twoloop_update(long long n, const double* init, const double* coef, 
                            const double* xprev, double* v, const double* dnext, double* partial,
                            hipStream_t st);
 // dot_out = sum(partial); alpha_out = rho*dot; coef_out = alpha_in - rho*dot
-void launch_finish_lbfgs(const double* partial, const double* rho, const double* alpha_in,
-                         double* dot_out, double* alpha_out, double* coef_out, hipStream_t st);
+void launch_finish_lbfgs(long long n, const double* partial, const double* rho,
+                         const double* alpha_in, double* dot_out, double* alpha_out,
+                         double* coef_out, hipStream_t st);
 // dvt = dv + alpha p, sv = dvt - dv
 void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
                         double* sv, hipStream_t st);
