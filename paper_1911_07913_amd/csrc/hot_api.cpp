@@ -362,6 +362,13 @@ SetCounts count_sets(const hot_params* p, int64_t n, const double* x) {
   return c;
 }
 
+// Points of the padded grid of level m.
+long long gm_level_ptotal(const hot_params* p, int m) {
+  GridGeom g = make_geom(p->grid_cells[0] + 1, p->grid_cells[1] + 1, p->grid_cells[2] + 1);
+  for (int k = 0; k < m; ++k) g = make_geom(g.dims[0] / 2 + 1, g.dims[1] / 2 + 1, g.dims[2] / 2 + 1);
+  return g.ptotal;
+}
+
 // Device bytes a scene allocates for a particle set of this shape: every
 // buffer the step uses, with the 25% growth headroom each allocation takes.
 // Exact for the initial configuration; a scene whose active grid grows later
@@ -400,7 +407,8 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
     double nm = (double)c.nodes[m];
     A(nm * 4); A(nm * kRowStride * 8); A(nm * 72); A(nm * 24); A(nm * 3); A(nm * 16);
     if (mx) { A(nm * kRowStride * 2); A(nm * 36); A(nm * 12); }
-    for (int k = 0; k < 4; ++k) A(nm * 3 * vsz);
+    A(nm * 3 * vsz); A(nm * 3 * vsz);  // b, r
+    A((double)gm_level_ptotal(p, m) * 4 * vsz); A((double)gm_level_ptotal(p, m) * 4 * vsz);  // u, t
   }
   // level-0 node data, solver vectors and history, row segments
   const double n0 = (double)c.nodes[0];
@@ -430,9 +438,9 @@ hot_status alloc_level(hot_scene* s, int m, int n) {
     TRY(ensure(s, L.diag32, (size_t)n * 12));
   }
   TRY(ensure(s, L.b, (size_t)n * 3 * vsz));
-  TRY(ensure(s, L.u, (size_t)n * 3 * vsz));
+  TRY(ensure(s, L.u, (size_t)L.g.ptotal * 4 * vsz));
   TRY(ensure(s, L.r, (size_t)n * 3 * vsz));
-  TRY(ensure(s, L.t, (size_t)n * 3 * vsz));
+  TRY(ensure(s, L.t, (size_t)L.g.ptotal * 4 * vsz));
   L.n = n;
   return HOT_OK;
 }
@@ -617,11 +625,7 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
       us[m] = s->L[m].u.p;
     }
   }
-  long long n3 = (long long)s->L[0].n * 3;
-  if (mx)
-    launch_to_f64(n3, P<float>(s->L[0].u), r, st);
-  else
-    HIPCHK(hipMemcpyAsync(r, s->L[0].u.p, n3 * 8, hipMemcpyDeviceToDevice, st));
+  launch_dense_out(view(s, 0), mx, s->L[0].u.p, r, st);
   return HOT_OK;
 }
 

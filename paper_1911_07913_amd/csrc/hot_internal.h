@@ -202,8 +202,13 @@ void launch_to_bf16(const LevelView& L, hipStream_t st);
 void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u, hipStream_t st);
 void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,
                      hipStream_t st);
+// The V-cycle iterate u of every level (and the smoother's output) is stored
+// on the level's padded dense grid as 4-vectors (double4 or float4); b and r
+// are compact [n][3].
 void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u, void* u_out,
                    hipStream_t st);
+// compact FP64 copy of a level's dense iterate
+void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out, hipStream_t st);
 void launch_restrict(const LevelView& F, const LevelView& Cv, bool mixed, const void* r,
                      void* bc, hipStream_t st);
 void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, const void* uc,

@@ -55,6 +55,22 @@ struct MatOf<float> {
   static __device__ const float* diag(const LevelView& L) { return L.diag32; }
 };
 
+// Level vectors that sweeps gather from (the smoother iterate u and its
+// ping-pong copy) live on the level's padded dense grid, one 4-vector per grid
+// point (x, y, z, unused): a neighbour's entries are one 16- or 32-byte load at
+// an address known from the row's own grid index, with no map lookup.  Only
+// active points are ever written or read.
+template <typename V>
+struct Vec4Of;
+template <>
+struct Vec4Of<double> {
+  typedef double4 type;
+};
+template <>
+struct Vec4Of<float> {
+  typedef float4 type;
+};
+
 // y = H_i . x for one row, computed by a whole wave; result valid in all lanes.
 // Lane l owns the blocks of slots l and l + 64: it reads their 9 entries with
 // coalesced loads (entry-major row layout) and the neighbour's 3 vector
@@ -130,17 +146,18 @@ struct SweepRows<float> {
 };
 
 template <typename V, int R>
-__device__ inline void rows_matvec(const LevelView& L, int i0, const V* __restrict__ x, int lane,
+__device__ inline void rows_matvec(const LevelView& L, int i0,
+                                   const typename Vec4Of<V>::type* __restrict__ x4, int lane,
                                    V (&y)[R][3]) {
   typedef typename MatOf<V>::type M;
   V h[R][2][9];
-  int jn[R][2];
+  int jp[R][2];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = i0 + r;
     const bool live = i < L.n;
     const M* Hrow = MatOf<V>::H(L) + (long long)(live ? i : 0) * kRowStride;
-    const long long pn = live ? L.nodes[i] : 0;
+    const int pn = live ? L.nodes[i] : 0;
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     if (live)
       for (int q = 0; q < 4; ++q) w[q] = L.pat[4 * i + q];
@@ -149,7 +166,7 @@ __device__ inline void rows_matvec(const LevelView& L, int i0, const V* __restri
     for (int k = 0; k < 2; ++k) {
       const int s = SweepRows<V>::slot(lane, k);
       pr[k] = slot_present(w, s);
-      jn[r][k] = pr[k] ? L.map[pn + slot_offset(L.g, s)] : -1;
+      jp[r][k] = pr[k] ? pn + slot_offset(L.g, s) : -1;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) SweepRows<V>::load(Hrow, c, lane, pr[0], pr[1], h[r][0][c], h[r][1][c]);
@@ -159,9 +176,9 @@ __device__ inline void rows_matvec(const LevelView& L, int i0, const V* __restri
     V a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (jn[r][k] >= 0) {
-        const V* xj = x + 3 * (long long)jn[r][k];
-        V x0 = xj[0], x1 = xj[1], x2 = xj[2];
+      if (jp[r][k] >= 0) {
+        const typename Vec4Of<V>::type xv = x4[jp[r][k]];
+        const V x0 = xv.x, x1 = xv.y, x2 = xv.z;
         a0 += h[r][k][0] * x0 + h[r][k][1] * x1 + h[r][k][2] * x2;
         a1 += h[r][k][3] * x0 + h[r][k][4] * x1 + h[r][k][5] * x2;
         a2 += h[r][k][6] * x0 + h[r][k][7] * x1 + h[r][k][8] * x2;
@@ -171,6 +188,16 @@ __device__ inline void rows_matvec(const LevelView& L, int i0, const V* __restri
     y[r][1] = wave_sum_t(a1);
     y[r][2] = wave_sum_t(a2);
   }
+}
+
+// Component c of the dense 4-vector at grid point pn.
+template <typename V>
+__device__ inline V& comp(typename Vec4Of<V>::type* v4, int pn, int c) {
+  return reinterpret_cast<V*>(v4)[4 * (long long)pn + c];
+}
+template <typename V>
+__device__ inline V comp(const typename Vec4Of<V>::type* v4, int pn, int c) {
+  return reinterpret_cast<const V*>(v4)[4 * (long long)pn + c];
 }
 
 // ---------------------------------------------------------------- RAP
@@ -260,27 +287,34 @@ __global__ void k_to_bf16(LevelView L) {
 }
 
 // ---------------------------------------------------------------- V-cycle
-// First smoothing sweep from u = 0: u = D~^{-1} b.
+// First smoothing sweep from u = 0: u = D~^{-1} b (u dense).
 template <typename V>
-__global__ void k_jacobi_first(LevelView L, const V* __restrict__ b, V* __restrict__ u) {
+__global__ void k_jacobi_first(LevelView L, const V* __restrict__ b,
+                               typename Vec4Of<V>::type* __restrict__ u4) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   const V* Di = MatOf<V>::Dinv(L) + 9 * (long long)i;
   V b0 = b[3 * i], b1 = b[3 * i + 1], b2 = b[3 * i + 2];
-  for (int g = 0; g < 3; ++g) u[3 * i + g] = Di[3 * g] * b0 + Di[3 * g + 1] * b1 + Di[3 * g + 2] * b2;
+  typename Vec4Of<V>::type o;
+  o.x = Di[0] * b0 + Di[1] * b1 + Di[2] * b2;
+  o.y = Di[3] * b0 + Di[4] * b1 + Di[5] * b2;
+  o.z = Di[6] * b0 + Di[7] * b1 + Di[8] * b2;
+  o.w = 0;
+  u4[L.nodes[i]] = o;
 }
 
 constexpr int kRowWaves = 4;
 
-// r = b - H u (one wave per R consecutive rows)
+// r = b - H u (one wave per R consecutive rows; u dense, r compact)
 template <typename V, int R>
 __global__ __launch_bounds__(256) void k_residual(LevelView L, const V* __restrict__ b,
-                                                  const V* __restrict__ u, V* __restrict__ r) {
+                                                  const typename Vec4Of<V>::type* __restrict__ u4,
+                                                  V* __restrict__ r) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int i0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
   if (i0 >= L.n) return;
   V y[R][3];
-  rows_matvec<V, R>(L, i0, u, lane, y);
+  rows_matvec<V, R>(L, i0, u4, lane, y);
   if (lane < 3 * R) {
     const int rr = lane / 3, c = lane - 3 * rr;
     const int i = i0 + rr;
@@ -293,15 +327,17 @@ __global__ __launch_bounds__(256) void k_residual(LevelView L, const V* __restri
   }
 }
 
-// l1 block-Jacobi sweep: u_out = u + D~^{-1} (b - H u), projected.
+// l1 block-Jacobi sweep: u_out = u + D~^{-1} (b - H u), projected (u, u_out
+// dense).
 template <typename V, int R>
 __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict__ b,
-                                                const V* __restrict__ u, V* __restrict__ uo) {
+                                                const typename Vec4Of<V>::type* __restrict__ u4,
+                                                typename Vec4Of<V>::type* __restrict__ uo4) {
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int i0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
   if (i0 >= L.n) return;
   V y[R][3];
-  rows_matvec<V, R>(L, i0, u, lane, y);
+  rows_matvec<V, R>(L, i0, u4, lane, y);
   if (lane < 3 * R) {
     const int rr = lane / 3, c = lane - 3 * rr;
     const int i = i0 + rr;
@@ -314,11 +350,12 @@ __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict
         y2 = y[q][2];
       }
     if (i < L.n) {
+      const int pn = L.nodes[i];
       const V* Di = MatOf<V>::Dinv(L) + 9 * (long long)i;
       V r0 = b[3 * i] - y0, r1 = b[3 * i + 1] - y1, r2 = b[3 * i + 2] - y2;
       V upd = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
-      V out = u[3 * i + c] + upd;
-      uo[3 * i + c] = L.free_dof[3 * i + c] ? out : (V)0;
+      V out = comp<V>(u4, pn, c) + upd;
+      comp<V>(uo4, pn, c) = L.free_dof[3 * i + c] ? out : (V)0;
     }
   }
 }
@@ -358,13 +395,17 @@ __global__ __launch_bounds__(256) void k_restrict(LevelView F, LevelView C,
   }
 }
 
-// u_i += sum_J P~_iJ u^c_J over the (at most 8) parents of fine node i.
+// u_i += sum_J P~_iJ u^c_J over the (at most 8) parents of fine node i (both
+// dense: a parent's grid index needs no map lookup).
 template <typename V>
-__global__ void k_prolong_add(LevelView F, LevelView C, const V* __restrict__ uc, V* __restrict__ u) {
+__global__ void k_prolong_add(LevelView F, LevelView C,
+                              const typename Vec4Of<V>::type* __restrict__ uc4,
+                              typename Vec4Of<V>::type* __restrict__ u4) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= F.n) return;
+  const int pn = F.nodes[i];
   int x, y, z;
-  unpidx(F.g, F.nodes[i], x, y, z);
+  unpidx(F.g, pn, x, y, z);
   int Px[2], Py[2], Pz[2];
   V wx[2], wy[2], wz[2];
   int nx, ny, nz;
@@ -378,15 +419,27 @@ __global__ void k_prolong_add(LevelView F, LevelView C, const V* __restrict__ uc
   for (int a = 0; a < nx; ++a)
     for (int b = 0; b < ny; ++b)
       for (int c = 0; c < nz; ++c) {
-        int J = C.map[pidx(C.g, Px[a], Py[b], Pz[c])];
+        const typename Vec4Of<V>::type v = uc4[pidx(C.g, Px[a], Py[b], Pz[c])];
         V w = wx[a] * wy[b] * wz[c];
-        s0 += w * uc[3 * J];
-        s1 += w * uc[3 * J + 1];
-        s2 += w * uc[3 * J + 2];
+        s0 += w * v.x;
+        s1 += w * v.y;
+        s2 += w * v.z;
       }
-  if (F.free_dof[3 * i]) u[3 * i] += s0;
-  if (F.free_dof[3 * i + 1]) u[3 * i + 1] += s1;
-  if (F.free_dof[3 * i + 2]) u[3 * i + 2] += s2;
+  if (F.free_dof[3 * i]) comp<V>(u4, pn, 0) += s0;
+  if (F.free_dof[3 * i + 1]) comp<V>(u4, pn, 1) += s1;
+  if (F.free_dof[3 * i + 2]) comp<V>(u4, pn, 2) += s2;
+}
+
+// Level-0 iterate (dense) to the compact FP64 output of the cycle.
+template <typename V>
+__global__ void k_dense_out(LevelView L, const typename Vec4Of<V>::type* __restrict__ u4,
+                            double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  const typename Vec4Of<V>::type v = u4[L.nodes[i]];
+  out[3 * i] = (double)v.x;
+  out[3 * i + 1] = (double)v.y;
+  out[3 * i + 2] = (double)v.z;
 }
 
 // ---------------------------------------------------------------- coarsest
@@ -412,16 +465,16 @@ __device__ inline V block_dot(const V* a, const V* b, int n, V* red) {
 }
 
 template <typename V>
-__global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(LevelView L, const V* __restrict__ b,
-                                                            V* __restrict__ x, V* __restrict__ work,
-                                                            int* __restrict__ iters_out, int max_iter,
-                                                            double rel) {
+__global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(
+    LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
+    V* __restrict__ work, int* __restrict__ iters_out, int max_iter, double rel) {
   __shared__ V red[kPcgWaves];
   const int n3 = 3 * L.n;
   V* r = work;
   V* z = r + n3;
   V* p = z + n3;
   V* q = p + n3;
+  V* x = q + n3;  // compact iterate, scattered to the dense x4 at the end
   const V* dg = MatOf<V>::diag(L);
   for (int k = threadIdx.x; k < n3; k += kPcgThreads) {
     V bk = b[k];
@@ -463,6 +516,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(LevelView L, const V
       for (int k = threadIdx.x; k < n3; k += kPcgThreads) p[k] = z[k] + beta * p[k];
     }
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n3; k += kPcgThreads) comp<V>(x4, L.nodes[k / 3], k % 3) = x[k];
   if (threadIdx.x == 0) *iters_out = it;
 }
 
@@ -559,9 +614,9 @@ __device__ inline void block_partial(double loc, double* part, double* red) {
 
 template <typename V>
 __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
-    LevelView L, const V* __restrict__ b, V* __restrict__ x, V* __restrict__ work,
-    double* __restrict__ part, GridBar* __restrict__ bar, int* __restrict__ iters_out,
-    int max_iter, double rel) {
+    LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
+    V* __restrict__ work, double* __restrict__ part, GridBar* __restrict__ bar,
+    int* __restrict__ iters_out, int max_iter, double rel) {
   __shared__ double red[kCgWaves];
   __shared__ double s_val;
   __shared__ int s_ok;
@@ -570,6 +625,7 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
   V* z = r + n3;
   V* p = z + n3;
   V* q = p + n3;
+  V* x = q + n3;  // compact iterate, scattered to the dense x4 at the end
   double* part_pq = part;
   double* part_rz = part + kCgMaxBlocks;
   const V* dg = MatOf<V>::diag(L);
@@ -636,6 +692,8 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
       if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
     }
   }
+  for (int row = gw; row < n; row += nw)
+    if (lane < 3) comp<V>(x4, L.nodes[row], lane) = x[3 * row + lane];
   if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
 }
 
@@ -682,29 +740,31 @@ void launch_to_bf16(const LevelView& L, hipStream_t st) {
 void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u, hipStream_t st) {
   if (L.n == 0) return;
   if (mixed)
-    k_jacobi_first<float><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const float*)b, (float*)u);
+    k_jacobi_first<float><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const float*)b, (float4*)u);
   else
-    k_jacobi_first<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double*)b, (double*)u);
+    k_jacobi_first<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double*)b, (double4*)u);
 }
 // Levels with at least this many rows run several rows per wave.
 constexpr int kMultiRowMin = 65536;
 
 template <typename V>
-void sweep_launch(bool smooth, const LevelView& L, const V* b, const V* u, V* out,
+void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, void* out,
                   hipStream_t st) {
+  typedef typename Vec4Of<V>::type V4;
   constexpr int R = SweepRows<V>::R;
+  const V4* u4 = (const V4*)u;
   if (L.n >= kMultiRowMin) {
     unsigned g = (unsigned)((L.n + kRowWaves * R - 1) / (kRowWaves * R));
     if (smooth)
-      k_smooth<V, R><<<g, 256, 0, st>>>(L, b, u, out);
+      k_smooth<V, R><<<g, 256, 0, st>>>(L, b, u4, (V4*)out);
     else
-      k_residual<V, R><<<g, 256, 0, st>>>(L, b, u, out);
+      k_residual<V, R><<<g, 256, 0, st>>>(L, b, u4, (V*)out);
   } else {
     unsigned g = (unsigned)((L.n + kRowWaves - 1) / kRowWaves);
     if (smooth)
-      k_smooth<V, 1><<<g, 256, 0, st>>>(L, b, u, out);
+      k_smooth<V, 1><<<g, 256, 0, st>>>(L, b, u4, (V4*)out);
     else
-      k_residual<V, 1><<<g, 256, 0, st>>>(L, b, u, out);
+      k_residual<V, 1><<<g, 256, 0, st>>>(L, b, u4, (V*)out);
   }
 }
 
@@ -712,17 +772,17 @@ void launch_residual(const LevelView& L, bool mixed, const void* b, const void* 
                      hipStream_t st) {
   if (L.n == 0) return;
   if (mixed)
-    sweep_launch<float>(false, L, (const float*)b, (const float*)u, (float*)r, st);
+    sweep_launch<float>(false, L, (const float*)b, u, r, st);
   else
-    sweep_launch<double>(false, L, (const double*)b, (const double*)u, (double*)r, st);
+    sweep_launch<double>(false, L, (const double*)b, u, r, st);
 }
 void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u, void* uo,
                    hipStream_t st) {
   if (L.n == 0) return;
   if (mixed)
-    sweep_launch<float>(true, L, (const float*)b, (const float*)u, (float*)uo, st);
+    sweep_launch<float>(true, L, (const float*)b, u, uo, st);
   else
-    sweep_launch<double>(true, L, (const double*)b, (const double*)u, (double*)uo, st);
+    sweep_launch<double>(true, L, (const double*)b, u, uo, st);
 }
 void launch_restrict(const LevelView& F, const LevelView& C, bool mixed, const void* r, void* bc,
                      hipStream_t st) {
@@ -737,21 +797,29 @@ void launch_prolong_add(const LevelView& F, const LevelView& C, bool mixed, cons
                         hipStream_t st) {
   if (F.n == 0) return;
   if (mixed)
-    k_prolong_add<float><<<blocks_for(F.n), kTpb, 0, st>>>(F, C, (const float*)uc, (float*)u);
+    k_prolong_add<float><<<blocks_for(F.n), kTpb, 0, st>>>(F, C, (const float4*)uc, (float4*)u);
   else
-    k_prolong_add<double><<<blocks_for(F.n), kTpb, 0, st>>>(F, C, (const double*)uc, (double*)u);
+    k_prolong_add<double><<<blocks_for(F.n), kTpb, 0, st>>>(F, C, (const double4*)uc,
+                                                            (double4*)u);
+}
+void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out, hipStream_t st) {
+  if (L.n == 0) return;
+  if (mixed)
+    k_dense_out<float><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const float4*)u, out);
+  else
+    k_dense_out<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double4*)u, out);
 }
 
 // Coarsest levels smaller than this run in one work-group.
 constexpr int kGridMinRows = 128;
 
 size_t coarse_pcg_work_bytes(int n) {
-  return (size_t)4 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 256;
+  return (size_t)5 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 512;
 }
 
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
                              int* iters_out, int max_iter, double rel, hipStream_t st) {
-  const size_t vec = (size_t)4 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double));
+  const size_t vec = (size_t)5 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double));
   double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
   GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
   const int maxb = mixed ? grid_blocks<float>() : grid_blocks<double>();
@@ -759,20 +827,20 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   if (L.n >= kGridMinRows && nb >= 2) {
     k_reset_bar<<<1, 64, 0, st>>>(bar);
     if (mixed)
-      k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float*)x,
+      k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float4*)x,
                                                             (float*)work, part, bar, iters_out,
                                                             max_iter, rel);
     else
-      k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double*)x,
+      k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double4*)x,
                                                              (double*)work, part, bar, iters_out,
                                                              max_iter, rel);
     return hipGetLastError();
   }
   if (mixed)
-    k_coarse_pcg<float><<<1, kPcgThreads, 0, st>>>(L, (const float*)b, (float*)x, (float*)work,
+    k_coarse_pcg<float><<<1, kPcgThreads, 0, st>>>(L, (const float*)b, (float4*)x, (float*)work,
                                                     iters_out, max_iter, rel);
   else
-    k_coarse_pcg<double><<<1, kPcgThreads, 0, st>>>(L, (const double*)b, (double*)x,
+    k_coarse_pcg<double><<<1, kPcgThreads, 0, st>>>(L, (const double*)b, (double4*)x,
                                                      (double*)work, iters_out, max_iter, rel);
   return hipGetLastError();
 }
