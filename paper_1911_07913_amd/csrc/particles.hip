@@ -6,6 +6,8 @@
 // results are reproducible run to run.
 #include "mpm_math.h"
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 namespace hot {
 namespace {
 
@@ -456,12 +458,16 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // x-line.  The group sweeps the base cells c = x_first - 2 .. x_last of the 9
 // cell columns (c, y - ky, z - kz), ky, kz in {0,1,2}; a particle of column
 // (ky, kz) in cell c touches rows c + r, r in {0,1,2}, of this segment, with
-// stencil offset k = (r, ky, kz).  Thread (r, l, g) owns block row g of block
-// (row c + r, stencil node l) and accumulates it in registers over the cell's
-// particles; per cell the sums go to a 3-row sliding window in LDS.  After
-// cell c, row c receives nothing more: it is finalised (mass, Dirichlet
-// projection, smoother inverse) and written once.  Every block of every
-// particle is computed exactly once; no atomics.
+// stencil offset k = (r, ky, kz).  For one cell column the blocks are a dense
+// contraction over the column's particles p and the component eps:
+//   B[(r, g, d)][l] = sum_(p, eps) Z_p[(r, g, d)][eps] a_p[l][eps],
+// Z_p[(r, g, d)][eps] = sum_b a_p[k][b] C_p[3g + b][3d + eps] (k = (r, ky, kz)),
+// a 27 x 27 x 3P product that the four waves compute as 2 x 2 tiles of FP64
+// 16x16x4 matrix-core instructions, accumulating in registers over the
+// column's particles.  Per cell column the sums go to a 3-row sliding window in
+// LDS.  After cell c, row c receives nothing more: it is finalised (mass,
+// Dirichlet projection, smoother inverse) and written once.  Every block of
+// every particle is computed exactly once; no atomics.
 constexpr int kAsmChunk = 8;   // particles staged per pass
 constexpr int kPData = 57;     // f (3), F (9), C (45)
 constexpr int kStageRegs = (kAsmChunk * kPData + 255) / 256;
@@ -474,23 +480,49 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
   dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
 }
 
+// Entries (c, s) of a block row owned by one of 256 threads, decomposed once:
+// LDS index, offset of the slot's neighbour in the segment's constrained-flag
+// window (kNoNb for the diagonal slot), and block row g of off-diagonal slots
+// (-1 for the diagonal slot and for unused items).
+constexpr int kFinItems = (kBlock * kSlots + 255) / 256;
+constexpr int kNoNb = -(1 << 30);
+struct FinRoles {
+  int idx[kFinItems];
+  int nb[kFinItems];
+  int g[kFinItems];
+};
+
+__device__ inline void fin_roles(int tid, int nxw, FinRoles& fr) {
+#pragma unroll
+  for (int k = 0; k < kFinItems; ++k) {
+    const int e = tid + 256 * k;
+    const int c = e / kSlots, sl = e - c * kSlots;
+    const bool valid = e < kBlock * kSlots;
+    fr.idx[k] = valid ? c * kSlotPad + sl : -1;
+    const bool center = sl == kCenter;
+    fr.nb[k] = (!valid || center) ? kNoNb
+                                  : (sl % 5 - 2) + nxw * ((sl / 5) % 5 + 5 * (sl / 25));
+    fr.g[k] = (!valid || center) ? -1 : c / 3;
+  }
+}
+
 // Block-level finalisation of level-0 row i held in LDS (256 threads): mass
 // on the diagonal, Dirichlet projection (constrained row -> m_i I, blocks to
 // constrained neighbours -> 0), exact-zero diagonal rule, write-out, scalar
 // diagonal and the l1 block-Jacobi inverse.  nbf holds the constrained flags
 // of the 5x5 y-z neighbourhood of the segment's x-line, x-major from xw0.
-__device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0, int nxw,
+__device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
                                           const LevelView& L, const uint8_t* nbf,
-                                          bool row_fixed, double mass_i, double* red) {
+                                          const FinRoles& fr, bool row_fixed, double mass_i,
+                                          double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < kBlock * kSlots; e += 256) {
-    int c = e / kSlots, s = e - c * kSlots;
-    bool z = row_fixed;
-    if (!z && s != kCenter) {
-      int dx = s % 5 - 2, dy = (s / 5) % 5 - 2, dz = s / 25 - 2;
-      z = nbf[(xi + dx - xw0) + nxw * ((dy + 2) + 5 * (dz + 2))] != 0;
+  const uint8_t* nbx = nbf + (xi - xw0);
+#pragma unroll
+  for (int k = 0; k < kFinItems; ++k) {
+    if (fr.idx[k] >= 0) {
+      bool z = row_fixed || (fr.nb[k] != kNoNb && nbx[fr.nb[k]] != 0);
+      if (z) acc[fr.idx[k]] = 0.0;
     }
-    if (z) acc[c * kSlotPad + s] = 0.0;
   }
   __syncthreads();
   if (tid == 0) {
@@ -505,16 +537,15 @@ __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0, i
   __syncthreads();
   double l1[3] = {0.0, 0.0, 0.0};
   double* Hrow = L.H + (long long)i * kRowStride;
-  for (int e = tid; e < kBlock * kSlots; e += 256) {
-    int c = e / kSlots, s = e - c * kSlots;
-    double v = acc[c * kSlotPad + s];
-    Hrow[c * kSlotPad + s] = v;
-    if (s != kCenter) {
-      int g = c / 3;
-      double av = fabs(v);
-      l1[0] += (g == 0) ? av : 0.0;
-      l1[1] += (g == 1) ? av : 0.0;
-      l1[2] += (g == 2) ? av : 0.0;
+#pragma unroll
+  for (int k = 0; k < kFinItems; ++k) {
+    if (fr.idx[k] >= 0) {
+      double v = acc[fr.idx[k]];
+      Hrow[fr.idx[k]] = v;
+      const double av = fabs(v);
+      l1[0] += (fr.g[k] == 0) ? av : 0.0;
+      l1[1] += (fr.g[k] == 1) ? av : 0.0;
+      l1[2] += (fr.g[k] == 2) ? av : 0.0;
     }
   }
   for (int g = 0; g < 3; ++g) {
@@ -600,9 +631,46 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
     z_c1[k] = tri9(3 * z_g[k] + 1, z_de[k]) - z_c0[k];
     z_c2[k] = tri9(3 * z_g[k] + 2, z_de[k]) - z_c0[k];
   }
-  const bool blk_thread = tid < 243;
-  const int br = tid / 81, bl = (tid / 3) % 27, bg = tid % 3;
-  const int blx = bl % 3, bly = (bl / 3) % 3, blz = bl / 9;
+  // matrix-core roles: wave w owns output tile (rows 16 tile_m.., columns
+  // 16 tile_n..) of the 27 x 27 product; lane l feeds A[l % 16][l / 16] and
+  // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3
+  const int wave = tid >> 6, lane = tid & 63;
+  const int tile_m = wave >> 1, tile_n = wave & 1;
+  const int am = tile_m * 16 + (lane & 15);      // A row: (r, g, d)
+  const bool am_ok = am < 27;
+  const int amc = am_ok ? am : 0;                // clamped for addressing
+  const int am_r = amc / 9, am_g = (amc % 9) / 3, am_d = amc % 3;
+  const int bn = tile_n * 16 + (lane & 15);      // B column: stencil node l
+  const bool bn_ok = bn < 27;
+  const int bnc = bn_ok ? bn : 0;
+  const int kq = lane >> 4;                      // k offset within a 4-step
+  int dm_r[4], dm_e[4];                          // D rows held by this lane
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = tile_m * 16 + kq + 4 * v;
+    dm_r[v] = (m < 27) ? m / 9 : 3;
+    dm_e[v] = (m < 27) ? 3 * ((m % 9) / 3) + m % 3 : 0;
+  }
+  const int dn = tile_n * 16 + (lane & 15);      // D column: stencil node l
+  const int dnx = dn % 3, dny = (dn / 3) % 3, dnz = dn / 9;
+  // window slot of (node l, row r, column ky, kz) = dsl0 - r - 5 ky - 25 kz
+  const int dsl0 = (dnx + 2) + 5 * (dny + 2) + 25 * (dnz + 2);
+  // zv[q][r][g][3d + e] and av[q][l][e] share the per-particle stride of 108
+  // doubles: operand k = (q, e) of step st sits at koff[st] past the lane's base
+  static_assert(sizeof(zv[0]) == sizeof(av[0]), "zv/av particle strides differ");
+  constexpr int kPStride = (int)(sizeof(av[0]) / sizeof(double));
+  const int zbase = am_r * 36 + am_g * 12 + 3 * am_d;
+  const int abase = bnc * 4;
+  int koff[kAsmChunk * 3 / 4];
+#pragma unroll
+  for (int st = 0; st < kAsmChunk * 3 / 4; ++st) {
+    const int k = 4 * st + kq;
+    koff[st] = (k / 3) * kPStride + (k % 3);
+  }
+  const double* zflat = &zv[0][0][0][0];
+  const double* aflat = &av[0][0][0];
+  FinRoles fr;
+  fin_roles(tid, nxw, fr);
   __syncthreads();
   auto next_job = [&](int v, int t0, int& nv, int& nt) {
     if (v >= 0 && t0 + kAsmChunk < mcnt[v]) {
@@ -652,13 +720,12 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
   for (int ci = 0; ci < ncx; ++ci) {
     const int c = xa - 2 + ci;
     const int rlo = max(0, xa - c), rhi = min(2, xb - c);
-    const bool blk_active = blk_thread && br >= rlo && br <= rhi;
     for (int col = 0; col < 9; ++col) {
       const int v = ci * 9 + col;
       const int cnt = mcnt[v];
       if (cnt == 0) continue;
       const int ky = col % 3, kz = col / 3;
-      double acc3[3] = {0.0, 0.0, 0.0};
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
       for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
         const int np = min(kAsmChunk, cnt - t0);
 #pragma unroll
@@ -694,32 +761,38 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
           }
         }
         __syncthreads();
-        if (blk_active) {
-          for (int q = 0; q < np; ++q) {
-            const double2* z2 = reinterpret_cast<const double2*>(&zv[q][br][bg][0]);
-            const double2* a2 = reinterpret_cast<const double2*>(&av[q][bl][0]);
-            double2 z01 = z2[0], z23 = z2[1], z45 = z2[2], z67 = z2[3], z89 = z2[4];
-            double2 a01 = a2[0], a2x = a2[1];
-            double al0 = a01.x, al1 = a01.y, al2 = a2x.x;
-            acc3[0] += z01.x * al0 + z01.y * al1 + z23.x * al2;
-            acc3[1] += z23.y * al0 + z45.x * al1 + z45.y * al2;
-            acc3[2] += z67.x * al0 + z67.y * al1 + z89.x * al2;
+        // B[(r, g, d)][l] += sum over the chunk's (p, eps), four at a time
+        {
+          const bool a_ok = am_ok && am_r >= rlo && am_r <= rhi;
+          const int nk = 3 * np;
+#pragma unroll
+          for (int st = 0; st < kAsmChunk * 3 / 4; ++st) {
+            if (4 * st < nk) {  // uniform
+              const bool kin = 4 * st + kq < nk;
+              const double a = (kin && a_ok) ? zflat[zbase + koff[st]] : 0.0;
+              const double b = (kin && bn_ok) ? aflat[abase + koff[st]] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
           }
         }
       }
-      if (blk_active) {
-        int sl = (blx - br + 2) + 5 * (bly - ky + 2) + 25 * (blz - kz + 2);
-        double* wrow = win[(c + br + 3) % 3] + (3 * bg) * kSlotPad + sl;
-        wrow[0] += acc3[0];
-        wrow[kSlotPad] += acc3[1];
-        wrow[2 * kSlotPad] += acc3[2];
+      // the column's blocks into the sliding window (disjoint per lane/wave)
+      if (dn < 27) {
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int r = dm_r[vv];
+          if (r >= rlo && r <= rhi) {
+            const int sl = dsl0 - r - 5 * ky - 25 * kz;
+            win[(c + r + 3) % 3][dm_e[vv] * kSlotPad + sl] += acc[vv];
+          }
+        }
       }
     }
     __syncthreads();
     if (next_row < re && rx[next_row - rb] == c) {
       int ro = next_row - rb;
       bool rf = nbf[(c - xw0) + nxw * (2 + 5 * 2)] != 0;
-      finalize_row_block(win[(c + 3) % 3], next_row, c, xw0, nxw, L, nbf, rf, rmass[ro], red);
+      finalize_row_block(win[(c + 3) % 3], next_row, c, xw0, L, nbf, fr, rf, rmass[ro], red);
       ++next_row;
     }
     double* wz = win[(c + 3) % 3];
