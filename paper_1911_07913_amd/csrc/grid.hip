@@ -124,6 +124,20 @@ __global__ void k_mark_coarse(GridGeom fg, int nf, const int* __restrict__ fnode
       for (int c = 0; c < nz; ++c) cflags[pidx(cg, Jx[a], Jy[b], Jz[c])] = 1;
 }
 
+// Points (X, Y, z) of the half-coarsened grid (x and y coarsened, z fine)
+// that are x-y parents of an active fine node.
+__global__ void k_mark_xy(GridGeom fg, int nf, const int* __restrict__ fnodes, GridGeom tg,
+                          int* __restrict__ tflags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  int x, y, z;
+  unpidx(fg, fnodes[i], x, y, z);
+  int Jx[2], Jy[2];
+  int nx = parents1d(x, Jx), ny = parents1d(y, Jy);
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b) tflags[pidx(tg, Jx[a], Jy[b], z)] = 1;
+}
+
 __global__ void k_compact(long long total, const int* __restrict__ flags,
                           const int* __restrict__ scan, int* __restrict__ map,
                           int* __restrict__ nodes) {
@@ -331,6 +345,10 @@ void launch_mark_fine(const GridGeom& g, const int* counts, int* flags, hipStrea
 void launch_mark_coarse(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& coarse,
                         int* cflags, hipStream_t st) {
   if (nf > 0) k_mark_coarse<<<blocks_for(nf), kTpb, 0, st>>>(fine, nf, fnodes, coarse, cflags);
+}
+void launch_mark_xy(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& half,
+                    int* flags, hipStream_t st) {
+  if (nf > 0) k_mark_xy<<<blocks_for(nf), kTpb, 0, st>>>(fine, nf, fnodes, half, flags);
 }
 void launch_compact(long long total, const int* flags, const int* scan, int* map, int* nodes,
                     hipStream_t st) {

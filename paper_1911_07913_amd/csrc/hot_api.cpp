@@ -110,6 +110,8 @@ struct hot_scene {
   DBuf pbuf[2];
   DBuf f, key, keys, tmp, Cp, psi[2], S[2];
   DBuf wnode;  // double4 node velocities over the padded level-0 grid
+  // half-coarsened grid of the Galerkin product (reused for every level)
+  DBuf tnodes, tmap, tpat, tH;
   int pc = 0;  // current psi/S buffer
   // level-0 grid
   DBuf counts, start, cursor, flags, scan, scan_temp, err;
@@ -309,6 +311,7 @@ hot_status validate_positions(const hot_params* p, int64_t n, const double* x) {
 struct SetCounts {
   long long nodes[kMaxLevels] = {0};
   long long bricks = 0;
+  long long half0 = 0;  // x-y parents of the level-0 nodes
 };
 
 SetCounts count_sets(const hot_params* p, int64_t n, const double* x) {
@@ -336,6 +339,23 @@ SetCounts count_sets(const hot_params* p, int64_t n, const double* x) {
         ++c.nodes[0];
       }
     }
+  }
+  {
+    int hd[3] = {dims[0] / 2 + 1, dims[1] / 2 + 1, dims[2]};
+    std::vector<uint8_t> hm((size_t)hd[0] * hd[1] * hd[2], 0);
+    for (int z = 0; z < dims[2]; ++z)
+      for (int y = 0; y < dims[1]; ++y)
+        for (int xx = 0; xx < dims[0]; ++xx) {
+          if (!mark[(size_t)xx + dims[0] * ((size_t)y + (size_t)dims[1] * z)]) continue;
+          for (int Y = y / 2; Y <= (y + 1) / 2; ++Y)
+            for (int X = xx / 2; X <= (xx + 1) / 2; ++X) {
+              size_t id = (size_t)X + hd[0] * ((size_t)Y + (size_t)hd[1] * z);
+              if (!hm[id]) {
+                hm[id] = 1;
+                ++c.half0;
+              }
+            }
+        }
   }
   for (int m = 1; m < p->mg_levels; ++m) {
     int cd[3] = {dims[0] / 2 + 1, dims[1] / 2 + 1, dims[2] / 2 + 1};
@@ -409,6 +429,12 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
     if (mx) { A(nm * kRowStride * 2); A(nm * 36); A(nm * 12); }
     A(nm * 3 * vsz); A(nm * 3 * vsz);  // b, r
     A((double)gm_level_ptotal(p, m) * 4 * vsz); A((double)gm_level_ptotal(p, m) * 4 * vsz);  // u, t
+  }
+  // half-coarsened grid of the level-0 Galerkin product (the largest)
+  if (p->mg_levels > 1) {
+    GridGeom th = make_geom(g0.dims[0] / 2 + 1, g0.dims[1] / 2 + 1, g0.dims[2]);
+    const double nt = (double)c.half0;
+    A(nt * 4); A((double)th.ptotal * 4); A(nt * 16); A(nt * kRowStride * 8);
   }
   // level-0 node data, solver vectors and history, row segments
   const double n0 = (double)c.nodes[0];
@@ -550,10 +576,31 @@ hot_status prepare(hot_scene* s, double dt) {
                           P<double>(s->Cp), P<int>(s->start), P<int>(s->counts),
                           P<double>(s->mass), P<int>(s->fixed), st));
   for (int m = 0; m + 1 < s->levels; ++m) {
+    // rows of the half-coarsened grid: x-y parents of level m's nodes
+    const GridGeom& fg = s->L[m].g;
+    LevelView T;
+    std::memset(&T, 0, sizeof(T));
+    T.g = make_geom(fg.dims[0] / 2 + 1, fg.dims[1] / 2 + 1, fg.dims[2]);
+    launch_fill_int(T.g.ptotal, P<int>(s->flags), 0, st);
+    launch_mark_xy(fg, s->L[m].n, P<int>(s->L[m].nodes), T.g, P<int>(s->flags), st);
+    launch_scan(T.g.ptotal, P<int>(s->flags), P<int>(s->scan), s->scan_temp.p, st);
+    int nt = 0;
+    TRY(read_int(s, P<int>(s->scan) + T.g.ptotal, &nt));
+    TRY(ensure(s, s->tnodes, (size_t)nt * 4));
+    TRY(ensure(s, s->tmap, (size_t)T.g.ptotal * 4));
+    TRY(ensure(s, s->tpat, (size_t)nt * 16));
+    TRY(ensure(s, s->tH, (size_t)nt * kRowStride * 8));
+    launch_compact(T.g.ptotal, P<int>(s->flags), P<int>(s->scan), P<int>(s->tmap),
+                   P<int>(s->tnodes), st);
+    T.n = nt;
+    T.nodes = P<int>(s->tnodes);
+    T.map = P<int>(s->tmap);
+    T.pat = P<uint32_t>(s->tpat);
+    T.H = P<double>(s->tH);
     if (m == 0)
-      PROF(s, HOT_PROF_RAP0, launch_rap(view(s, m), view(s, m + 1), st));
+      PROF(s, HOT_PROF_RAP0, launch_rap(view(s, m), T, view(s, m + 1), st));
     else
-      launch_rap(view(s, m), view(s, m + 1), st);
+      launch_rap(view(s, m), T, view(s, m + 1), st);
   }
   if (s->prof)
     for (int m = 0; m < s->levels; ++m)
@@ -936,7 +983,8 @@ void destroy(hot_scene* s) {
                  &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
                  &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
                  &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
-                 &s->bmap, &s->blist, &s->bpartial, &s->wnode};
+                 &s->bmap, &s->blist, &s->bpartial, &s->wnode, &s->tnodes, &s->tmap,
+                 &s->tpat, &s->tH};
   for (DBuf* b : all) release(s, *b);
   for (auto& b : s->Sh) release(s, b);
   for (auto& b : s->Yh) release(s, b);

@@ -145,6 +145,8 @@ struct Particles {
 void launch_permute_particles(int n, const int* perm, const Particles& src, const Particles& dst,
                               hipStream_t st);
 void launch_mark_fine(const GridGeom& g, const int* counts, int* flags, hipStream_t st);
+void launch_mark_xy(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& half,
+                    int* flags, hipStream_t st);
 void launch_mark_coarse(const GridGeom& fine, int nf, const int* fnodes, const GridGeom& coarse,
                         int* cflags, hipStream_t st);
 void launch_compact(long long total, const int* flags, const int* scan, int* map, int* nodes,
@@ -196,7 +198,10 @@ void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_b
 
 // matrix.hip
 void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);
-void launch_rap(const LevelView& F, const LevelView& Cv, hipStream_t st);
+// Galerkin product F -> Cv through the half-coarsened grid T (x, y coarse, z
+// fine; T.g has dims (F.x/2 + 1, F.y/2 + 1, F.z), T.nodes/map/pat/H sized for
+// T.n rows); writes Cv's blocks, pattern, free flags, diagonal and l1 inverse.
+void launch_rap(const LevelView& F, const LevelView& T, const LevelView& Cv, hipStream_t st);
 void launch_to_bf16(const LevelView& L, hipStream_t st);
 // V-cycle pieces (FP64 and FP32/BF16 variants chosen by `mixed`)
 void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u, hipStream_t st);

@@ -201,81 +201,165 @@ __device__ inline V comp(const typename Vec4Of<V>::type* v4, int pn, int c) {
 }
 
 // ---------------------------------------------------------------- RAP
-// Coarse row I of H^{m+1} = P~^T H^m P~ (Eq. buildMultigrid) with the linear
-// node embedding: the fine children of I are 2I + a, a in {-1,0,1}^3, weight
-// prod(1 or 1/2); each fine block (i, j) is spread to the coarse parents J of
-// j.  P~ = Pi P drops constrained fine DOFs.  The symbolic coarse pattern is
-// the structure of R pattern P.  Accumulation in LDS, one wave per coarse
-// row; lane l handles fine slots l and l + 64 of each child row.
+// H^{m+1} = P~^T H^m P~ (Eq. buildMultigrid) with the linear node embedding.
+// P = Px (x) Py (x) Pz is a tensor product of 1-D embeddings (child 2J + b of
+// coarse J with weight 1 for b = 0 and 1/2 for b = +-1), so the product is
+// taken one axis group at a time, each a gather with no atomics:
+//   T[(X, Y, z)][(dX, dY, dz)] = sum_{bx, by, bx', by'} w w w w
+//        H~[(2X+bx, 2Y+by, z)][(2dX + bx' - bx, 2dY + by' - by, dz)]
+// on the half-coarsened grid (x, y coarse, z fine), then
+//   H^{m+1}[(X, Y, Z)][(dX, dY, dZ)] = sum_{bz, bz'} w w T[(X, Y, 2Z+bz)][(dX, dY, 2dZ + bz' - bz)].
+// Both stay within +-2 per axis.  H~ = Pi H Pi: constrained DOFs have zero
+// rows and columns off the diagonal block already, so only the diagonal
+// block's constrained entries are masked.  A slot of T or of the coarse row is
+// structurally present iff some contributing fine slot is (the symbolic
+// R pattern P).  One wave per output row; lane l owns output slots l, l + 64.
 constexpr int kRapWaves = 4;
 
-__global__ __launch_bounds__(256) void k_rap(LevelView F, LevelView C) {
-  __shared__ double acc_all[kRapWaves][kRowStride];
-  __shared__ uint32_t pat_all[kRapWaves][4];
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int I = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
-  if (I >= C.n) return;
-  double* acc = acc_all[wave];
-  uint32_t* pat = pat_all[wave];
-  for (int e = lane; e < kRowStride; e += 64) acc[e] = 0.0;
-  if (lane < 4) pat[lane] = 0u;
-  wave_sync();
-  int X, Y, Z;
-  unpidx(C.g, C.nodes[I], X, Y, Z);
-  // the 27 fine children's indices, one per lane
-  int ichild = -1;
-  if (lane < 27)
-    ichild = F.map[pidx(F.g, 2 * X + lane % 3 - 1, 2 * Y + (lane / 3) % 3 - 1, 2 * Z + lane / 9 - 1)];
-  for (int a = 0; a < 27; ++a) {
-    int i = __shfl(ichild, a, 64);
+__device__ inline double emb_w(int b) { return b ? 0.5 : 1.0; }
+
+// pattern words of a row from the lanes' presence flags of slots l, l + 64
+__device__ inline void ballot_pattern(bool p0, bool p1, uint32_t* out, int lane) {
+  const unsigned long long b0 = __ballot(p0), b1 = __ballot(p1);
+  if (lane == 0) {
+    out[0] = (uint32_t)b0;
+    out[1] = (uint32_t)(b0 >> 32);
+    out[2] = (uint32_t)b1;
+    out[3] = (uint32_t)(b1 >> 32) & ((1u << (kSlots - 96)) - 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rap_xy(LevelView F, LevelView T) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
+  if (t >= T.n) return;
+  int X, Y, z;
+  unpidx(T.g, T.nodes[t], X, Y, z);
+  int child = -1;  // fine row of child a = (bx + 1) + 3 (by + 1), in lane a
+  if (lane < 9)
+    child = F.map[pidx(F.g, 2 * X + lane % 3 - 1, 2 * Y + lane / 3 - 1, z)];
+  const int S0 = lane, S1 = lane + 64;
+  const bool v1 = S1 < kSlots;
+  const int dX0 = S0 % 5 - 2, dY0 = (S0 / 5) % 5 - 2, dz0 = S0 / 25 - 2;
+  const int dX1 = S1 % 5 - 2, dY1 = (S1 / 5) % 5 - 2, dz1 = S1 / 25 - 2;
+  double acc0[9], acc1[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc0[c] = acc1[c] = 0.0;
+  bool p0 = false, p1 = false;
+  for (int a = 0; a < 9; ++a) {
+    const int i = __shfl(child, a, 64);
     if (i < 0) continue;
-    int ax = a % 3 - 1, ay = (a / 3) % 3 - 1, az = a / 9 - 1;
-    int cx = 2 * X + ax, cy = 2 * Y + ay, cz = 2 * Z + az;
-    double wa = (ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0);
-    const double fi0 = (double)F.free_dof[3 * i], fi1 = (double)F.free_dof[3 * i + 1],
-                 fi2 = (double)F.free_dof[3 * i + 2];
+    const int bx = a % 3 - 1, by = a / 3 - 1;
+    const double wa = emb_w(bx) * emb_w(by);
     const uint32_t w[4] = {F.pat[4 * i], F.pat[4 * i + 1], F.pat[4 * i + 2], F.pat[4 * i + 3]};
     const double* Hrow = F.H + (long long)i * kRowStride;
-    const long long pni = F.nodes[i];
-    double h[2][9];
-    int jn[2];
+    const double f0 = (double)F.free_dof[3 * i], f1 = (double)F.free_dof[3 * i + 1],
+                 f2 = (double)F.free_dof[3 * i + 2];
+    const double fm[9] = {f0 * f0, f0 * f1, f0 * f2, f1 * f0, f1 * f1, f1 * f2,
+                          f2 * f0, f2 * f1, f2 * f2};
+    for (int bxp = -1; bxp <= 1; ++bxp)
+      for (int byp = -1; byp <= 1; ++byp) {
+        const double wb = wa * emb_w(bxp) * emb_w(byp);
+        {
+          const int sx = 2 * dX0 + bxp - bx, sy = 2 * dY0 + byp - by;
+          if (sx >= -2 && sx <= 2 && sy >= -2 && sy <= 2) {
+            const int s = (sx + 2) + 5 * (sy + 2) + 25 * (dz0 + 2);
+            if (slot_present(w, s)) {
+              p0 = true;
+              const bool ctr = s == kCenter;
 #pragma unroll
-    for (int ps = 0; ps < 2; ++ps) {
-      const int s = lane + 64 * ps;
-      const bool pr = slot_present(w, s);
-      jn[ps] = pr ? F.map[pni + slot_offset(F.g, s)] : -1;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) h[ps][c] = pr ? Hrow[c * kSlotPad + s] : 0.0;
-    }
-#pragma unroll
-    for (int ps = 0; ps < 2; ++ps) {
-      if (jn[ps] < 0) continue;
-      const int s = lane + 64 * ps;
-      const int j = jn[ps];
-      const double fj0 = (double)F.free_dof[3 * j], fj1 = (double)F.free_dof[3 * j + 1],
-                   fj2 = (double)F.free_dof[3 * j + 2];
-      double v[9];
-      v[0] = h[ps][0] * fi0 * fj0; v[1] = h[ps][1] * fi0 * fj1; v[2] = h[ps][2] * fi0 * fj2;
-      v[3] = h[ps][3] * fi1 * fj0; v[4] = h[ps][4] * fi1 * fj1; v[5] = h[ps][5] * fi1 * fj2;
-      v[6] = h[ps][6] * fi2 * fj0; v[7] = h[ps][7] * fi2 * fj1; v[8] = h[ps][8] * fi2 * fj2;
-      const int jx = cx + s % 5 - 2, jy = cy + (s / 5) % 5 - 2, jz = cz + s / 25 - 2;
-      const int Px0 = jx >> 1, Py0 = jy >> 1, Pz0 = jz >> 1;
-      const int nx = (jx & 1) + 1, ny = (jy & 1) + 1, nz = (jz & 1) + 1;
-      const double wj = wa * ((jx & 1) ? 0.5 : 1.0) * ((jy & 1) ? 0.5 : 1.0) * ((jz & 1) ? 0.5 : 1.0);
-      for (int u = 0; u < nx; ++u)
-        for (int vv = 0; vv < ny; ++vv)
-          for (int ww = 0; ww < nz; ++ww) {
-            const int S = (Px0 + u - X + 2) + 5 * (Py0 + vv - Y + 2) + 25 * (Pz0 + ww - Z + 2);
-            atomicOr(&pat[S >> 5], 1u << (S & 31));
-#pragma unroll
-            for (int c = 0; c < 9; ++c)
-              if (v[c] != 0.0) atomicAdd(&acc[c * kSlotPad + S], v[c] * wj);
+              for (int c = 0; c < 9; ++c) {
+                const double h = Hrow[c * kSlotPad + s];
+                acc0[c] += wb * (ctr ? h * fm[c] : h);
+              }
+            }
           }
+        }
+        if (v1) {
+          const int sx = 2 * dX1 + bxp - bx, sy = 2 * dY1 + byp - by;
+          if (sx >= -2 && sx <= 2 && sy >= -2 && sy <= 2) {
+            const int s = (sx + 2) + 5 * (sy + 2) + 25 * (dz1 + 2);
+            if (slot_present(w, s)) {
+              p1 = true;
+              const bool ctr = s == kCenter;
+#pragma unroll
+              for (int c = 0; c < 9; ++c) {
+                const double h = Hrow[c * kSlotPad + s];
+                acc1[c] += wb * (ctr ? h * fm[c] : h);
+              }
+            }
+          }
+        }
+      }
+  }
+  double* Tout = T.H + (long long)t * kRowStride;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    Tout[c * kSlotPad + S0] = acc0[c];
+    Tout[c * kSlotPad + S1] = v1 ? acc1[c] : 0.0;
+  }
+  ballot_pattern(p0, p1 && v1, T.pat + 4 * t, lane);
+}
+
+__global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
+  __shared__ double acc_all[kRapWaves][kRowStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int I = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
+  if (I >= C.n) return;
+  double* accr = acc_all[wave];
+  int X, Y, Z;
+  unpidx(C.g, C.nodes[I], X, Y, Z);
+  int child = -1;  // half-grid row of child bz = lane - 1, in lanes 0..2
+  if (lane < 3) child = T.map[pidx(T.g, X, Y, 2 * Z + lane - 1)];
+  const int S0 = lane, S1 = lane + 64;
+  const bool v1 = S1 < kSlots;
+  const int dX0 = S0 % 5 - 2, dY0 = (S0 / 5) % 5 - 2, dZ0 = S0 / 25 - 2;
+  const int dX1 = S1 % 5 - 2, dY1 = (S1 / 5) % 5 - 2, dZ1 = S1 / 25 - 2;
+  double acc0[9], acc1[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc0[c] = acc1[c] = 0.0;
+  bool p0 = false, p1 = false;
+  for (int a = 0; a < 3; ++a) {
+    const int tr = __shfl(child, a, 64);
+    if (tr < 0) continue;
+    const int bz = a - 1;
+    const double wa = emb_w(bz);
+    const uint32_t w[4] = {T.pat[4 * tr], T.pat[4 * tr + 1], T.pat[4 * tr + 2], T.pat[4 * tr + 3]};
+    const double* Trow = T.H + (long long)tr * kRowStride;
+    for (int bzp = -1; bzp <= 1; ++bzp) {
+      const double wb = wa * emb_w(bzp);
+      {
+        const int sz = 2 * dZ0 + bzp - bz;
+        if (sz >= -2 && sz <= 2) {
+          const int s = (dX0 + 2) + 5 * (dY0 + 2) + 25 * (sz + 2);
+          if (slot_present(w, s)) {
+            p0 = true;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc0[c] += wb * Trow[c * kSlotPad + s];
+          }
+        }
+      }
+      if (v1) {
+        const int sz = 2 * dZ1 + bzp - bz;
+        if (sz >= -2 && sz <= 2) {
+          const int s = (dX1 + 2) + 5 * (dY1 + 2) + 25 * (sz + 2);
+          if (slot_present(w, s)) {
+            p1 = true;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc1[c] += wb * Trow[c * kSlotPad + s];
+          }
+        }
+      }
     }
   }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    accr[c * kSlotPad + S0] = acc0[c];
+    accr[c * kSlotPad + S1] = v1 ? acc1[c] : 0.0;
+  }
+  ballot_pattern(p0, p1 && v1, C.pat + 4 * I, lane);
   wave_sync();
-  finalize_row(acc, I, C, nullptr, 0.0, lane);
-  if (lane < 4) C.pat[4 * I + lane] = pat[lane];
+  finalize_row(accr, I, C, nullptr, 0.0, lane);
 }
 
 __global__ void k_to_bf16(LevelView L) {
@@ -727,8 +811,9 @@ int grid_blocks() {
 
 }  // namespace
 
-void launch_rap(const LevelView& F, const LevelView& C, hipStream_t st) {
-  if (C.n > 0) k_rap<<<(unsigned)((C.n + kRapWaves - 1) / kRapWaves), 256, 0, st>>>(F, C);
+void launch_rap(const LevelView& F, const LevelView& T, const LevelView& C, hipStream_t st) {
+  if (T.n > 0) k_rap_xy<<<(unsigned)((T.n + kRapWaves - 1) / kRapWaves), 256, 0, st>>>(F, T);
+  if (C.n > 0) k_rap_z<<<(unsigned)((C.n + kRapWaves - 1) / kRapWaves), 256, 0, st>>>(T, C);
 }
 void launch_to_bf16(const LevelView& L, hipStream_t st) {
   long long nv = (long long)L.n * kRowStride;
