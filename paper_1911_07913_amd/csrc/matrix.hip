@@ -548,17 +548,72 @@ __device__ inline V block_dot(const V* a, const V* b, int n, V* red) {
   return t;
 }
 
+// y_r = H_{i0+r} . x for R consecutive rows with x compact [n][3] in LDS
+// (neighbour rows through the level map); same lane roles and summation order
+// as rows_matvec.
+template <typename V, int R>
+__device__ inline void rows_matvec_lds(const LevelView& L, int i0, const V* xs, int lane,
+                                       V (&y)[R][3]) {
+  typedef typename MatOf<V>::type M;
+  V h[R][2][9];
+  int jn[R][2];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = i0 + r;
+    const bool live = i < L.n;
+    const M* Hrow = MatOf<V>::H(L) + (long long)(live ? i : 0) * kRowStride;
+    const int pn = live ? L.nodes[i] : 0;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (live)
+      for (int q = 0; q < 4; ++q) w[q] = L.pat[4 * i + q];
+    bool pr[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int s = SweepRows<V>::slot(lane, k);
+      pr[k] = slot_present(w, s);
+      jn[r][k] = pr[k] ? L.map[pn + slot_offset(L.g, s)] : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) SweepRows<V>::load(Hrow, c, lane, pr[0], pr[1], h[r][0][c], h[r][1][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    V a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (jn[r][k] >= 0) {
+        const V* xj = xs + 3 * jn[r][k];
+        const V x0 = xj[0], x1 = xj[1], x2 = xj[2];
+        a0 += h[r][k][0] * x0 + h[r][k][1] * x1 + h[r][k][2] * x2;
+        a1 += h[r][k][3] * x0 + h[r][k][4] * x1 + h[r][k][5] * x2;
+        a2 += h[r][k][6] * x0 + h[r][k][7] * x1 + h[r][k][8] * x2;
+      }
+    }
+    y[r][0] = wave_sum_t(a0);
+    y[r][1] = wave_sum_t(a1);
+    y[r][2] = wave_sum_t(a2);
+  }
+}
+
+// Single work-group form for coarsest levels whose five CG vectors fit in
+// LDS: r, z, p, q, x live in LDS, rows are processed several per wave (as in
+// the sweeps) with all their loads in flight, and inner products are block
+// reductions; no memory traffic leaves the compute unit except the matrix and
+// map reads.
+constexpr size_t kPcgLdsMax = 60 * 1024;
+
 template <typename V>
 __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(
     LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
-    V* __restrict__ work, int* __restrict__ iters_out, int max_iter, double rel) {
+    int* __restrict__ iters_out, int max_iter, double rel) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char pcg_lds[];
   __shared__ V red[kPcgWaves];
   const int n3 = 3 * L.n;
-  V* r = work;
+  V* r = reinterpret_cast<V*>(pcg_lds);
   V* z = r + n3;
   V* p = z + n3;
   V* q = p + n3;
-  V* x = q + n3;  // compact iterate, scattered to the dense x4 at the end
+  V* x = q + n3;
   const V* dg = MatOf<V>::diag(L);
   for (int k = threadIdx.x; k < n3; k += kPcgThreads) {
     V bk = b[k];
@@ -572,14 +627,23 @@ __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(
   V rz = block_dot<V>(r, z, n3, red);
   double stop = rel * sqrt(fmax((double)rz, 0.0));
   int it = 0;
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kPcgRows = SweepRows<V>::R;
   if (rz > (V)0) {
     while (it < max_iter) {
       __syncthreads();
-      for (int row = wave; row < L.n; row += kPcgWaves) {
-        V y[3];
-        row_matvec<V>(L, row, p, lane, y);
-        if (lane < 3) q[3 * row + lane] = y[lane];
+      for (int row0 = wave * kPcgRows; row0 < L.n; row0 += kPcgWaves * kPcgRows) {
+        V y[kPcgRows][3];
+        rows_matvec_lds<V, kPcgRows>(L, row0, p, lane, y);
+        if (lane < 3 * kPcgRows) {
+          const int rr = lane / 3, c = lane - 3 * rr;
+          V yv = y[0][0];
+#pragma unroll
+          for (int qq = 0; qq < kPcgRows; ++qq)
+            for (int e = 0; e < 3; ++e)
+              if (qq == rr && e == c) yv = y[qq][e];
+          if (row0 + rr < L.n) q[3 * (row0 + rr) + c] = yv;
+        }
       }
       __syncthreads();
       V pq = block_dot<V>(p, q, n3, red);
@@ -614,7 +678,6 @@ __global__ __launch_bounds__(256) void k_spmv(LevelView L, const double* __restr
   row_matvec<double>(L, i, x, lane, v);
   if (lane < 3) y[3 * i + lane] = v[lane];
 }
-
 
 // Multi-work-group form of the same solve for larger coarsest levels: one
 // wave per row (rows strided over all waves of the grid), the same update
@@ -895,38 +958,46 @@ void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out
     k_dense_out<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double4*)u, out);
 }
 
-// Coarsest levels smaller than this run in one work-group.
-constexpr int kGridMinRows = 128;
 
 size_t coarse_pcg_work_bytes(int n) {
   return (size_t)5 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 512;
 }
 
+// FP64 coarsest levels at least this large use the multi-work-group solve.
+constexpr int kGridMinRows = 128;
+
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
                              int* iters_out, int max_iter, double rel, hipStream_t st) {
-  const size_t vec = (size_t)5 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double));
-  double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
-  GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
+  const size_t vsz = mixed ? sizeof(float) : sizeof(double);
+  const size_t lds = (size_t)5 * 3 * L.n * vsz;
+  // One work-group streams the whole level matrix through one compute unit
+  // per CG iteration: right for BF16 blocks or small levels; FP64 levels of
+  // kGridMinRows rows or more are read by a grid of work-groups instead.
   const int maxb = mixed ? grid_blocks<float>() : grid_blocks<double>();
-  const int nb = std::min((L.n + kCgWaves - 1) / kCgWaves, maxb);
-  if (L.n >= kGridMinRows && nb >= 2) {
-    k_reset_bar<<<1, 64, 0, st>>>(bar);
+  const bool grid = (!mixed && L.n >= kGridMinRows) || lds > kPcgLdsMax;
+  if (!grid || maxb < 2) {
+    if (lds > kPcgLdsMax) return hipErrorInvalidConfiguration;
     if (mixed)
-      k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float4*)x,
-                                                            (float*)work, part, bar, iters_out,
-                                                            max_iter, rel);
+      k_coarse_pcg<float><<<1, kPcgThreads, lds, st>>>(L, (const float*)b, (float4*)x, iters_out,
+                                                      max_iter, rel);
     else
-      k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double4*)x,
-                                                             (double*)work, part, bar, iters_out,
-                                                             max_iter, rel);
+      k_coarse_pcg<double><<<1, kPcgThreads, lds, st>>>(L, (const double*)b, (double4*)x,
+                                                       iters_out, max_iter, rel);
     return hipGetLastError();
   }
+  const size_t vec = (size_t)5 * 3 * L.n * vsz;
+  double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
+  GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
+  const int nb = std::max(2, std::min((L.n + kCgWaves - 1) / kCgWaves, maxb));
+  k_reset_bar<<<1, 64, 0, st>>>(bar);
   if (mixed)
-    k_coarse_pcg<float><<<1, kPcgThreads, 0, st>>>(L, (const float*)b, (float4*)x, (float*)work,
-                                                    iters_out, max_iter, rel);
+    k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float4*)x,
+                                                          (float*)work, part, bar, iters_out,
+                                                          max_iter, rel);
   else
-    k_coarse_pcg<double><<<1, kPcgThreads, 0, st>>>(L, (const double*)b, (double4*)x,
-                                                     (double*)work, iters_out, max_iter, rel);
+    k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double4*)x,
+                                                           (double*)work, part, bar, iters_out,
+                                                           max_iter, rel);
   return hipGetLastError();
 }
 
