@@ -602,8 +602,9 @@ hot_status prepare(hot_scene* s, double dt) {
     else
       launch_rap(view(s, m), T, view(s, m + 1), st);
   }
+  // structural block counts of levels 0 and 1 (the traced kernels' bytes)
   if (s->prof)
-    for (int m = 0; m < s->levels; ++m)
+    for (int m = 0; m < std::min(s->levels, 2); ++m)
       launch_pattern_count(view(s, m), P<double>(s->dscal) + S_NNZ + m, st);
   if (s->mixed)
     for (int m = 0; m < s->levels; ++m) launch_to_bf16(view(s, m), st);

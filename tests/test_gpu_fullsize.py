@@ -1,0 +1,120 @@
+"""Parity at the benchmark's full size: the 1,572,864-particle twisting bars
+(256x64x64 grid, 5 levels), prepared exactly as the benchmark's first step.
+
+Integer work is compared whole and bit for bit against the oracle:
+binning permutation, the active node set of every level, constrained nodes.
+Floating-point fields are compared at sampled nodes, each computed by the
+oracle on the sub-scene of particles that can influence it (the particles
+whose base node lies within [i - 4, i + 2] per axis of the sampled node i:
+they hold every particle of i's stencil and every particle of the stencils
+of those particles' nodes), so the oracle's value is exact for the full
+scene:  node mass, v*, CN stiffness, the gradient at dv = 0 and the whole
+125-block row of the level-0 Hessian.  Finally one full step at this size
+must converge with a decreasing incremental potential.
+"""
+import numpy as np
+import pytest
+
+import hot_scenes as hs
+import oracle as O
+from test_gpu_parity import _hot, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    hot = _hot()
+    sc = hs.twisting_bars(side=16)
+    dt = O.time_step(sc)
+    g = hot.Scene.from_scene(sc)
+    g.debug_prepare(dt)
+    yield sc, dt, g
+    g.close()
+
+
+def test_binning_permutation_bit_exact(full):
+    hot = _hot()
+    sc, dt, g = full
+    _, perm = O.bin_particles(sc)
+    assert np.array_equal(g.debug_read(hot.DBG_PERM, dtype=np.int32), perm)
+
+
+def test_level_node_sets_and_constraints_bit_exact(full):
+    hot = _hot()
+    sc, dt, g = full
+    lev = O.active_fine_nodes(sc)
+    fixed, _ = O.bc_nodes(sc, lev, dt)
+    assert np.array_equal(g.debug_read(hot.DBG_NODE_FIXED, dtype=np.int32).astype(bool), fixed)
+    counts = []
+    for m in range(sc.mg_levels):
+        nodes = g.debug_read(hot.DBG_LEVEL_NODES, m, dtype=np.int32).astype(np.int64)
+        assert np.array_equal(nodes, lev.lin), f"level {m}"
+        counts.append(lev.n)
+        if m + 1 < sc.mg_levels:
+            _, lev = O.prolongation(lev)
+    # the closed-form counts of the 16x16-bar scene
+    assert counts == [281580, 47916, 8619, 1323, 375]
+
+
+def _subscene(sc, node, lo=-4, hi=2):
+    base = O.bspline(sc.x, sc.origin, sc.dx)[0]
+    sel = np.all((base >= node + lo) & (base <= node + hi), axis=1)
+    out = sc.copy()
+    for f in ("x", "v", "F", "C", "vol0", "mat_id"):
+        setattr(out, f, getattr(sc, f)[sel].copy())
+    return out
+
+
+def _sample_nodes(sc, lev, fixed, k=6, seed=11):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    free = np.nonzero(~fixed)[0]
+    picks = list(rng.choice(free, size=k, replace=False))
+    # two free nodes next to a gripped node, so the Dirichlet projection of
+    # the Hessian is sampled too
+    nb = lev.lookup(O.linear(lev.coords[:, None, :] + O.SLOT_OFFS[None], lev.dims))
+    near = np.nonzero(~fixed & np.any((nb >= 0) & fixed[np.maximum(nb, 0)], axis=1))[0]
+    picks += list(rng.choice(near, size=2, replace=False))
+    return [int(p) for p in picks]
+
+
+def test_sampled_nodes_p2g_gradient_and_hessian_rows(full):
+    hot = _hot()
+    sc, dt, g = full
+    lev = O.active_fine_nodes(sc)
+    fixed, _ = O.bc_nodes(sc, lev, dt)
+    mass = g.debug_read(hot.DBG_NODE_MASS)
+    vstar = g.debug_read(hot.DBG_NODE_VSTAR).reshape(-1, 3)
+    xi = g.debug_read(hot.DBG_NODE_XI)
+    grad = g.debug_apply(1, np.zeros(3 * lev.n)).reshape(-1, 3)
+    H0 = g.debug_read(hot.DBG_LEVEL_MATRIX, 0).reshape(lev.n, 125, 3, 3)
+    for i in _sample_nodes(sc, lev, fixed):
+        node = lev.coords[i]
+        sub = _subscene(sc, node)
+        st = O.prepare(sub, dt)
+        j = int(st.lev0.lookup(np.array([lev.lin[i]]))[0])
+        assert j >= 0
+        assert abs(mass[i] - st.m[j]) <= 1e-13 * st.m[j]
+        assert rel(vstar[i], st.vstar[j]) < 1e-12
+        assert abs(xi[i] - st.xi[j]) <= 1e-13 * st.xi[j]
+        go = O.gradient(st, np.zeros((st.lev0.n, 3)))[j]
+        # at dv = 0 the elastic forces nearly cancel away from the grips; the
+        # node's momentum m_i |v*_i| sets the scale of a meaningful difference
+        scale = max(np.abs(go).max(), st.m[j] * np.abs(st.vstar[j]).max())
+        assert np.abs(grad[i] - go).max() <= 1e-10 * scale, (i, grad[i], go)
+        Hs, _ = O.hessian_slots(st)
+        assert rel(H0[i], Hs[j]) < 1e-12, f"row {i}"
+
+
+def test_full_size_step_converges_and_decreases_energy():
+    hot = _hot()
+    sc = hs.twisting_bars(side=16)
+    g = hot.Scene.from_scene(sc)
+    try:
+        status = g.step()
+        st = g.stats
+    finally:
+        g.close()
+    assert status == 0 and st["converged"]
+    assert st["E"] < st["E0"]
+    assert st["cn"] <= st["cn_tol"] < st["cn0"]
