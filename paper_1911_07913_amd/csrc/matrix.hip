@@ -123,12 +123,20 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
 // L.n contribute nothing.  Results are valid in all lanes.
 template <typename V>
 struct SweepRows;
+// Matrix rows are streamed once per sweep: non-temporal loads keep them from
+// evicting the gathered iterate from L2.
 template <>
 struct SweepRows<double> {
   static constexpr int R = 2;
   static __device__ inline int slot(int lane, int k) { return lane + 64 * k; }
   static __device__ inline void load(const double* Hrow, int c, int lane, bool p0, bool p1,
                                      double& h0, double& h1) {
+    h0 = p0 ? __builtin_nontemporal_load(Hrow + c * kSlotPad + lane) : 0.0;
+    h1 = p1 ? __builtin_nontemporal_load(Hrow + c * kSlotPad + lane + 64) : 0.0;
+  }
+  // cached form, for matrices read repeatedly (the coarsest solve)
+  static __device__ inline void load_cached(const double* Hrow, int c, int lane, bool p0, bool p1,
+                                            double& h0, double& h1) {
     h0 = p0 ? Hrow[c * kSlotPad + lane] : 0.0;
     h1 = p1 ? Hrow[c * kSlotPad + lane + 64] : 0.0;
   }
@@ -139,6 +147,14 @@ struct SweepRows<float> {
   static __device__ inline int slot(int lane, int k) { return 2 * lane + k; }
   static __device__ inline void load(const uint16_t* Hrow, int c, int lane, bool p0, bool p1,
                                      float& h0, float& h1) {
+    uint32_t u = (p0 || p1)
+                     ? __builtin_nontemporal_load((const uint32_t*)(Hrow + c * kSlotPad + 2 * lane))
+                     : 0u;
+    h0 = p0 ? bf16_to_f32((uint16_t)(u & 0xFFFFu)) : 0.0f;
+    h1 = p1 ? bf16_to_f32((uint16_t)(u >> 16)) : 0.0f;
+  }
+  static __device__ inline void load_cached(const uint16_t* Hrow, int c, int lane, bool p0,
+                                            bool p1, float& h0, float& h1) {
     uint32_t u = (p0 || p1) ? *(const uint32_t*)(Hrow + c * kSlotPad + 2 * lane) : 0u;
     h0 = p0 ? bf16_to_f32((uint16_t)(u & 0xFFFFu)) : 0.0f;
     h1 = p1 ? bf16_to_f32((uint16_t)(u >> 16)) : 0.0f;
@@ -574,7 +590,7 @@ __device__ inline void rows_matvec_lds(const LevelView& L, int i0, const V* xs, 
       jn[r][k] = pr[k] ? L.map[pn + slot_offset(L.g, s)] : -1;
     }
 #pragma unroll
-    for (int c = 0; c < 9; ++c) SweepRows<V>::load(Hrow, c, lane, pr[0], pr[1], h[r][0][c], h[r][1][c]);
+    for (int c = 0; c < 9; ++c) SweepRows<V>::load_cached(Hrow, c, lane, pr[0], pr[1], h[r][0][c], h[r][1][c]);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
