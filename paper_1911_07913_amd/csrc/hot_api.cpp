@@ -1137,9 +1137,13 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
   {
     size_t mb = sizeof(MaterialDev) * n_mats, bb = sizeof(BcDev) * hb.size();
     if ((rc = ensure(s, s->tables, mb + bb)) < 0) return bail(rc);
-    if (hipMemcpy(s->tables.p, hm.data(), mb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy((char*)s->tables.p + mb, hb.data(), bb, hipMemcpyHostToDevice) != hipSuccess)
-      return bail(fail(HOT_E_DEVICE, "table upload failed"));
+    // stream-ordered: scenes of one process may be created from several threads
+    hipError_t e = hipMemcpyAsync(s->tables.p, hm.data(), mb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((char*)s->tables.p + mb, hb.data(), bb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess)
+      return bail(fail(HOT_E_DEVICE, "table upload failed: %s", hipGetErrorString(e)));
     sd.mats = (const MaterialDev*)s->tables.p;
     sd.bcs = (const BcDev*)((char*)s->tables.p + mb);
   }
