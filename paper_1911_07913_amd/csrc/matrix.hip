@@ -80,9 +80,11 @@ __device__ inline bool slot_present(const uint32_t* w, int s) {
   return s < kSlots && ((w[s >> 5] >> (s & 31)) & 1u);
 }
 
-template <typename V>
-__device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict__ x, int lane,
-                                  V* y) {
+// y = H_i . x for one row, one wave; the neighbour values x_j come from
+// gather(j, x0, x1, x2) with j the neighbour's compact index, so that a solver
+// can form the multiplied vector on the fly.
+template <typename V, typename Gather>
+__device__ inline void row_matvec_with(const LevelView& L, int i, int lane, V* y, Gather gather) {
   typedef typename MatOf<V>::type M;
   const M* Hrow = MatOf<V>::H(L) + (long long)i * kRowStride;
   const long long pn = L.nodes[i];
@@ -101,8 +103,8 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
 #pragma unroll
   for (int ps = 0; ps < 2; ++ps) {
     if (jn[ps] >= 0) {
-      const V* xj = x + 3 * (long long)jn[ps];
-      V x0 = xj[0], x1 = xj[1], x2 = xj[2];
+      V x0, x1, x2;
+      gather((long long)jn[ps], x0, x1, x2);
       a0 += h[ps][0] * x0 + h[ps][1] * x1 + h[ps][2] * x2;
       a1 += h[ps][3] * x0 + h[ps][4] * x1 + h[ps][5] * x2;
       a2 += h[ps][6] * x0 + h[ps][7] * x1 + h[ps][8] * x2;
@@ -111,6 +113,17 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
   y[0] = wave_sum_t(a0);
   y[1] = wave_sum_t(a1);
   y[2] = wave_sum_t(a2);
+}
+
+template <typename V>
+__device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict__ x, int lane,
+                                  V* y) {
+  row_matvec_with<V>(L, i, lane, y, [&](long long j, V& x0, V& x1, V& x2) {
+    const V* xj = x + 3 * j;
+    x0 = xj[0];
+    x1 = xj[1];
+    x2 = xj[2];
+  });
 }
 
 // y_r = H_{i0+r} . x for R consecutive rows, computed by one wave with all
@@ -706,7 +719,7 @@ __global__ __launch_bounds__(256) void k_spmv(LevelView L, const double* __restr
 // while a block of one of them waits to start.  Every wait is still bounded:
 // a barrier that does not complete within the spin limit raises a flag that
 // makes every block leave, and the solve reports a negative iteration count.
-constexpr int kCgWaves = 4;
+constexpr int kCgWaves = 8;
 constexpr int kCgMaxBlocks = 32;
 constexpr unsigned kSpinLimit = 1u << 22;
 
@@ -717,30 +730,32 @@ struct GridBar {
   int pad;
 };
 
+// One release (the arrival) and one acquire (after the wait) per barrier;
+// the wait itself polls with relaxed loads, so that it does not invalidate
+// the caches that the other blocks are reading the level matrix through.
 __device__ inline bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& gen, int* s_ok) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
     const unsigned target = gen + 1u;
-    __threadfence();
-    const unsigned arrived = atomicAdd(&bar->count, 1u) + 1u;
+    const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == nblocks) {
-      atomicExch(&bar->count, 0u);
-      __threadfence();
-      atomicExch(&bar->gen, target);
+      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
         if (__hip_atomic_load(&bar->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
             ++spins > kSpinLimit) {
-          atomicExch(&bar->fail, 1);
+          __hip_atomic_store(&bar->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();
     *s_ok = ok;
   }
   __syncthreads();
@@ -786,8 +801,9 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
   const int n = L.n, n3 = 3 * n;
   V* r = work;
   V* z = r + n3;
-  V* p = z + n3;
-  V* q = p + n3;
+  V* pa = z + n3;  // direction read by this iteration's product
+  V* pb = pa + n3; // direction written by this iteration
+  V* q = pb + n3;
   V* x = q + n3;  // compact iterate, scattered to the dense x4 at the end
   double* part_pq = part;
   double* part_rz = part + kCgMaxBlocks;
@@ -805,7 +821,7 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
       r[k] = bk;
       V zk = bk / dg[k];
       z[k] = zk;
-      p[k] = zk;
+      pa[k] = zk;
       loc += (double)(bk * zk);
     }
   block_partial(loc, part_rz, red);
@@ -813,15 +829,33 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
   bool ok = grid_sync(bar, nb, gen, &s_ok);
   double rz = ok ? grid_total(part_rz, nb, &s_val) : 0.0;
   const double stop = rel * sqrt(fmax(rz, 0.0));
+  // The direction update p = z + beta p is formed on the fly wherever p is
+  // read (the product's gathers and the block's own rows) from z and the
+  // previous p, both complete at the last barrier; each block stores its own
+  // rows of the new p in the other buffer.  Two barriers per iteration, the
+  // same arithmetic as the textbook ordering.
+  V beta = 0;
+  bool first = true;
   if (ok && rz > 0.0) {
     while (it < max_iter) {
       loc = 0.0;
       for (int row = gw; row < n; row += nw) {
         V y[3];
-        row_matvec<V>(L, row, p, lane, y);
+        if (first)
+          row_matvec<V>(L, row, pa, lane, y);
+        else
+          row_matvec_with<V>(L, row, lane, y, [&](long long j, V& x0, V& x1, V& x2) {
+            const long long k = 3 * j;
+            x0 = z[k] + beta * pa[k];
+            x1 = z[k + 1] + beta * pa[k + 1];
+            x2 = z[k + 2] + beta * pa[k + 2];
+          });
         if (lane < 3) {
-          q[3 * row + lane] = y[lane];
-          loc += (double)(p[3 * row + lane] * y[lane]);
+          const int k = 3 * row + lane;
+          const V pk = first ? pa[k] : z[k] + beta * pa[k];
+          pb[k] = pk;
+          q[k] = y[lane];
+          loc += (double)(pk * y[lane]);
         }
       }
       block_partial(loc, part_pq, red);
@@ -833,7 +867,7 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
       for (int row = gw; row < n; row += nw)
         if (lane < 3) {
           const int k = 3 * row + lane;
-          x[k] += alpha * p[k];
+          x[k] += alpha * pb[k];
           V rk = r[k] - alpha * q[k];
           r[k] = rk;
           V zk = rk / dg[k];
@@ -845,14 +879,12 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
       const double rzn = grid_total(part_rz, nb, &s_val);
       ++it;
       if (sqrt(fmax(rzn, 0.0)) <= stop) break;
-      const V beta = (V)(rzn / rz);
+      beta = (V)(rzn / rz);
       rz = rzn;
-      for (int row = gw; row < n; row += nw)
-        if (lane < 3) {
-          const int k = 3 * row + lane;
-          p[k] = z[k] + beta * p[k];
-        }
-      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+      V* t = pa;
+      pa = pb;
+      pb = t;
+      first = false;
     }
   }
   for (int row = gw; row < n; row += nw)
@@ -976,10 +1008,10 @@ void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out
 
 
 size_t coarse_pcg_work_bytes(int n) {
-  return (size_t)5 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 512;
+  return (size_t)6 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 512;
 }
 
-// FP64 coarsest levels at least this large use the multi-work-group solve.
+// Coarsest levels at least this large use the multi-work-group solve.
 constexpr int kGridMinRows = 128;
 
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
@@ -987,10 +1019,11 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   const size_t vsz = mixed ? sizeof(float) : sizeof(double);
   const size_t lds = (size_t)5 * 3 * L.n * vsz;
   // One work-group streams the whole level matrix through one compute unit
-  // per CG iteration: right for BF16 blocks or small levels; FP64 levels of
-  // kGridMinRows rows or more are read by a grid of work-groups instead.
+  // per CG iteration, which is limited by that unit's outstanding memory
+  // requests: it serves small levels only; levels of kGridMinRows rows or
+  // more are read by a grid of work-groups instead.
   const int maxb = mixed ? grid_blocks<float>() : grid_blocks<double>();
-  const bool grid = (!mixed && L.n >= kGridMinRows) || lds > kPcgLdsMax;
+  const bool grid = L.n >= kGridMinRows || lds > kPcgLdsMax;
   if (!grid || maxb < 2) {
     if (lds > kPcgLdsMax) return hipErrorInvalidConfiguration;
     if (mixed)
@@ -1001,7 +1034,7 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
                                                        iters_out, max_iter, rel);
     return hipGetLastError();
   }
-  const size_t vec = (size_t)5 * 3 * L.n * vsz;
+  const size_t vec = (size_t)6 * 3 * L.n * vsz;
   double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
   GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
   const int nb = std::max(2, std::min((L.n + kCgWaves - 1) / kCgWaves, maxb));
