@@ -80,39 +80,59 @@ __device__ inline bool slot_present(const uint32_t* w, int s) {
   return s < kSlots && ((w[s >> 5] >> (s & 31)) & 1u);
 }
 
-// y = H_i . x for one row, one wave; the neighbour values x_j come from
-// gather(j, x0, x1, x2) with j the neighbour's compact index, so that a solver
-// can form the multiplied vector on the fly.
-template <typename V, typename Gather>
-__device__ inline void row_matvec_with(const LevelView& L, int i, int lane, V* y, Gather gather) {
+// One row's blocks as one wave holds them: lane l owns slots l and l + 64,
+// with their 3x3 blocks and the compact indices of their neighbours (-1 for
+// absent slots).
+template <typename V>
+struct RowBlocks {
+  V h[2][9];
+  int jn[2];
+};
+
+template <typename V>
+__device__ inline void row_load(const LevelView& L, int i, int lane, RowBlocks<V>& rb) {
   typedef typename MatOf<V>::type M;
   const M* Hrow = MatOf<V>::H(L) + (long long)i * kRowStride;
   const long long pn = L.nodes[i];
   const uint32_t w[4] = {L.pat[4 * i], L.pat[4 * i + 1], L.pat[4 * i + 2], L.pat[4 * i + 3]};
-  V h[2][9];
-  int jn[2];
 #pragma unroll
   for (int ps = 0; ps < 2; ++ps) {
     const int s = lane + 64 * ps;
     const bool pr = slot_present(w, s);
-    jn[ps] = pr ? L.map[pn + slot_offset(L.g, s)] : -1;
+    rb.jn[ps] = pr ? L.map[pn + slot_offset(L.g, s)] : -1;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) h[ps][c] = pr ? ldm<V, M>(Hrow + c * kSlotPad + s) : (V)0;
+    for (int c = 0; c < 9; ++c) rb.h[ps][c] = pr ? ldm<V, M>(Hrow + c * kSlotPad + s) : (V)0;
   }
+}
+
+// y = (held row) . x with x_j supplied by gather(j, x0, x1, x2); the sums are
+// valid in every lane.
+template <typename V, typename Gather>
+__device__ inline void row_apply(const RowBlocks<V>& rb, V* y, Gather gather) {
   V a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
   for (int ps = 0; ps < 2; ++ps) {
-    if (jn[ps] >= 0) {
+    if (rb.jn[ps] >= 0) {
       V x0, x1, x2;
-      gather((long long)jn[ps], x0, x1, x2);
-      a0 += h[ps][0] * x0 + h[ps][1] * x1 + h[ps][2] * x2;
-      a1 += h[ps][3] * x0 + h[ps][4] * x1 + h[ps][5] * x2;
-      a2 += h[ps][6] * x0 + h[ps][7] * x1 + h[ps][8] * x2;
+      gather((long long)rb.jn[ps], x0, x1, x2);
+      a0 += rb.h[ps][0] * x0 + rb.h[ps][1] * x1 + rb.h[ps][2] * x2;
+      a1 += rb.h[ps][3] * x0 + rb.h[ps][4] * x1 + rb.h[ps][5] * x2;
+      a2 += rb.h[ps][6] * x0 + rb.h[ps][7] * x1 + rb.h[ps][8] * x2;
     }
   }
   y[0] = wave_sum_t(a0);
   y[1] = wave_sum_t(a1);
   y[2] = wave_sum_t(a2);
+}
+
+// y = H_i . x for one row, one wave; the neighbour values x_j come from
+// gather(j, x0, x1, x2) with j the neighbour's compact index, so that a solver
+// can form the multiplied vector on the fly.
+template <typename V, typename Gather>
+__device__ inline void row_matvec_with(const LevelView& L, int i, int lane, V* y, Gather gather) {
+  RowBlocks<V> rb;
+  row_load<V>(L, i, lane, rb);
+  row_apply<V>(rb, y, gather);
 }
 
 template <typename V>
@@ -723,43 +743,52 @@ constexpr int kCgWaves = 8;
 constexpr int kCgMaxBlocks = 32;
 constexpr unsigned kSpinLimit = 1u << 22;
 
+// Barrier state: the generation each block has reached (one word per
+// block) and a failure flag.
 struct GridBar {
-  unsigned count;
-  unsigned gen;
+  unsigned flag[kCgMaxBlocks];
   int fail;
-  int pad;
+  int pad[3];
 };
+static_assert(kCgMaxBlocks <= 64, "one wave polls every block's flag");
 
-// One release (the arrival) and one acquire (after the wait) per barrier;
-// the wait itself polls with relaxed loads, so that it does not invalidate
-// the caches that the other blocks are reading the level matrix through.
+// Each block publishes the generation it has reached in its own word (one
+// release store) and its first wave polls every block's word with one
+// relaxed wave-wide load until all have reached it, then acquires.  No
+// read-modify-write atomics, so arrivals are not serialised on one address,
+// and the polls do not invalidate the caches that the other blocks are
+// reading the level matrix through.  A block can be at most one generation
+// ahead of a poller (it cannot pass the next barrier without the poller), so
+// "reached" is flag - target >= 0.
 __device__ inline bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& gen, int* s_ok) {
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const unsigned target = gen + 1u;
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    if (l == 0)
+      __hip_atomic_store(&bar->flag[blockIdx.x], target, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
-    const unsigned target = gen + 1u;
-    const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
-        if (__hip_atomic_load(&bar->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            ++spins > kSpinLimit) {
-          __hip_atomic_store(&bar->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    unsigned spins = 0;
+    for (;;) {
+      const unsigned v =
+          l < (int)nblocks
+              ? __hip_atomic_load(&bar->flag[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+              : target;
+      const int f = __hip_atomic_load(&bar->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__ballot((int)(v - target) >= 0) == ~0ull) break;
+      if (__ballot(f != 0) != 0ull || ++spins > kSpinLimit) {
+        if (l == 0) __hip_atomic_store(&bar->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_sleep(1);
     }
-    *s_ok = ok;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (l == 0) *s_ok = ok;
   }
   __syncthreads();
-  gen += 1u;
+  gen = target;
   return *s_ok != 0;
 }
 
@@ -892,26 +921,157 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
   if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
 }
 
-__global__ void k_reset_bar(GridBar* bar) {
-  if (threadIdx.x == 0) {
-    bar->count = 0u;
-    bar->gen = 0u;
-    bar->fail = 0;
-    bar->pad = 0;
+// Register-resident form of the grid solve for coarsest levels of at most R
+// rows per wave (row gw + k nw, k < R, as in the strided loops above): each
+// wave loads its rows' blocks and neighbour indices once per solve and keeps
+// them, with its rows' entries of r, x, z, p, q and the diagonal, in
+// registers.  Only z and p, which other waves gather, go through memory.  The
+// arithmetic and the order of every sum are those of k_coarse_pcg_grid.
+template <typename V, int R>
+__global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_reg(
+    LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
+    V* __restrict__ work, double* __restrict__ part, GridBar* __restrict__ bar,
+    int* __restrict__ iters_out, int max_iter, double rel) {
+  __shared__ double red[kCgWaves];
+  __shared__ double s_val;
+  __shared__ int s_ok;
+  const int n = L.n, n3 = 3 * n;
+  V* z = work;
+  V* pa = z + n3;  // direction read by this iteration's product
+  V* pb = pa + n3; // direction written by this iteration
+  double* part_pq = part;
+  double* part_rz = part + kCgMaxBlocks;
+  const V* dg = MatOf<V>::diag(L);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nb = gridDim.x;
+  const int gw = blockIdx.x * kCgWaves + wave, nw = nb * kCgWaves;
+  const int c3 = lane < 3 ? lane : 0;
+  RowBlocks<V> rows[R];
+  V rr[R], xx[R], zz[R], dd[R], pp[R], qq[R];
+  double loc = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int row = gw + k * nw;
+    rr[k] = xx[k] = zz[k] = pp[k] = qq[k] = 0;
+    dd[k] = 1;
+    if (row < n) {
+      row_load<V>(L, row, lane, rows[k]);
+      if (lane < 3) {
+        const int kk = 3 * row + lane;
+        const V bk = b[kk];
+        dd[k] = dg[kk];
+        rr[k] = bk;
+        const V zk = bk / dd[k];
+        zz[k] = zk;
+        pp[k] = zk;
+        z[kk] = zk;
+        pa[kk] = zk;
+        loc += (double)(bk * zk);
+      }
+    }
   }
+  block_partial(loc, part_rz, red);
+  int it = 0;
+  unsigned gen = 0;
+  bool ok = grid_sync(bar, nb, gen, &s_ok);
+  double rz = ok ? grid_total(part_rz, nb, &s_val) : 0.0;
+  const double stop = rel * sqrt(fmax(rz, 0.0));
+  V beta = 0;
+  bool first = true;
+  if (ok && rz > 0.0) {
+    while (it < max_iter) {
+      loc = 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int row = gw + k * nw;
+        if (row < n) {
+          V y[3];
+          if (first)
+            row_apply<V>(rows[k], y, [&](long long j, V& x0, V& x1, V& x2) {
+              const V* xj = pa + 3 * j;
+              x0 = xj[0];
+              x1 = xj[1];
+              x2 = xj[2];
+            });
+          else
+            row_apply<V>(rows[k], y, [&](long long j, V& x0, V& x1, V& x2) {
+              const long long kk = 3 * j;
+              x0 = z[kk] + beta * pa[kk];
+              x1 = z[kk + 1] + beta * pa[kk + 1];
+              x2 = z[kk + 2] + beta * pa[kk + 2];
+            });
+          if (lane < 3) {
+            const V yl = c3 == 0 ? y[0] : (c3 == 1 ? y[1] : y[2]);
+            const V pk = first ? pp[k] : zz[k] + beta * pp[k];
+            pp[k] = pk;
+            pb[3 * row + lane] = pk;
+            qq[k] = yl;
+            loc += (double)(pk * yl);
+          }
+        }
+      }
+      block_partial(loc, part_pq, red);
+      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+      const double pq = grid_total(part_pq, nb, &s_val);
+      if (!(pq > 0.0)) break;
+      const V alpha = (V)(rz / pq);
+      loc = 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int row = gw + k * nw;
+        if (row < n && lane < 3) {
+          xx[k] += alpha * pp[k];
+          const V rk = rr[k] - alpha * qq[k];
+          rr[k] = rk;
+          const V zk = rk / dd[k];
+          zz[k] = zk;
+          z[3 * row + lane] = zk;
+          loc += (double)(rk * zk);
+        }
+      }
+      block_partial(loc, part_rz, red);
+      if (!(ok = grid_sync(bar, nb, gen, &s_ok))) break;
+      const double rzn = grid_total(part_rz, nb, &s_val);
+      ++it;
+      if (sqrt(fmax(rzn, 0.0)) <= stop) break;
+      beta = (V)(rzn / rz);
+      rz = rzn;
+      V* t = pa;
+      pa = pb;
+      pb = t;
+      first = false;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int row = gw + k * nw;
+    if (row < n && lane < 3) comp<V>(x4, L.nodes[row], lane) = xx[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
 }
 
-// Grid size of k_coarse_pcg_grid<V> on the current device: 1/16 of the
-// resident block capacity, at most kCgMaxBlocks (0 or less if unknown).
-template <typename V>
+__global__ void k_reset_bar(GridBar* bar) {
+  if (threadIdx.x < kCgMaxBlocks) bar->flag[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) bar->fail = 0;
+}
+
+// Rows per wave of the register-resident coarsest solve.
+constexpr int kRegRows = 2;
+
+// Grid size of the grid solve (Reg = false: k_coarse_pcg_grid<V>, true:
+// k_coarse_pcg_reg<V, kRegRows>) on the current device: 1/16 of the resident
+// block capacity, at most kCgMaxBlocks (0 or less if unknown).
+template <typename V, bool Reg>
 int grid_blocks() {
   static int cached[16] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
   if (cached[dev] == 0) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_coarse_pcg_grid<V>, kCgWaves * 64,
-                                                     0) != hipSuccess ||
+    const void* kern = Reg ? (const void*)k_coarse_pcg_reg<V, kRegRows>
+                           : (const void*)k_coarse_pcg_grid<V>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kCgWaves * 64, 0) !=
+            hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cached[dev] = -1;
     else
@@ -1008,7 +1168,8 @@ void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out
 
 
 size_t coarse_pcg_work_bytes(int n) {
-  return (size_t)6 * 3 * n * sizeof(double) + 2 * kCgMaxBlocks * sizeof(double) + 512;
+  return (size_t)6 * 3 * n * sizeof(double) + 256 + 2 * kCgMaxBlocks * sizeof(double) +
+         sizeof(GridBar);
 }
 
 // Coarsest levels at least this large use the multi-work-group solve.
@@ -1022,7 +1183,7 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   // per CG iteration, which is limited by that unit's outstanding memory
   // requests: it serves small levels only; levels of kGridMinRows rows or
   // more are read by a grid of work-groups instead.
-  const int maxb = mixed ? grid_blocks<float>() : grid_blocks<double>();
+  const int maxb = mixed ? grid_blocks<float, false>() : grid_blocks<double, false>();
   const bool grid = L.n >= kGridMinRows || lds > kPcgLdsMax;
   if (!grid || maxb < 2) {
     if (lds > kPcgLdsMax) return hipErrorInvalidConfiguration;
@@ -1039,6 +1200,18 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
   const int nb = std::max(2, std::min((L.n + kCgWaves - 1) / kCgWaves, maxb));
   k_reset_bar<<<1, 64, 0, st>>>(bar);
+  // levels of at most kRegRows rows per wave keep their rows in registers
+  const int maxr = mixed ? grid_blocks<float, true>() : grid_blocks<double, true>();
+  const int nbr = std::max(2, std::min((L.n + kCgWaves - 1) / kCgWaves, maxr));
+  if (maxr >= 2 && L.n <= kRegRows * nbr * kCgWaves) {
+    if (mixed)
+      k_coarse_pcg_reg<float, kRegRows><<<nbr, kCgWaves * 64, 0, st>>>(
+          L, (const float*)b, (float4*)x, (float*)work, part, bar, iters_out, max_iter, rel);
+    else
+      k_coarse_pcg_reg<double, kRegRows><<<nbr, kCgWaves * 64, 0, st>>>(
+          L, (const double*)b, (double4*)x, (double*)work, part, bar, iters_out, max_iter, rel);
+    return hipGetLastError();
+  }
   if (mixed)
     k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float4*)x,
                                                           (float*)work, part, bar, iters_out,
