@@ -617,6 +617,64 @@ def l1_block_jacobi_inverse(A):
     return sp.csr_matrix((Dinv.ravel(), (rows.ravel(), cols.ravel())), shape=A.shape)
 
 
+SMOOTHERS = ("l1jacobi", "sgs")
+N_COLORS = 27
+
+
+def node_colors(lev):
+    """Colour of every node of a level for the coloured Gauss-Seidel smoother
+    (Alg. V-cycle; Sec. 5.3 names coloured symmetric Gauss-Seidel, Sec. 8
+    parallelises it by colouring): (x mod 3) + 3 (y mod 3) + 9 (z mod 3) of
+    the node's grid coordinate.  A block row couples nodes at most 2 apart
+    per axis (125 slots), so two distinct nodes of one colour are never
+    coupled and a colour's nodes can all be updated at once."""
+    c = np.mod(lev.coords, 3)
+    return c[:, 0] + 3 * c[:, 1] + 9 * c[:, 2]
+
+
+def sgs_setup(A, lev):
+    """Per colour: its nodes, their DOF rows, the off-diagonal-block part of
+    those rows of A and the inverses of their 3x3 diagonal blocks."""
+    n = lev.n
+    C = A.tocoo()
+    bi, bj = C.row // 3, C.col // 3
+    on = bi == bj
+    D = np.zeros((n, 3, 3))
+    np.add.at(D, (bi[on], C.row[on] % 3, C.col[on] % 3), C.data[on])
+    Aoff = sp.csr_matrix((C.data[~on], (C.row[~on], C.col[~on])), shape=A.shape)
+    col = node_colors(lev)
+    out = []
+    for c in range(N_COLORS):
+        nodes = np.nonzero(col == c)[0]
+        dofs = (3 * nodes[:, None] + np.arange(3)[None, :]).ravel()
+        out.append((nodes, dofs, Aoff[dofs], np.linalg.inv(D[nodes])))
+    return out
+
+
+def sgs(setup, b, u, sweeps=1):
+    """Symmetric block Gauss-Seidel smoothing (Alg. V-cycle): a forward pass
+    over the colours 0..26, then a backward pass 26..0.  Within a colour every
+    node i takes u_i = H_ii^{-1} (b_i - sum_{j != i} H_ij u_j) with the
+    current u (the colour's nodes do not see each other)."""
+    u = u.copy()
+    for _ in range(sweeps):
+        for order in (range(N_COLORS), range(N_COLORS - 1, -1, -1)):
+            for c in order:
+                nodes, dofs, Aoff_c, Dinv_c = setup[c]
+                if len(nodes) == 0:
+                    continue
+                r = (b[dofs] - Aoff_c @ u).reshape(-1, 3)
+                u[dofs] = np.einsum("kab,kb->ka", Dinv_c, r).ravel()
+    return u
+
+
+def sgs_data(hz):
+    """The coloured Gauss-Seidel set-up of every smoothed level (cached)."""
+    if getattr(hz, "sgs", None) is None:
+        hz.sgs = [sgs_setup(hz.A[m], hz.levels[m]) for m in range(len(hz.A) - 1)]
+    return hz.sgs
+
+
 def coarse_pcg(A, diag, b, rel=0.5, max_iter=500, log=None):
     """Jacobi-preconditioned CG on the coarsest level (Alg. V-cycle), from
     x0 = 0, stopped once sqrt(r^T D^{-1} r) <= rel * sqrt(b^T D^{-1} b) with D
@@ -647,18 +705,24 @@ def coarse_pcg(A, diag, b, rel=0.5, max_iter=500, log=None):
     return x
 
 
-def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None):
-    """Multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi smoothing.
+def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None, smoother="l1jacobi"):
+    """Multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi smoothing, or with
+    the paper's coloured symmetric block Gauss-Seidel (smoother="sgs").
 
     Down: u^m = smooth(0, b^m); b^{m+1} = P~^T (b^m - H^m u^m).  Coarsest: PCG
     to relative 1/2.  Up: u^m += P~ u^{m+1}; u^m = smooth(u^m, b^m)."""
+    assert smoother in SMOOTHERS
     M = len(hz.A)
     us, bs = [None] * M, [None] * M
     bs[0] = b * hz.free[0]
+    gs = sgs_data(hz) if smoother == "sgs" else None
     for m in range(M - 1):
         u = np.zeros_like(bs[m])
-        for _ in range(sweeps):
-            u = u + hz.Dinv[m] @ (bs[m] - hz.A[m] @ u)
+        if gs is not None:
+            u = sgs(gs[m], bs[m], u, sweeps)
+        else:
+            for _ in range(sweeps):
+                u = u + hz.Dinv[m] @ (bs[m] - hz.A[m] @ u)
         us[m] = u
         bs[m + 1] = hz.P[m].T @ (bs[m] - hz.A[m] @ u)
     if coarse_solver is None:
@@ -668,8 +732,11 @@ def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None):
     us[M - 1] = us[M - 1] * hz.free[M - 1]
     for m in range(M - 2, -1, -1):
         u = us[m] + hz.P[m] @ us[m + 1]
-        for _ in range(sweeps):
-            u = u + hz.Dinv[m] @ (bs[m] - hz.A[m] @ u)
+        if gs is not None:
+            u = sgs(gs[m], bs[m], u, sweeps)
+        else:
+            for _ in range(sweeps):
+                u = u + hz.Dinv[m] @ (bs[m] - hz.A[m] @ u)
         us[m] = u * hz.free[m]
     return us[0]
 
@@ -697,7 +764,8 @@ def two_loop(hist, g, apply_H0):
     return r
 
 
-def solve(st, hz, tol, history, max_iters=500, sweeps=1, c1=1e-4, max_halvings=30):
+def solve(st, hz, tol, history, max_iters=500, sweeps=1, c1=1e-4, max_halvings=30,
+          smoother="l1jacobi"):
     """HOT quasi-Newton solve (Alg. HOT).
 
     dv^1 = 0; while the CN-scaled gradient norm exceeds eps*sqrt(n): two-loop
@@ -720,7 +788,8 @@ def solve(st, hz, tol, history, max_iters=500, sweeps=1, c1=1e-4, max_halvings=3
     converged = cn <= thresh
     while not converged and it < max_iters:
         cg_log = []
-        V = lambda q: vcycle(hz, q.ravel(), sweeps=sweeps, log=cg_log).reshape(n, 3)
+        V = lambda q: vcycle(hz, q.ravel(), sweeps=sweeps, log=cg_log,
+                             smoother=smoother).reshape(n, 3)
         p = two_loop(hist, g, V)
         fb = 0
         if float(np.sum(p * g)) >= 0.0:
@@ -823,7 +892,7 @@ def g2p(st, dv):
 
 
 def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=None,
-         sweeps=1, return_internals=False):
+         sweeps=1, return_internals=False, smoother="l1jacobi"):
     """One implicit MPM step: P2G, HOT solve for dv, G2P (Sec. 3.1, Alg. HOT)."""
     if dt is None or dt <= 0:
         dt = time_step(scene)
@@ -834,7 +903,8 @@ def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=N
     st = prepare(scene, dt, t)
     H0, nbr0 = hessian_slots(st)
     hz = build_hierarchy(st, H0, nbr0, levels)
-    dv, info = solve(st, hz, tol, history, max_iters=max_iters, sweeps=sweeps)
+    dv, info = solve(st, hz, tol, history, max_iters=max_iters, sweeps=sweeps,
+                     smoother=smoother)
     out = g2p(st, dv)
     info["dt"] = dt
     if return_internals:
