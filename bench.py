@@ -37,7 +37,7 @@ FP64_PEAK_TFLOPS = 78.6
 # for 27 nodes (27 x 9 FMA), C+ a_jp for 27 nodes (27 x 81 FMA), and the 378
 # distinct 3x3 blocks a_ip^T (C+ a_jp) of the symmetric 27 x 27 block pattern
 # (378 x 27 FMA): 12,636 FMA = 25,272 flop.
-BOUND = {"smooth0": "hbm", "residual0": "hbm", "rap0": "hbm", "particle_eval": "hbm",
+BOUND = {"smooth0": "hbm", "residual0": "hbm", "sgs0": "hbm", "rap0": "hbm", "particle_eval": "hbm",
          "gradient": "hbm", "assemble_h0": "alu", "particle_hessian": "alu"}
 FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 9 + 27 * 81 + 378 * 27)}
 

@@ -55,6 +55,17 @@ typedef enum { HOT_FCR = 0, HOT_NEOHOOKEAN = 1 } hot_model;
  * the L-BFGS history stay FP64. */
 typedef enum { HOT_FP64 = 0, HOT_MIXED = 1 } hot_precision;
 
+/* Smoother of the V-cycle's non-coarsest levels (Alg. V-cycle).
+ * HOT_SMOOTH_L1_JACOBI: l1 block-Jacobi, u += D~^{-1} (b - H u), D~ the 3x3
+ *   diagonal block plus the l1 sums of the rest of the row on its diagonal;
+ *   one fully parallel pass per sweep (the default).
+ * HOT_SMOOTH_SGS: the paper's coloured symmetric block Gauss-Seidel (Sec. 5.3,
+ *   Sec. 8): nodes coloured by grid coordinate mod 3 per axis (27 colours),
+ *   a forward pass over colours 0..26 then a backward pass 26..0, each node
+ *   taking u_i = H_ii^{-1} (b_i - sum_{j != i} H_ij u_j).
+ * smoother_sweeps counts sweeps (Jacobi) or forward-backward pairs (SGS). */
+typedef enum { HOT_SMOOTH_L1_JACOBI = 0, HOT_SMOOTH_SGS = 1 } hot_smoother;
+
 typedef struct {
   int32_t model;        /* hot_model */
   double E;             /* Young's modulus, Pa, > 0 */
@@ -109,7 +120,8 @@ typedef struct {
   int32_t max_iters;       /* L-BFGS iteration cap (e.g. 500) */
   int32_t smoother_sweeps; /* smoothing sweeps per level and direction (1) */
   int32_t precision;       /* hot_precision */
-  int32_t reserved[3];     /* must be zero */
+  int32_t smoother;        /* hot_smoother */
+  int32_t reserved[2];     /* must be zero */
 } hot_params;
 
 typedef struct {
@@ -224,7 +236,8 @@ enum {
   HOT_PROF_EVAL = 4,       /* per-particle energy / stress evaluation */
   HOT_PROF_GRAD = 5,       /* gradient gather */
   HOT_PROF_PHESS = 6,      /* per-particle projected stress derivative */
-  HOT_PROF_COUNT = 7
+  HOT_PROF_SGS0 = 7,       /* level-0 symmetric Gauss-Seidel smoothing (54 colour passes) */
+  HOT_PROF_COUNT = 8
 };
 hot_status hot_profile_enable(hot_scene* scene, int32_t enable);
 hot_status hot_profile_read(const hot_scene* scene, int32_t kernel, double* total_ms,
@@ -240,6 +253,9 @@ enum {
   HOT_DBG_LEVEL_FREE = 13,    /* uint8 [n_m][3]: 1 = free DOF, 0 = constrained */
   HOT_DBG_LEVEL_MATRIX_BF16 = 14, /* uint16 [n_m][125][3][3] BF16 bit patterns of the
                                  blocks the mixed V-cycle reads (HOT_MIXED only) */
+  HOT_DBG_LEVEL_COLOR_ROWS = 15, /* int32 [n_m]: rows of level m ordered by
+                                    Gauss-Seidel colour, ascending within a
+                                    colour (HOT_SMOOTH_SGS, m < levels - 1) */
   HOT_DBG_NODE_MASS = 20,     /* double [n_0] */
   HOT_DBG_NODE_VSTAR = 21,    /* double [n_0][3]: v after gravity and BCs */
   HOT_DBG_NODE_XI = 22,       /* double [n_0]: CN stiffness field */

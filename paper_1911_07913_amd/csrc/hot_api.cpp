@@ -83,6 +83,9 @@ struct LevelH {
   int n = 0;
   DBuf nodes, map, H, Hb, Dinv, Dinv32, diag, diag32, freed, pat;
   DBuf b, u, r, t;  // V-cycle vectors
+  // coloured Gauss-Seidel: rows by colour, colour offsets, diagonal-block inverses
+  DBuf crow, coffd, Dg, Dg32;
+  int coff[kColors + 1] = {0};
 };
 
 }  // namespace
@@ -120,6 +123,7 @@ struct hot_scene {
   DBuf mass, vstar, xi, fixed;
   // solver vectors
   DBuf dv, dvt, g, gnew, q, r, pcg_work, pcg_iters, vin, vout;
+  DBuf cscratch;  // colour counting of the Gauss-Seidel set-up
   std::vector<DBuf> Sh, Yh;
   DBuf ddot, dalpha, dcoef, drho, dscal, partial, tables;
   // work lists: row segments (assembly) and cell bricks (particle-to-node sums)
@@ -289,8 +293,9 @@ hot_status validate_params(const hot_params* p) {
   if (p->smoother_sweeps < 1) return fail(HOT_E_INVALID, "smoother_sweeps must be >= 1");
   if (p->precision != HOT_FP64 && p->precision != HOT_MIXED)
     return fail(HOT_E_INVALID, "unknown precision");
-  if (p->reserved[0] || p->reserved[1] || p->reserved[2])
-    return fail(HOT_E_INVALID, "reserved fields must be zero");
+  if (p->smoother != HOT_SMOOTH_L1_JACOBI && p->smoother != HOT_SMOOTH_SGS)
+    return fail(HOT_E_INVALID, "unknown smoother");
+  if (p->reserved[0] || p->reserved[1]) return fail(HOT_E_INVALID, "reserved fields must be zero");
   return HOT_OK;
 }
 
@@ -429,7 +434,12 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
     if (mx) { A(nm * kRowStride * 2); A(nm * 36); A(nm * 12); }
     A(nm * 3 * vsz); A(nm * 3 * vsz);  // b, r
     A((double)gm_level_ptotal(p, m) * 4 * vsz); A((double)gm_level_ptotal(p, m) * 4 * vsz);  // u, t
+    if (p->smoother == HOT_SMOOTH_SGS && m + 1 < p->mg_levels) {
+      A(nm * 4); A((kColors + 1) * 4.0); A(nm * 72);
+      if (mx) A(nm * 36);
+    }
   }
+  if (p->smoother == HOT_SMOOTH_SGS) A((double)color_scratch_bytes((int)c.nodes[0]));
   // half-coarsened grid of the level-0 Galerkin product (the largest)
   if (p->mg_levels > 1) {
     GridGeom th = make_geom(g0.dims[0] / 2 + 1, g0.dims[1] / 2 + 1, g0.dims[2]);
@@ -449,6 +459,46 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
 }
 
 // ---------------------------------------------------------------- prepare
+// Coloured Gauss-Seidel set-up of the smoothed levels 0 .. M-2: the rows of
+// each colour and the inverses of the 3x3 diagonal blocks; the colour
+// offsets come to the host for the launch sizes.
+hot_status prepare_sgs(hot_scene* s) {
+  hipStream_t st = s->stream;
+  TRY(ensure(s, s->cscratch, color_scratch_bytes(s->L[0].n)));
+  for (int m = 0; m + 1 < s->levels; ++m) {
+    LevelH& L = s->L[m];
+    TRY(ensure(s, L.crow, (size_t)L.n * 4));
+    TRY(ensure(s, L.coffd, (kColors + 1) * 4));
+    TRY(ensure(s, L.Dg, (size_t)L.n * 72));
+    if (s->mixed) TRY(ensure(s, L.Dg32, (size_t)L.n * 36));
+    LevelView v = view(s, m);
+    launch_color_rows(v, P<int>(s->cscratch), P<int>(L.coffd), P<int>(L.crow), st);
+    launch_block_diag_inv(v, P<double>(L.Dg), s->mixed ? P<float>(L.Dg32) : nullptr, st);
+    HIPCHK(hipMemcpyAsync(L.coff, L.coffd.p, sizeof(L.coff), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int m = 0; m + 1 < s->levels; ++m)
+    if (s->L[m].coff[kColors] != s->L[m].n)
+      return fail(HOT_E_DEVICE, "colour lists of level %d are inconsistent", m);
+  return HOT_OK;
+}
+
+// One symmetric Gauss-Seidel smoothing (forward pass over the colours, then
+// backward), repeated smoother_sweeps times, in place on the level iterate u.
+void sgs_smooth(hot_scene* s, int m, const void* b, void* u) {
+  LevelH& L = s->L[m];
+  LevelView v = view(s, m);
+  const void* Dg = s->mixed ? L.Dg32.p : L.Dg.p;
+  for (int k = 0; k < s->prm.smoother_sweeps; ++k) {
+    for (int c = 0; c < kColors; ++c)
+      launch_sgs_color(v, s->mixed, P<int>(L.crow) + L.coff[c], L.coff[c + 1] - L.coff[c], Dg, b,
+                       u, s->stream);
+    for (int c = kColors - 1; c >= 0; --c)
+      launch_sgs_color(v, s->mixed, P<int>(L.crow) + L.coff[c], L.coff[c + 1] - L.coff[c], Dg, b,
+                       u, s->stream);
+  }
+}
+
 hot_status alloc_level(hot_scene* s, int m, int n) {
   LevelH& L = s->L[m];
   size_t vsz = s->mixed ? 4 : 8;
@@ -608,6 +658,7 @@ hot_status prepare(hot_scene* s, double dt) {
       launch_pattern_count(view(s, m), P<double>(s->dscal) + S_NNZ + m, st);
   if (s->mixed)
     for (int m = 0; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
+  if (s->prm.smoother == HOT_SMOOTH_SGS && s->levels > 1) TRY(prepare_sgs(s));
   size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
   TRY(ensure(s, s->pcg_work, pcg));
   TRY(ensure(s, s->pcg_iters, (size_t)(s->prm.max_iters * 3 + 16) * 4));
@@ -619,8 +670,9 @@ hot_status prepare(hot_scene* s, double dt) {
 }
 
 // ---------------------------------------------------------------- V-cycle
-// r = V(q): one multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi
-// smoothing and an inexact Jacobi-PCG coarsest solve.  In the mixed policy the
+// r = V(q): one multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi or
+// coloured symmetric block Gauss-Seidel smoothing and an inexact Jacobi-PCG
+// coarsest solve.  In the mixed policy the
 // cycle runs on FP32 vectors over BF16 blocks; q and r stay FP64.
 hot_status vcycle(hot_scene* s, const double* q, double* r) {
   hipStream_t st = s->stream;
@@ -640,10 +692,19 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
     us[m] = s->L[m].u.p;
     if (m > 0) bs[m] = s->L[m].b.p;
   }
+  const bool gs = s->prm.smoother == HOT_SMOOTH_SGS;
   for (int m = 0; m + 1 < M; ++m) {
     LevelView Lm = view(s, m);
-    launch_jacobi_first(Lm, mx, bs[m], us[m], st);
-    for (int k = 1; k < sweeps; ++k) {
+    if (gs) {
+      launch_zero_rows(Lm, mx, us[m], st);
+      if (m == 0)
+        PROF(s, HOT_PROF_SGS0, sgs_smooth(s, m, bs[m], us[m]));
+      else
+        sgs_smooth(s, m, bs[m], us[m]);
+    } else {
+      launch_jacobi_first(Lm, mx, bs[m], us[m], st);
+    }
+    for (int k = 1; k < sweeps && !gs; ++k) {
       if (m == 0)
         PROF(s, HOT_PROF_SMOOTH0, launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st));
       else
@@ -664,7 +725,13 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
   for (int m = M - 2; m >= 0; --m) {
     LevelView Lm = view(s, m);
     launch_prolong_add(Lm, view(s, m + 1), mx, us[m + 1], us[m], st);
-    for (int k = 0; k < sweeps; ++k) {
+    if (gs) {
+      if (m == 0)
+        PROF(s, HOT_PROF_SGS0, sgs_smooth(s, m, bs[m], us[m]));
+      else
+        sgs_smooth(s, m, bs[m], us[m]);
+    }
+    for (int k = 0; k < sweeps && !gs; ++k) {
       if (m == 0)
         PROF(s, HOT_PROF_SMOOTH0, launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st));
       else
@@ -705,6 +772,10 @@ double prof_launch_bytes(hot_scene* s, int kind) {
   bool mx = s->mixed;
   switch (kind) {
     case HOT_PROF_SMOOTH0: return mx ? 18.0 * nnz0 + 79.0 * n0 : 72.0 * nnz0 + 151.0 * n0;
+    // two passes, each reading every off-diagonal block, the diagonal-block
+    // inverse, b, the gathered iterate, the row list, node index, pattern and
+    // free flags once and writing the iterate once
+    case HOT_PROF_SGS0: return mx ? 2.0 * (18.0 * nnz0 + 85.0 * n0) : 2.0 * (72.0 * nnz0 + 107.0 * n0);
     case HOT_PROF_RESIDUAL0: return mx ? 18.0 * nnz0 + 40.0 * n0 : 72.0 * nnz0 + 76.0 * n0;
     case HOT_PROF_ASSEMBLE: return 72.0 * nnz0 + 456.0 * np + 111.0 * n0;
     case HOT_PROF_RAP0: return 72.0 * nnz0 + 23.0 * n0 + 72.0 * nnz1 + 111.0 * n1;
@@ -985,14 +1056,14 @@ void destroy(hot_scene* s) {
                  &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
                  &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
                  &s->bmap, &s->blist, &s->bpartial, &s->wnode, &s->tnodes, &s->tmap,
-                 &s->tpat, &s->tH};
+                 &s->tpat, &s->tH, &s->cscratch};
   for (DBuf* b : all) release(s, *b);
   for (auto& b : s->Sh) release(s, b);
   for (auto& b : s->Yh) release(s, b);
   for (int m = 0; m < kMaxLevels; ++m) {
     LevelH& L = s->L[m];
     DBuf* lb[] = {&L.nodes, &L.map, &L.H, &L.Hb, &L.Dinv, &L.Dinv32, &L.diag, &L.diag32,
-                  &L.freed, &L.pat, &L.b, &L.u, &L.r, &L.t};
+                  &L.freed, &L.pat, &L.b, &L.u, &L.r, &L.t, &L.crow, &L.coffd, &L.Dg, &L.Dg32};
     for (DBuf* b : lb) release(s, *b);
   }
   if (s->hscal) (void)hipHostFree(s->hscal);
@@ -1356,6 +1427,12 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
       sz = (size_t)L.n * kRowVals * 2;
       break;
     case HOT_DBG_LEVEL_FREE: src = L.freed.p; sz = (size_t)L.n * 3; break;
+    case HOT_DBG_LEVEL_COLOR_ROWS:
+      if (s->prm.smoother != HOT_SMOOTH_SGS || level + 1 >= s->levels)
+        return fail(HOT_E_INVALID, "colour lists exist only for HOT_SMOOTH_SGS smoothed levels");
+      src = L.crow.p;
+      sz = (size_t)L.n * 4;
+      break;
     case HOT_DBG_NODE_MASS: src = s->mass.p; sz = (size_t)s->L[0].n * 8; break;
     case HOT_DBG_NODE_VSTAR: src = s->vstar.p; sz = (size_t)s->L[0].n * 24; break;
     case HOT_DBG_NODE_XI: src = s->xi.p; sz = (size_t)s->L[0].n * 8; break;

@@ -32,6 +32,7 @@ constexpr int kRowVals = kSlots * kBlock;  // 1125 structural values per row
 constexpr int kSlotPad = 128;                // slots per entry plane (padded)
 constexpr int kRowStride = kBlock * kSlotPad;  // 1152 stored values per row
 constexpr int kCenter = 62;                // slot of offset (0,0,0)
+constexpr int kColors = 27;                // Gauss-Seidel colours (grid coordinate mod 3)
 constexpr int kMaxLevels = 8;
 constexpr int kMaxMats = 64;
 constexpr int kMaxBcs = 32;
@@ -223,6 +224,14 @@ void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, con
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
                              int* iters_out, int max_iter, double rel, hipStream_t st);
 size_t coarse_pcg_work_bytes(int n);
+// coloured symmetric Gauss-Seidel: rows of each colour (coff[0..27], device),
+// diagonal-block inverses, and one colour's in-place pass
+size_t color_scratch_bytes(int n);
+void launch_color_rows(const LevelView& L, int* scratch, int* coff, int* rows, hipStream_t st);
+void launch_block_diag_inv(const LevelView& L, double* Dg, float* Dg32, hipStream_t st);
+void launch_zero_rows(const LevelView& L, bool mixed, void* u, hipStream_t st);
+void launch_sgs_color(const LevelView& L, bool mixed, const int* rows, int cnt, const void* Dg,
+                      const void* b, void* u, hipStream_t st);
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st);
 
 // blas.hip: deterministic reductions and vector updates on FP64 node vectors.

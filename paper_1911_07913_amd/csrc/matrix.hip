@@ -194,17 +194,20 @@ struct SweepRows<float> {
   }
 };
 
-template <typename V, int R>
-__device__ inline void rows_matvec(const LevelView& L, int i0,
-                                   const typename Vec4Of<V>::type* __restrict__ x4, int lane,
-                                   V (&y)[R][3]) {
+// Row r of the wave: row_of(r, i) sets i and returns whether the row exists.
+// SkipCenter leaves out the diagonal block (the off-diagonal part of the row,
+// for Gauss-Seidel).
+template <typename V, int R, bool SkipCenter, typename RowOf>
+__device__ inline void rows_matvec_g(const LevelView& L, RowOf row_of,
+                                     const typename Vec4Of<V>::type* __restrict__ x4, int lane,
+                                     V (&y)[R][3]) {
   typedef typename MatOf<V>::type M;
   V h[R][2][9];
   int jp[R][2];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = i0 + r;
-    const bool live = i < L.n;
+    int i;
+    const bool live = row_of(r, i);
     const M* Hrow = MatOf<V>::H(L) + (long long)(live ? i : 0) * kRowStride;
     const int pn = live ? L.nodes[i] : 0;
     uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -214,7 +217,7 @@ __device__ inline void rows_matvec(const LevelView& L, int i0,
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int s = SweepRows<V>::slot(lane, k);
-      pr[k] = slot_present(w, s);
+      pr[k] = slot_present(w, s) && !(SkipCenter && s == kCenter);
       jp[r][k] = pr[k] ? pn + slot_offset(L.g, s) : -1;
     }
 #pragma unroll
@@ -237,6 +240,19 @@ __device__ inline void rows_matvec(const LevelView& L, int i0,
     y[r][1] = wave_sum_t(a1);
     y[r][2] = wave_sum_t(a2);
   }
+}
+
+template <typename V, int R>
+__device__ inline void rows_matvec(const LevelView& L, int i0,
+                                   const typename Vec4Of<V>::type* __restrict__ x4, int lane,
+                                   V (&y)[R][3]) {
+  rows_matvec_g<V, R, false>(
+      L,
+      [&](int r, int& i) {
+        i = i0 + r;
+        return i < L.n;
+      },
+      x4, lane, y);
 }
 
 // Component c of the dense 4-vector at grid point pn.
@@ -489,6 +505,135 @@ __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict
       V upd = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
       V out = comp<V>(u4, pn, c) + upd;
       comp<V>(uo4, pn, c) = L.free_dof[3 * i + c] ? out : (V)0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- coloured Gauss-Seidel
+// Symmetric block Gauss-Seidel (Alg. V-cycle smoother; Sec. 5.3 and Sec. 8
+// colour it for parallelism).  Nodes are coloured by their grid coordinate
+// mod 3 per axis (27 colours); a row couples nodes at most 2 apart per axis,
+// so rows of one colour never see each other and a colour is one parallel,
+// in-place pass.  A forward pass runs the colours 0..26, a backward pass
+// 26..0.  Per level and step: the rows of each colour (ascending row index)
+// and the inverses of the rows' 3x3 diagonal blocks.
+constexpr int kColorChunk = 256;  // rows per block of the colour counting
+
+__device__ inline int node_color(const GridGeom& g, int pn) {
+  int x, y, z;
+  unpidx(g, pn, x, y, z);
+  return x % 3 + 3 * (y % 3) + 9 * (z % 3);
+}
+
+// per-chunk colour counts, in row order (one thread walks the chunk)
+__global__ void k_color_counts(LevelView L, int* __restrict__ bc) {
+  const int r0 = blockIdx.x * kColorChunk, r1 = min(L.n, r0 + kColorChunk);
+  if (threadIdx.x < kColors) bc[blockIdx.x * kColors + threadIdx.x] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = r0; i < r1; ++i) bc[blockIdx.x * kColors + node_color(L.g, L.nodes[i])] += 1;
+}
+
+// Exclusive offsets: coff[c] = first position of colour c (coff[27] = n);
+// bc[b][c] becomes the first position of chunk b's rows of colour c.
+__global__ void k_color_offsets(int nchunks, int* __restrict__ bc, int* __restrict__ coff) {
+  __shared__ int tot[kColors];
+  const int c = threadIdx.x;
+  if (c < kColors) {
+    int run = 0;
+    for (int b = 0; b < nchunks; ++b) {
+      const int v = bc[b * kColors + c];
+      bc[b * kColors + c] = run;
+      run += v;
+    }
+    tot[c] = run;
+  }
+  __syncthreads();
+  if (c == 0) {
+    int run = 0;
+    for (int k = 0; k < kColors; ++k) {
+      coff[k] = run;
+      run += tot[k];
+    }
+    coff[kColors] = run;
+  }
+  __syncthreads();
+  if (c < kColors) {
+    const int base = coff[c];
+    for (int b = 0; b < nchunks; ++b) bc[b * kColors + c] += base;
+  }
+}
+
+__global__ void k_color_scatter(LevelView L, const int* __restrict__ bc, int* __restrict__ rows) {
+  __shared__ int cur[kColors];
+  const int r0 = blockIdx.x * kColorChunk, r1 = min(L.n, r0 + kColorChunk);
+  if (threadIdx.x < kColors) cur[threadIdx.x] = bc[blockIdx.x * kColors + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = r0; i < r1; ++i) rows[cur[node_color(L.g, L.nodes[i])]++] = i;
+}
+
+// Inverses of the 3x3 diagonal blocks (FP64, and FP32 copies in mixed mode).
+__global__ void k_block_diag_inv(LevelView L, double* __restrict__ Dg, float* __restrict__ Dg32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  const double* Hrow = L.H + (long long)i * kRowStride;
+  double A[9], B[9];
+  for (int c = 0; c < 9; ++c) A[c] = Hrow[c * kSlotPad + kCenter];
+  inv3(A, B);
+  for (int c = 0; c < 9; ++c) {
+    Dg[9 * (long long)i + c] = B[c];
+    if (Dg32) Dg32[9 * (long long)i + c] = (float)B[c];
+  }
+}
+
+// u at the level's active nodes set to zero (start of the down-sweep).
+template <typename V>
+__global__ void k_zero_rows(LevelView L, typename Vec4Of<V>::type* __restrict__ u4) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  typename Vec4Of<V>::type z;
+  z.x = z.y = z.z = z.w = 0;
+  u4[L.nodes[i]] = z;
+}
+
+// One colour of a pass: for the colour's rows i (rows[0..cnt)),
+// u_i = H_ii^{-1} (b_i - sum_{j != i} H_ij u_j), in place on the dense iterate,
+// projected on the free DOFs.  R rows per wave with their loads in flight, as
+// in the sweeps.
+template <typename V, int R>
+__global__ __launch_bounds__(256) void k_sgs_color(LevelView L, const int* __restrict__ rows,
+                                                   int cnt, const V* __restrict__ Dg,
+                                                   const V* __restrict__ b,
+                                                   typename Vec4Of<V>::type* __restrict__ u4) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
+  if (k0 >= cnt) return;
+  V y[R][3];
+  rows_matvec_g<V, R, true>(
+      L,
+      [&](int r, int& i) {
+        const bool live = k0 + r < cnt;
+        i = live ? rows[k0 + r] : 0;
+        return live;
+      },
+      u4, lane, y);
+  if (lane < 3 * R) {
+    const int rr = lane / 3, c = lane - 3 * rr;
+    V y0 = y[0][0], y1 = y[0][1], y2 = y[0][2];
+#pragma unroll
+    for (int q = 1; q < R; ++q)
+      if (q == rr) {
+        y0 = y[q][0];
+        y1 = y[q][1];
+        y2 = y[q][2];
+      }
+    if (k0 + rr < cnt) {
+      const int i = rows[k0 + rr];
+      const V* Di = Dg + 9 * (long long)i;
+      const V r0 = b[3 * i] - y0, r1 = b[3 * i + 1] - y1, r2 = b[3 * i + 2] - y2;
+      const V v = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
+      comp<V>(u4, L.nodes[i], c) = L.free_dof[3 * i + c] ? v : (V)0;
     }
   }
 }
@@ -1221,6 +1366,47 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
                                                            (double*)work, part, bar, iters_out,
                                                            max_iter, rel);
   return hipGetLastError();
+}
+
+size_t color_scratch_bytes(int n) {
+  return (size_t)((n + kColorChunk - 1) / kColorChunk + 1) * kColors * sizeof(int) +
+         (kColors + 1) * sizeof(int);
+}
+
+void launch_color_rows(const LevelView& L, int* scratch, int* coff, int* rows, hipStream_t st) {
+  const int nch = (L.n + kColorChunk - 1) / kColorChunk;
+  if (L.n == 0) return;
+  k_color_counts<<<nch, 64, 0, st>>>(L, scratch);
+  k_color_offsets<<<1, 64, 0, st>>>(nch, scratch, coff);
+  k_color_scatter<<<nch, 64, 0, st>>>(L, scratch, rows);
+}
+
+void launch_block_diag_inv(const LevelView& L, double* Dg, float* Dg32, hipStream_t st) {
+  if (L.n > 0) k_block_diag_inv<<<blocks_for(L.n), kTpb, 0, st>>>(L, Dg, Dg32);
+}
+
+void launch_zero_rows(const LevelView& L, bool mixed, void* u, hipStream_t st) {
+  if (L.n == 0) return;
+  if (mixed)
+    k_zero_rows<float><<<blocks_for(L.n), kTpb, 0, st>>>(L, (float4*)u);
+  else
+    k_zero_rows<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (double4*)u);
+}
+
+void launch_sgs_color(const LevelView& L, bool mixed, const int* rows, int cnt, const void* Dg,
+                      const void* b, void* u, hipStream_t st) {
+  if (cnt <= 0) return;
+  if (mixed) {
+    constexpr int R = SweepRows<float>::R;
+    const unsigned g = (unsigned)((cnt + kRowWaves * R - 1) / (kRowWaves * R));
+    k_sgs_color<float, R><<<g, 256, 0, st>>>(L, rows, cnt, (const float*)Dg, (const float*)b,
+                                             (float4*)u);
+  } else {
+    constexpr int R = SweepRows<double>::R;
+    const unsigned g = (unsigned)((cnt + kRowWaves * R - 1) / (kRowWaves * R));
+    k_sgs_color<double, R><<<g, 256, 0, st>>>(L, rows, cnt, (const double*)Dg,
+                                              (const double*)b, (double4*)u);
+  }
 }
 
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st) {

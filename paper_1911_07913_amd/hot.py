@@ -22,6 +22,8 @@ HOT_E_DEVICE = -3
 HOT_E_NONFINITE = -4
 HOT_FP64 = 0
 HOT_MIXED = 1
+HOT_SMOOTH_L1_JACOBI = 0
+HOT_SMOOTH_SGS = 1
 
 DBG_PERM = 1
 DBG_LEVEL_NODES = 10
@@ -29,6 +31,7 @@ DBG_LEVEL_PATTERN = 11
 DBG_LEVEL_MATRIX = 12
 DBG_LEVEL_FREE = 13
 DBG_LEVEL_MATRIX_BF16 = 14
+DBG_LEVEL_COLOR_ROWS = 15
 DBG_NODE_MASS = 20
 DBG_NODE_VSTAR = 21
 DBG_NODE_XI = 22
@@ -47,7 +50,7 @@ EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_partic
 BATCH_MAX_STEPS = 64
 
 PROF_KERNELS = {0: "smooth0", 1: "residual0", 2: "assemble_h0", 3: "rap0", 4: "particle_eval",
-                5: "gradient", 6: "particle_hessian"}
+                5: "gradient", 6: "particle_hessian", 7: "sgs0"}
 
 
 class hot_material(C.Structure):
@@ -78,7 +81,8 @@ class hot_params(C.Structure):
                 ("gravity", C.c_double * 3), ("cfl", C.c_double), ("max_dt", C.c_double),
                 ("tol", C.c_double), ("lbfgs_history", C.c_int32), ("mg_levels", C.c_int32),
                 ("max_iters", C.c_int32), ("smoother_sweeps", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("precision", C.c_int32), ("smoother", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class hot_step_stats(C.Structure):
@@ -178,7 +182,7 @@ def _dp(a):
 
 def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol=1e-6,
                 lbfgs_history=8, mg_levels=3, max_iters=500, smoother_sweeps=1,
-                precision=HOT_FP64):
+                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI):
     p = hot_params()
     p.dx = dx
     for a in range(3):
@@ -188,6 +192,7 @@ def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol
     p.cfl, p.max_dt, p.tol = cfl, max_dt, tol
     p.lbfgs_history, p.mg_levels, p.max_iters = int(lbfgs_history), int(mg_levels), int(max_iters)
     p.smoother_sweeps, p.precision = int(smoother_sweeps), int(precision)
+    p.smoother = int(smoother)
     return p
 
 

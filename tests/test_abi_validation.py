@@ -22,7 +22,7 @@ def _hot():
 def _init(hot, sc, **over):
     """hot_init_scene on a possibly corrupted copy; returns (status, message)."""
     params = hot.params_of(sc, **{k: v for k, v in over.items() if k in ("tol", "mg_levels",
-                                                                          "max_iters")})
+                                                                          "max_iters", "smoother")})
     L = hot.lib()
     x = np.ascontiguousarray(sc.x, dtype=np.float64)
     n = x.shape[0]
@@ -83,7 +83,7 @@ def test_invalid_scenes_are_refused(case):
 
 
 @pytest.mark.parametrize("field,value", [("mg_levels", 0), ("mg_levels", 9), ("max_iters", 0),
-                                         ("tol", -1.0)])
+                                         ("tol", -1.0), ("smoother", 2), ("smoother", -1)])
 def test_invalid_parameters_are_refused(field, value):
     hot = _hot()
     st, msg = _init(hot, _box(), **{field: value})
@@ -98,6 +98,9 @@ def test_footprint_grows_with_the_scene_and_with_mixed_blocks():
     fl = hot.footprint(hot.params_of(large), large.x)
     fm = hot.footprint(hot.params_of(large, hot.HOT_MIXED), large.x)
     assert 0 < fs < fl < fm
+    # the Gauss-Seidel colour lists and diagonal-block inverses are counted
+    fg = hot.footprint(hot.params_of(large, smoother=hot.HOT_SMOOTH_SGS), large.x)
+    assert fg > fl
     # at least the level-0 block rows: n0 rows of 1152 doubles
     import oracle as O
     n0 = O.active_fine_nodes(large).n
