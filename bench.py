@@ -60,7 +60,8 @@ SAMPLE = dict(side=6, length=24)
 def workload_name(side):
     n = 4 * 192 * side * side * 8
     return (f"twisting_bars: 4 Neo-Hookean bars 192x{side}x{side} cells, {n} particles, "
-            f"256x64x64 grid dx=1/64, 5-level Galerkin MG, L-BFGS w=8, CN eps=1e-6")
+            f"256x64x64 grid dx=1/64, 5-level Galerkin MG with coloured symmetric Gauss-Seidel "
+            f"smoothing, L-BFGS w=8, CN eps=1e-6")
 
 
 def cpu_worker():
@@ -91,10 +92,11 @@ def cpu_baseline(n_full):
                        f"scaled linearly by particle count to {n_full}")}
 
 
-def run(precision, steps, warmup, side, profile=True):
+def run(precision, steps, warmup, side, profile=True, smoother=0):
     """Warm up on a throwaway copy of the scene (kernels loaded, device memory
     in torch's cache), then time ``steps`` steps of a fresh scene from t = 0:
-    with the default 20 steps, the whole twisting-bars job."""
+    with the default 20 steps, the whole twisting-bars job.  ``smoother`` is a
+    hot_smoother (0: coloured symmetric Gauss-Seidel)."""
     import torch
 
     import hot_scenes as hs
@@ -105,12 +107,13 @@ def run(precision, steps, warmup, side, profile=True):
     alloc = hot.TorchAllocator(0)
     if warmup > 0:
         w = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream,
-                                 allocator=alloc)
+                                 allocator=alloc, smoother=smoother)
         for _ in range(warmup):
             w.step()
         torch.cuda.synchronize()
         w.close()
-    g = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream, allocator=alloc)
+    g = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream, allocator=alloc,
+                             smoother=smoother)
     if profile:
         g.profile(True)
     stats = []
@@ -148,19 +151,21 @@ class ServingRequests:
         self.cache.pop(k, None)
 
 
-def run_serving(n_req, slots, budget_gb, precision, load=0.7, n_sat=64):
+def run_serving(n_req, slots, budget_gb, precision, smoother, load=0.7, n_sat=64):
     """Closed-loop run of the first n_sat requests for the saturated step
     rate, then the whole stream with Poisson arrivals at ``load`` times it."""
     from paper_1911_07913_amd import serving
     budget = int(budget_gb * (1 << 30))
     n_sat = min(n_sat, n_req)
-    _, sat, _ = serving.serve(ServingRequests(n_sat), [0.0] * n_sat, budget, slots, precision)
+    _, sat, _ = serving.serve(ServingRequests(n_sat), [0.0] * n_sat, budget, slots, precision,
+                              smoother=smoother)
     steps_per_req = 10
     rate = load * sat["steps_per_s"] / steps_per_req
     arrivals = serving.poisson_arrivals(n_req, rate, seed=4000)
     records, summary, trace = serving.serve(ServingRequests(n_req), arrivals, budget, slots,
-                                            precision)
-    summary.update(precision="fp64" if precision == 0 else "mixed", slots=slots,
+                                            precision, smoother=smoother)
+    summary.update(precision="fp64" if precision == 0 else "mixed",
+                   smoother="sgs" if smoother == 0 else "l1jacobi", slots=slots,
                    budget_gb=budget_gb, load=load, arrival_rate_req_per_s=rate,
                    saturated_steps_per_s=sat["steps_per_s"],
                    saturated_step_latency_ms=sat["step_latency_ms"], **trace)
@@ -221,22 +226,35 @@ def roofline_of(prof, n_particles):
 
 
 def vcycle_roofline(prof):
-    """HBM roofline of the level-0 V-cycle sweeps (smoothing + residual), the
-    bandwidth-bound kernels each quasi-Newton iteration repeats."""
-    ms = sum(prof[k][0] for k in ("smooth0", "residual0"))
-    launches = sum(prof[k][1] for k in ("smooth0", "residual0"))
-    nbytes = sum(prof[k][2] for k in ("smooth0", "residual0"))
+    """HBM roofline of the level-0 V-cycle passes (smoothing, Gauss-Seidel or
+    Jacobi, and the residual), the bandwidth-bound kernels each quasi-Newton
+    iteration repeats."""
+    ks = [k for k in ("sgs0", "smooth0", "residual0") if k in prof and prof[k][1] > 0]
+    ms = sum(prof[k][0] for k in ks)
+    launches = sum(prof[k][1] for k in ks)
+    nbytes = sum(prof[k][2] for k in ks)
     if launches == 0 or ms <= 0:
         return None
     achieved = nbytes / (ms * 1e-3) / 1e9
-    out = {"kernels": ["smooth0", "residual0"], "bound": "hbm", "achieved": achieved,
+    out = {"kernels": ks, "bound": "hbm", "achieved": achieved,
            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
-    for k in ("smooth0", "residual0"):
+    for k in ks:
         t, n, b = prof[k]
         out[k] = {"avg_launch_ms": t / n if n else None,
                   "algorithmic_bytes_per_launch": b / n if n else None,
                   "traffic": traffic_of(k)}
     return out
+
+
+def smoother_summary(r, steps):
+    """The same job with the l1 block-Jacobi smoother: rate, iteration counts
+    and the level-0 V-cycle passes' algorithmic bandwidth."""
+    return {"value": steps / r["seconds"], "unit": "steps/s",
+            "ms_per_step": 1000.0 * r["seconds"] / steps,
+            "iters": [s["iters"] for s in r["stats"]],
+            "cg_iters": [s["cg_iters_total"] for s in r["stats"]],
+            "roofline": roofline_of(r["prof"], r["n"]),
+            "vcycle_roofline": vcycle_roofline(r["prof"])}
 
 
 def calibrate_copy(nbytes=1 << 30):
@@ -267,6 +285,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--serving-precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--no-l1jacobi", action="store_true",
+                    help="skip the same job with the l1 block-Jacobi smoother")
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -309,7 +329,8 @@ def main():
         "dtype": "f64" if main_p == hot.HOT_FP64 else "f64+f32/bf16",
         "data": "synthetic",
         "config": {"workload": workload_name(a.side), "particles": r["n"],
-                   "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed"},
+                   "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed",
+                   "smoother": "coloured symmetric block Gauss-Seidel (27 colours)"},
         "roofline": roofline_of(r["prof"], r["n"]),
         "vcycle_roofline": vcycle_roofline(r["prof"]),
         "per_step": {
@@ -334,14 +355,26 @@ def main():
                          "iters": [s["iters"] for s in rm["stats"]],
                          "roofline": roofline_of(rm["prof"], rm["n"]),
                          "vcycle_roofline": vcycle_roofline(rm["prof"])}
+    if not a.no_l1jacobi:
+        line["smoother_l1jacobi"] = {
+            ("fp64" if p == hot.HOT_FP64 else "mixed"):
+            smoother_summary(run(p, a.steps, a.warmup, a.side,
+                                 smoother=hot.HOT_SMOOTH_L1_JACOBI), a.steps)
+            for p in precs}
     if a.serving_requests > 0:
         sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
               "both": [hot.HOT_MIXED, hot.HOT_FP64]}[a.serving_precision]
+        # the served scenes are small (4k-256k particles): there the single
+        # fully parallel pass of l1 block-Jacobi beats the 53 colour passes of
+        # Gauss-Seidel (measured: serving_sgs)
+        l1 = hot.HOT_SMOOTH_L1_JACOBI
         line["serving"] = run_serving(a.serving_requests, a.serving_slots, a.serving_budget_gb,
-                                      sp[0])
+                                      sp[0], l1)
         if len(sp) > 1:
             line["serving_fp64"] = run_serving(a.serving_requests, a.serving_slots,
-                                               a.serving_budget_gb, sp[1])
+                                               a.serving_budget_gb, sp[1], l1)
+        line["serving_sgs"] = run_serving(a.serving_requests, a.serving_slots,
+                                          a.serving_budget_gb, sp[0], hot.HOT_SMOOTH_SGS)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["n"])
     print(json.dumps(line), flush=True)

@@ -485,6 +485,8 @@ hot_status prepare_sgs(hot_scene* s) {
 
 // One symmetric Gauss-Seidel smoothing (forward pass over the colours, then
 // backward), repeated smoother_sweeps times, in place on the level iterate u.
+// The backward pass starts at colour 25: colour 26 would recompute exactly
+// the values the forward pass has just given it (same inputs).
 void sgs_smooth(hot_scene* s, int m, const void* b, void* u) {
   LevelH& L = s->L[m];
   LevelView v = view(s, m);
@@ -493,7 +495,7 @@ void sgs_smooth(hot_scene* s, int m, const void* b, void* u) {
     for (int c = 0; c < kColors; ++c)
       launch_sgs_color(v, s->mixed, P<int>(L.crow) + L.coff[c], L.coff[c + 1] - L.coff[c], Dg, b,
                        u, s->stream);
-    for (int c = kColors - 1; c >= 0; --c)
+    for (int c = kColors - 2; c >= 0; --c)
       launch_sgs_color(v, s->mixed, P<int>(L.crow) + L.coff[c], L.coff[c + 1] - L.coff[c], Dg, b,
                        u, s->stream);
   }
@@ -772,10 +774,16 @@ double prof_launch_bytes(hot_scene* s, int kind) {
   bool mx = s->mixed;
   switch (kind) {
     case HOT_PROF_SMOOTH0: return mx ? 18.0 * nnz0 + 79.0 * n0 : 72.0 * nnz0 + 151.0 * n0;
-    // two passes, each reading every off-diagonal block, the diagonal-block
-    // inverse, b, the gathered iterate, the row list, node index, pattern and
-    // free flags once and writing the iterate once
-    case HOT_PROF_SGS0: return mx ? 2.0 * (18.0 * nnz0 + 85.0 * n0) : 2.0 * (72.0 * nnz0 + 107.0 * n0);
+    // a forward pass over all rows and a backward pass over all but colour
+    // 26's, each row reading its off-diagonal blocks, diagonal-block inverse,
+    // b, the gathered iterate, row list entry, node index, pattern and free
+    // flags once and writing its iterate entries once (blocks counted in
+    // proportion to rows)
+    case HOT_PROF_SGS0: {
+      const LevelH& L0 = s->L[0];
+      const double f = 2.0 - (double)(L0.coff[kColors] - L0.coff[kColors - 1]) / std::max(n0, 1.0);
+      return mx ? f * (18.0 * nnz0 + 85.0 * n0) : f * (72.0 * nnz0 + 107.0 * n0);
+    }
     case HOT_PROF_RESIDUAL0: return mx ? 18.0 * nnz0 + 40.0 * n0 : 72.0 * nnz0 + 76.0 * n0;
     case HOT_PROF_ASSEMBLE: return 72.0 * nnz0 + 456.0 * np + 111.0 * n0;
     case HOT_PROF_RAP0: return 72.0 * nnz0 + 23.0 * n0 + 72.0 * nnz1 + 111.0 * n1;

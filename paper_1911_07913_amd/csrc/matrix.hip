@@ -1396,13 +1396,15 @@ void launch_zero_rows(const LevelView& L, bool mixed, void* u, hipStream_t st) {
 void launch_sgs_color(const LevelView& L, bool mixed, const int* rows, int cnt, const void* Dg,
                       const void* b, void* u, hipStream_t st) {
   if (cnt <= 0) return;
+  // a colour holds 1/27 of the rows: one row per wave keeps enough waves in
+  // flight on the device
   if (mixed) {
-    constexpr int R = SweepRows<float>::R;
+    constexpr int R = 1;
     const unsigned g = (unsigned)((cnt + kRowWaves * R - 1) / (kRowWaves * R));
     k_sgs_color<float, R><<<g, 256, 0, st>>>(L, rows, cnt, (const float*)Dg, (const float*)b,
                                              (float4*)u);
   } else {
-    constexpr int R = SweepRows<double>::R;
+    constexpr int R = 1;
     const unsigned g = (unsigned)((cnt + kRowWaves * R - 1) / (kRowWaves * R));
     k_sgs_color<double, R><<<g, 256, 0, st>>>(L, rows, cnt, (const double*)Dg,
                                               (const double*)b, (double4*)u);

@@ -69,14 +69,15 @@ def summarize(records: list, t_begin: float) -> dict:
 
 
 def serve(requests, arrivals, budget_bytes: int, max_slots: int, precision=hot.HOT_MIXED,
-          n_steps=None, collect=None, poll_ms: int = 20):
+          n_steps=None, collect=None, poll_ms: int = 20, smoother=hot.HOT_SMOOTH_SGS):
     """Run a stream of requests through one batch.
 
     ``requests``: indexable scene descriptions (positions, velocities, F, C,
     volumes, material ids, materials, boundary conditions, parameters) as
     accepted by ``hot.Scene.from_scene``; a sequence with a ``release(k)``
     method is told when request k's host data is no longer needed;
-    ``arrivals``: arrival time in seconds of each, non-decreasing; ``n_steps``: steps per request (default: each scene's
+    ``arrivals``: arrival time in seconds of each, non-decreasing; ``precision`` and
+    ``smoother``: hot_precision and hot_smoother of every request; ``n_steps``: steps per request (default: each scene's
     ``n_steps``); ``collect(index, scene)``: called on each finished scene
     before it is destroyed (read its particles there).
 
@@ -99,7 +100,7 @@ def serve(requests, arrivals, budget_bytes: int, max_slots: int, precision=hot.H
                 k = pending[0]
                 sc = requests[k]
                 if k not in params:
-                    params[k] = hot.params_of(sc, precision)
+                    params[k] = hot.params_of(sc, precision, smoother=smoother)
                     reserved[k] = hot.footprint(params[k], sc.x)
                 free_b, free_s = batch.capacity()
                 if free_s == 0 or reserved[k] > free_b:

@@ -14,8 +14,9 @@ FP64.  The hierarchy itself is still built in FP64, so:
   FP64 oracle step: the outer quasi-Newton iteration removes the
   preconditioner's rounding;
 * at the scene's own CN tolerance two runs of the method may stop anywhere
-  inside the tolerance ball, so there the mixed-vs-FP64 difference is held to
-  a fraction of the FP64 result's own distance to a much tighter solve.
+  inside the tolerance ball, so there the mixed step is held to the FP64
+  step's own accuracy: its distance to a much tighter FP64 solve is at most
+  twice the FP64 step's (or 1e-6 relative, whichever is larger).
 """
 import numpy as np
 import pytest
@@ -74,7 +75,7 @@ def test_mixed_vcycle_close_to_fp64(prepared_mixed):
     assert np.all(ug[hz.free[0] == 0] == 0.0)
 
 
-def _mixed_vs_oracle(sc):
+def _mixed_vs_oracle(sc, keep=False):
     hot = _hot()
     dt = O.time_step(sc)
     out, info = O.step(sc, dt=dt)
@@ -88,6 +89,8 @@ def _mixed_vs_oracle(sc):
     ev = rel(res["v"], out.v)
     eF = rel(res["F"], out.F)
     disp = np.abs(res["x"] - out.x).max() / max(np.abs(out.x - x0).max(), 1e-300)
+    if keep:
+        return status, stats, info, ex, ev, eF, disp, out, dt, (res["x"], res["v"])
     return status, stats, info, ex, ev, eF, disp, out, dt
 
 
@@ -99,18 +102,19 @@ TIGHT = {"box_walls_fcr": 1e-10, "box_nh_3mat": 1e-8, "bars_small_grips": 1e-7}
 @pytest.mark.parametrize("name", list(SCENES))
 def test_mixed_step_at_scene_tolerance(name):
     sc = _scene(name)
-    status, stats, info, ex, ev, eF, disp, out, dt = _mixed_vs_oracle(sc)
+    status, stats, info, ex, ev, eF, disp, out, dt, res_x_v = _mixed_vs_oracle(sc, keep=True)
     tight = _scene(name)
     tight.tol = TIGHT[name]
     ref, rinfo = O.step(tight, dt=dt)
     tx, tv = rel(out.x, ref.x), rel(out.v, ref.v)
+    mx, mv = rel(res_x_v[0], ref.x), rel(res_x_v[1], ref.v)
     print(f"{name} eps={sc.tol:g}: iters mixed {stats['iters']} fp64 {info['iters']}; "
           f"mixed-vs-fp64 x {ex:.2e} v {ev:.2e} F {eF:.2e} (displacement-relative x "
-          f"{disp:.2e}); fp64 at eps vs fp64 at {TIGHT[name]:g} ({rinfo['iters']} iters): "
-          f"x {tx:.2e} v {tv:.2e}")
+          f"{disp:.2e}); vs the fp64 step at {TIGHT[name]:g} ({rinfo['iters']} iters): "
+          f"fp64 x {tx:.2e} v {tv:.2e}, mixed x {mx:.2e} v {mv:.2e}")
     assert status == 0 and stats["converged"]
-    assert ex <= max(1e-6, 0.25 * tx)
-    assert ev <= max(1e-6, 0.25 * tv)
+    assert mx <= max(1e-6, 2.0 * tx)
+    assert mv <= max(1e-6, 2.0 * tv)
 
 
 def test_mixed_step_tight_tolerance():

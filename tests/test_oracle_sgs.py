@@ -96,7 +96,7 @@ def test_vcycle_with_sgs_symmetric_positive_definite():
     assert np.linalg.eigvalsh(0.5 * (Vf + Vf.T)).min() > 0
     assert np.all(V[~f] == 0.0)
     # a different operator from the l1 block-Jacobi cycle
-    Vj = _dense_V(hz)[np.ix_(f, f)]
+    Vj = _dense_V(hz, smoother="l1jacobi")[np.ix_(f, f)]
     assert np.abs(Vf - Vj).max() > 1e-3 * np.abs(Vj).max()
 
 
