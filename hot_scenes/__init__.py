@@ -79,9 +79,11 @@ class Scene:
         return out
 
 
-def material(model: int, E: float, nu: float, density: float, yield_stress: float = 0.0) -> dict:
+def material(model: int, E: float, nu: float, density: float, yield_stress: float = 0.0,
+             snow_clamp=(0.0, 0.0)) -> dict:
     return dict(model=int(model), E=float(E), nu=float(nu), density=float(density),
-                yield_stress=float(yield_stress))
+                yield_stress=float(yield_stress),
+                snow_clamp=(float(snow_clamp[0]), float(snow_clamp[1])))
 
 
 def bc_walls(thickness: int) -> dict:

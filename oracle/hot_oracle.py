@@ -35,7 +35,8 @@ def lame(E, nu):
 
 
 def particle_materials(scene):
-    """Per-particle (model, mu, lambda, density, yield) arrays."""
+    """Per-particle (model, mu, lambda, density, yield) arrays (the snow
+    clamp interval comes from ``particle_snow_clamp``)."""
     mats = scene.materials
     mid = scene.mat_id
     model = np.array([m["model"] for m in mats], dtype=np.int32)[mid]
@@ -45,6 +46,12 @@ def particle_materials(scene):
     ys = np.array([m["yield_stress"] for m in mats])[mid]
     mu, lam = lame(E, nu)
     return model, mu, lam, rho, ys
+
+
+def particle_snow_clamp(scene):
+    """Per-particle snow clamp interval [lo, hi] ((0, 0): none)."""
+    c = np.array([m.get("snow_clamp", (0.0, 0.0)) for m in scene.materials], dtype=np.float64)
+    return c[scene.mat_id]
 
 
 def cn_xi(mu, lam):
@@ -861,6 +868,22 @@ def von_mises(F, mu, ys):
     return out
 
 
+def snow_clamp(F, clamp):
+    """Snow-type plastic flow (Sec. 7, table of material parameters, after
+    Stomakhin et al. 2013): after the step the singular values of F are
+    clamped into [lo, hi]; the rest of the deformation is plastic and
+    forgotten (no hardening).  Uses the signed SVD; rows with hi = 0 are
+    untouched."""
+    out = F.copy()
+    sel = clamp[:, 1] > 0
+    if not np.any(sel):
+        return out
+    U, S, V = svd_signed(F[sel])
+    Sc = np.clip(S, clamp[sel, 0:1], clamp[sel, 1:2])
+    out[sel] = U @ (Sc[:, :, None] * np.swapaxes(V, -1, -2))
+    return out
+
+
 def time_step(scene):
     """dt = min(1/FPS, CFL * dx / v_max) (Sec. 7.1 simulation settings);
     v_max includes prescribed boundary speeds."""
@@ -874,7 +897,8 @@ def time_step(scene):
 def g2p(st, dv):
     """Grid-to-particle APIC transfer, deformation update and advection
     (Sec. 3.1): v_p = sum w v_i; C_p = 4/dx^2 sum w v_i (x_i - x_p)^T;
-    F^{n+1} = (I + dt sum v_i grad w^T) F^n; lagged plasticity; x += dt v_p."""
+    F^{n+1} = (I + dt sum v_i grad w^T) F^n; lagged plasticity (von Mises or
+    the snow clamp); x += dt v_p."""
     sc = st.scene
     vnew = st.vstar + dv
     vel = vnew[st.idx]
@@ -883,6 +907,7 @@ def g2p(st, dv):
     gradv = np.einsum("pka,pkb->pab", vel, st.G)
     F = (np.eye(3)[None] + st.dt * gradv) @ sc.F
     F = von_mises(F, st.mu, st.yield_stress)
+    F = snow_clamp(F, particle_snow_clamp(sc))
     out = sc.copy()
     out.x = sc.x + st.dt * vp
     out.v = vp

@@ -244,3 +244,33 @@ def test_von_mises_return_mapping():
     assert np.array_equal(Fp[below], F[below])
     assert np.abs(O.von_mises(Fp, mu, ys) - Fp).max() < 1e-12
     assert np.array_equal(O.von_mises(F, mu, np.zeros(n)), F)
+
+
+def test_snow_clamp():
+    """Snow-type plastic flow: singular values of F clamped into [lo, hi]
+    (Sec. 7, table of material parameters: [0.99, 1.001])."""
+    rng = np.random.Generator(np.random.PCG64(79))
+    n = 400
+    U = np.linalg.qr(rng.normal(size=(n, 3, 3)))[0]
+    V = np.linalg.qr(rng.normal(size=(n, 3, 3)))[0]
+    U *= np.sign(np.linalg.det(U))[:, None, None]
+    V *= np.sign(np.linalg.det(V))[:, None, None]
+    s = np.exp(rng.normal(size=(n, 3)) * 0.01)
+    F = U @ (s[:, :, None] * np.swapaxes(V, 1, 2))
+    clamp = np.tile([0.99, 1.001], (n, 1))
+    Fc = O.snow_clamp(F, clamp)
+    # plain positive-singular-value reconstruction (det F > 0 here)
+    Ur, Sr, Vtr = np.linalg.svd(F)
+    ref = Ur @ (np.clip(Sr, 0.99, 1.001)[:, :, None] * Vtr)
+    assert np.abs(Fc - ref).max() < 1e-13
+    Sc = np.linalg.svd(Fc, compute_uv=False)
+    assert Sc.min() >= 0.99 - 1e-13 and Sc.max() <= 1.001 + 1e-13
+    inside = np.all((s >= 0.99) & (s <= 1.001), axis=1)
+    assert inside.sum() > 0 and (~inside).sum() > 0
+    assert np.abs(Fc[inside] - F[inside]).max() < 1e-14
+    assert np.abs(O.snow_clamp(Fc, clamp) - Fc).max() < 1e-14
+    # rotation equivariance, and no effect where no clamp is set
+    R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    R *= np.sign(np.linalg.det(R))
+    assert np.abs(O.snow_clamp(R @ F, clamp) - R @ Fc).max() < 1e-13
+    assert np.array_equal(O.snow_clamp(F, np.zeros((n, 2))), F)
