@@ -74,6 +74,12 @@ typedef struct {
   double yield_stress;  /* von Mises yield stress, Pa; 0 = purely elastic.
                            Applied once per step after the solve (lagged
                            plasticity, Sec. 2 and Sec. 8). */
+  double snow_clamp[2]; /* snow-type plastic flow (Sec. 7, table of material
+                           parameters, after Stomakhin et al. 2013): after
+                           each step the singular values of F are clamped
+                           into [snow_clamp[0], snow_clamp[1]] (the paper
+                           uses [0.99, 1.001]); {0, 0} = none.  Requires
+                           0 < lo <= 1 <= hi and yield_stress = 0. */
 } hot_material;
 
 /* Dirichlet boundary conditions, resolved by projection at every level

@@ -1117,6 +1117,13 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     if (!(m.nu > -1.0 && m.nu < 0.5)) return fail(HOT_E_INVALID, "nu must be in (-1, 0.5)");
     if (!(m.density > 0.0) || !std::isfinite(m.density)) return fail(HOT_E_INVALID, "density must be > 0");
     if (!(m.yield_stress >= 0.0)) return fail(HOT_E_INVALID, "yield_stress must be >= 0");
+    const double lo = m.snow_clamp[0], hi = m.snow_clamp[1];
+    if (!(lo == 0.0 && hi == 0.0)) {
+      if (!(lo > 0.0 && lo <= 1.0 && hi >= 1.0 && std::isfinite(hi)))
+        return fail(HOT_E_INVALID, "snow_clamp must satisfy 0 < lo <= 1 <= hi");
+      if (m.yield_stress > 0.0)
+        return fail(HOT_E_INVALID, "snow_clamp and yield_stress are exclusive");
+    }
   }
   for (int k = 0; k < n_bcs; ++k) {
     if (bcs[k].kind < 0 || bcs[k].kind > 2) return fail(HOT_E_INVALID, "bad bc kind");
@@ -1205,6 +1212,8 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     m.lam = lame_lam(mats[k].E, mats[k].nu);
     m.density = mats[k].density;
     m.yield = mats[k].yield_stress;
+    m.clamp_lo = mats[k].snow_clamp[0];
+    m.clamp_hi = mats[k].snow_clamp[1];
     m.xi = std::sqrt(3.0 * (2.0 * m.mu + m.lam) * (2.0 * m.mu + m.lam) + 6.0 * m.lam * m.lam);
   }
   sd.n_bcs = n_bcs;

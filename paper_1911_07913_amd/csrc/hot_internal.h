@@ -40,6 +40,7 @@ constexpr int kMaxBcs = 32;
 struct MaterialDev {
   int model;   // 0 = fixed-corotated, 1 = Neo-Hookean
   double mu, lam, density, yield, xi;
+  double clamp_lo, clamp_hi;  // snow clamp of the singular values (hi = 0: none)
 };
 
 struct BcDev {

@@ -398,6 +398,18 @@ __device__ inline void von_mises(double* F, double mu, double ys) {
                      U[3 * r + 2] * sn[2] * V[3 * c + 2];
 }
 
+// Snow-type plastic flow (Sec. 7, table of material parameters): the
+// singular values of F clamped into [lo, hi], F = U clamp(S) V^T (signed SVD).
+__device__ inline void snow_clamp(double* F, double lo, double hi) {
+  double U[9], s[3], V[9];
+  svd3(F, U, s, V);
+  for (int a = 0; a < 3; ++a) s[a] = fmin(fmax(s[a], lo), hi);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      F[3 * r + c] = U[3 * r] * s[0] * V[3 * c] + U[3 * r + 1] * s[1] * V[3 * c + 1] +
+                     U[3 * r + 2] * s[2] * V[3 * c + 2];
+}
+
 // Grid-to-particle APIC transfer, deformation update, lagged plasticity and
 // advection (Sec. 3.1).
 __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
@@ -438,6 +450,7 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
     }
   const MaterialDev& md = s.mats[mat[p]];
   if (md.yield > 0.0) von_mises(F, md.mu, md.yield);
+  if (md.clamp_hi > 0.0) snow_clamp(F, md.clamp_lo, md.clamp_hi);
   double cs = 4.0 / (s.dx * s.dx);
   for (int i = 0; i < 9; ++i) {
     Fn[9 * (long long)p + i] = F[i];

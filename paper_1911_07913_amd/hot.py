@@ -55,7 +55,8 @@ PROF_KERNELS = {0: "smooth0", 1: "residual0", 2: "assemble_h0", 3: "rap0", 4: "p
 
 class hot_material(C.Structure):
     _fields_ = [("model", C.c_int32), ("E", C.c_double), ("nu", C.c_double),
-                ("density", C.c_double), ("yield_stress", C.c_double)]
+                ("density", C.c_double), ("yield_stress", C.c_double),
+                ("snow_clamp", C.c_double * 2)]
 
 
 class hot_bc(C.Structure):
@@ -243,8 +244,10 @@ class Scene:
         mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(n)
         mats = (hot_material * len(materials))()
         for k, m in enumerate(materials):
+            sc2 = m.get("snow_clamp", (0.0, 0.0))
             mats[k] = hot_material(int(m["model"]), m["E"], m["nu"], m["density"],
-                                   m.get("yield_stress", 0.0))
+                                   m.get("yield_stress", 0.0),
+                                   (C.c_double * 2)(float(sc2[0]), float(sc2[1])))
         nb = len(bcs)
         cb = (hot_bc * max(nb, 1))()
         for k, b in enumerate(bcs):

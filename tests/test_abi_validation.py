@@ -28,8 +28,9 @@ def _init(hot, sc, **over):
     n = x.shape[0]
     mats = (hot.hot_material * len(sc.materials))()
     for k, m in enumerate(sc.materials):
+        c2 = m.get("snow_clamp", (0.0, 0.0))
         mats[k] = hot.hot_material(int(m["model"]), m["E"], m["nu"], m["density"],
-                                   m.get("yield_stress", 0.0))
+                                   m.get("yield_stress", 0.0), (C.c_double * 2)(*c2))
     bcs = (hot.hot_bc * max(len(sc.bcs), 1))()
     for k, b in enumerate(sc.bcs):
         bcs[k].kind = int(b["kind"])
@@ -56,7 +57,8 @@ def _box():
 
 
 @pytest.mark.parametrize("case", ["nan_x", "outside", "E_zero", "nu_half", "bad_mat_id",
-                                  "nan_v", "vol_zero", "nh_inverted"])
+                                  "nan_v", "vol_zero", "nh_inverted", "snow_lo_above_1",
+                                  "snow_with_yield"])
 def test_invalid_scenes_are_refused(case):
     hot = _hot()
     sc = _box()
@@ -77,6 +79,11 @@ def test_invalid_scenes_are_refused(case):
     elif case == "nh_inverted":
         sc.materials[0]["model"] = 1
         sc.F[5] = np.diag([1.0, 1.0, -1.0])
+    elif case == "snow_lo_above_1":
+        sc.materials[0]["snow_clamp"] = (1.01, 1.02)
+    elif case == "snow_with_yield":
+        sc.materials[0]["snow_clamp"] = (0.99, 1.001)
+        sc.materials[0]["yield_stress"] = 100.0
     st, msg = _init(hot, sc)
     assert st == hot.HOT_E_INVALID, (case, st, msg)
     assert msg

@@ -81,3 +81,43 @@ def test_plastic_steps_fp64(name):
             cur = out
     finally:
         g.close()
+
+
+def test_snow_clamp_steps_fp64():
+    """Snow-type plastic flow (singular values of F clamped into
+    [0.99, 1.001] after each step): two steps against the oracle, every
+    decision identical, x, v, F within 1e-10; the GPU's output F has its
+    singular values inside the interval and many particles sit on a bound."""
+    hot = _hot()
+    sc = hs.small_box(seed=104, cells=(12, 12, 12), box_lo=(3, 3, 3), box_hi=(9, 8, 8),
+                      walls=2, levels=2, F_spread=0.05)
+    sc.materials[0]["snow_clamp"] = (0.99, 1.001)
+    sc.n_steps = 2
+    g = hot.Scene.from_scene(sc)
+    cur, t = sc, 0.0
+    try:
+        for k in range(sc.n_steps):
+            dt = O.time_step(cur)
+            out, info = O.step(cur, dt=dt, t=t)
+            t += dt
+            status = g.step(dt)
+            res = g.read()
+            logi = g.debug_read(hot.DBG_LOG_INT, dtype=np.int32).reshape(-1, 4)
+            log = info["log"]
+            assert status in (0, 1)
+            assert g.stats["iters"] == info["iters"], f"step {k}"
+            assert list(logi[:, 0]) == log["alpha_halvings"]
+            assert list(logi[:, 3]) == [sum(c) for c in log["cg"]]
+            assert rel(res["x"], out.x) < 1e-10, f"step {k}"
+            assert rel(res["v"], out.v) < 1e-10, f"step {k}"
+            assert rel(res["F"], out.F) < 1e-10, f"step {k}"
+            s = np.linalg.svd(res["F"], compute_uv=False)
+            assert s.min() >= 0.99 - 1e-12 and s.max() <= 1.001 + 1e-12
+            on_bound = np.count_nonzero(np.any((np.abs(s - 0.99) < 1e-12) |
+                                               (np.abs(s - 1.001) < 1e-12), axis=1))
+            print(f"snow step {k}: {on_bound} of {sc.n} particles on a clamp bound, "
+                  f"iters {info['iters']}")
+            assert on_bound > sc.n // 2
+            cur = out
+    finally:
+        g.close()
