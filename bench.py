@@ -60,8 +60,8 @@ SAMPLE = dict(side=6, length=24)
 def workload_name(side):
     n = 4 * 192 * side * side * 8
     return (f"twisting_bars: 4 Neo-Hookean bars 192x{side}x{side} cells, {n} particles, "
-            f"256x64x64 grid dx=1/64, 5-level Galerkin MG with coloured symmetric Gauss-Seidel "
-            f"smoothing, L-BFGS w=8, CN eps=1e-6")
+            f"256x64x64 grid dx=1/64, 5-level Galerkin MG with l1 block-Jacobi smoothing, "
+            f"L-BFGS w=8, CN eps=1e-6")
 
 
 def cpu_worker():
@@ -96,7 +96,7 @@ def run(precision, steps, warmup, side, profile=True, smoother=0):
     """Warm up on a throwaway copy of the scene (kernels loaded, device memory
     in torch's cache), then time ``steps`` steps of a fresh scene from t = 0:
     with the default 20 steps, the whole twisting-bars job.  ``smoother`` is a
-    hot_smoother (0: coloured symmetric Gauss-Seidel)."""
+    hot_smoother (0: l1 block-Jacobi, 1: coloured symmetric Gauss-Seidel)."""
     import torch
 
     import hot_scenes as hs
@@ -247,8 +247,9 @@ def vcycle_roofline(prof):
 
 
 def smoother_summary(r, steps):
-    """The same job with the l1 block-Jacobi smoother: rate, iteration counts
-    and the level-0 V-cycle passes' algorithmic bandwidth."""
+    """The same job with the paper's coloured symmetric Gauss-Seidel smoother:
+    rate, iteration counts and the level-0 V-cycle passes' algorithmic
+    bandwidth."""
     return {"value": steps / r["seconds"], "unit": "steps/s",
             "ms_per_step": 1000.0 * r["seconds"] / steps,
             "iters": [s["iters"] for s in r["stats"]],
@@ -285,8 +286,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--serving-precision", default="both", choices=["fp64", "mixed", "both"])
-    ap.add_argument("--no-l1jacobi", action="store_true",
-                    help="skip the same job with the l1 block-Jacobi smoother")
+    ap.add_argument("--no-sgs", action="store_true",
+                    help="skip the same job with the coloured Gauss-Seidel smoother")
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -330,7 +331,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(a.side), "particles": r["n"],
                    "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed",
-                   "smoother": "coloured symmetric block Gauss-Seidel (27 colours)"},
+                   "smoother": "l1 block-Jacobi"},
         "roofline": roofline_of(r["prof"], r["n"]),
         "vcycle_roofline": vcycle_roofline(r["prof"]),
         "per_step": {
@@ -355,11 +356,11 @@ def main():
                          "iters": [s["iters"] for s in rm["stats"]],
                          "roofline": roofline_of(rm["prof"], rm["n"]),
                          "vcycle_roofline": vcycle_roofline(rm["prof"])}
-    if not a.no_l1jacobi:
-        line["smoother_l1jacobi"] = {
+    if not a.no_sgs:
+        line["smoother_sgs"] = {
             ("fp64" if p == hot.HOT_FP64 else "mixed"):
             smoother_summary(run(p, a.steps, a.warmup, a.side,
-                                 smoother=hot.HOT_SMOOTH_L1_JACOBI), a.steps)
+                                 smoother=hot.HOT_SMOOTH_SGS), a.steps)
             for p in precs}
     if a.serving_requests > 0:
         sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],

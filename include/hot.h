@@ -56,15 +56,16 @@ typedef enum { HOT_FCR = 0, HOT_NEOHOOKEAN = 1 } hot_model;
 typedef enum { HOT_FP64 = 0, HOT_MIXED = 1 } hot_precision;
 
 /* Smoother of the V-cycle's non-coarsest levels (Alg. V-cycle).
- * HOT_SMOOTH_SGS (0, the default): the paper's coloured symmetric block
- *   Gauss-Seidel (Sec. 5.3, Sec. 8): nodes coloured by grid coordinate mod 3
- *   per axis (27 colours), a forward pass over colours 0..26 then a backward
- *   pass 26..0, each node taking u_i = H_ii^{-1} (b_i - sum_{j != i} H_ij u_j).
- * HOT_SMOOTH_L1_JACOBI (1): l1 block-Jacobi, u += D~^{-1} (b - H u), D~ the
- *   3x3 diagonal block plus the l1 sums of the rest of the row on its
- *   diagonal; one fully parallel pass per sweep, cheaper per cycle, weaker.
- * smoother_sweeps counts forward-backward pairs (SGS) or sweeps (Jacobi). */
-typedef enum { HOT_SMOOTH_SGS = 0, HOT_SMOOTH_L1_JACOBI = 1 } hot_smoother;
+ * HOT_SMOOTH_L1_JACOBI (0, the default): l1 block-Jacobi,
+ *   u += D~^{-1} (b - H u), D~ the 3x3 diagonal block plus the l1 sums of the
+ *   rest of the row on its diagonal; one fully parallel pass per sweep.
+ * HOT_SMOOTH_SGS (1): the paper's coloured symmetric block Gauss-Seidel
+ *   (Sec. 5.3, Sec. 8): nodes coloured by grid coordinate mod 3 per axis (27
+ *   colours), a forward pass over colours 0..26 then a backward pass 26..0,
+ *   each node taking u_i = H_ii^{-1} (b_i - sum_{j != i} H_ij u_j); costlier
+ *   per cycle, far fewer L-BFGS iterations on stiff scenes.
+ * smoother_sweeps counts sweeps (Jacobi) or forward-backward pairs (SGS). */
+typedef enum { HOT_SMOOTH_L1_JACOBI = 0, HOT_SMOOTH_SGS = 1 } hot_smoother;
 
 typedef struct {
   int32_t model;        /* hot_model */

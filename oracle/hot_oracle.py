@@ -624,7 +624,7 @@ def l1_block_jacobi_inverse(A):
     return sp.csr_matrix((Dinv.ravel(), (rows.ravel(), cols.ravel())), shape=A.shape)
 
 
-SMOOTHERS = ("sgs", "l1jacobi")
+SMOOTHERS = ("l1jacobi", "sgs")
 N_COLORS = 27
 
 
@@ -712,9 +712,9 @@ def coarse_pcg(A, diag, b, rel=0.5, max_iter=500, log=None):
     return x
 
 
-def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None, smoother="sgs"):
-    """Multigrid V-cycle (Alg. V-cycle) with the paper's coloured symmetric
-    block Gauss-Seidel smoothing, or with l1 block-Jacobi (smoother="l1jacobi").
+def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None, smoother="l1jacobi"):
+    """Multigrid V-cycle (Alg. V-cycle) with l1 block-Jacobi smoothing, or with
+    the paper's coloured symmetric block Gauss-Seidel (smoother="sgs").
 
     Down: u^m = smooth(0, b^m); b^{m+1} = P~^T (b^m - H^m u^m).  Coarsest: PCG
     to relative 1/2.  Up: u^m += P~ u^{m+1}; u^m = smooth(u^m, b^m)."""
@@ -772,7 +772,7 @@ def two_loop(hist, g, apply_H0):
 
 
 def solve(st, hz, tol, history, max_iters=500, sweeps=1, c1=1e-4, max_halvings=30,
-          smoother="sgs"):
+          smoother="l1jacobi"):
     """HOT quasi-Newton solve (Alg. HOT).
 
     dv^1 = 0; while the CN-scaled gradient norm exceeds eps*sqrt(n): two-loop
@@ -917,7 +917,7 @@ def g2p(st, dv):
 
 
 def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=None,
-         sweeps=1, return_internals=False, smoother="sgs"):
+         sweeps=1, return_internals=False, smoother="l1jacobi"):
     """One implicit MPM step: P2G, HOT solve for dv, G2P (Sec. 3.1, Alg. HOT)."""
     if dt is None or dt <= 0:
         dt = time_step(scene)

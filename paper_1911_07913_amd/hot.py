@@ -22,8 +22,8 @@ HOT_E_DEVICE = -3
 HOT_E_NONFINITE = -4
 HOT_FP64 = 0
 HOT_MIXED = 1
-HOT_SMOOTH_SGS = 0
-HOT_SMOOTH_L1_JACOBI = 1
+HOT_SMOOTH_L1_JACOBI = 0
+HOT_SMOOTH_SGS = 1
 
 DBG_PERM = 1
 DBG_LEVEL_NODES = 10
@@ -183,7 +183,7 @@ def _dp(a):
 
 def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol=1e-6,
                 lbfgs_history=8, mg_levels=3, max_iters=500, smoother_sweeps=1,
-                precision=HOT_FP64, smoother=HOT_SMOOTH_SGS):
+                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI):
     p = hot_params()
     p.dx = dx
     for a in range(3):

@@ -69,7 +69,7 @@ def summarize(records: list, t_begin: float) -> dict:
 
 
 def serve(requests, arrivals, budget_bytes: int, max_slots: int, precision=hot.HOT_MIXED,
-          n_steps=None, collect=None, poll_ms: int = 20, smoother=hot.HOT_SMOOTH_SGS):
+          n_steps=None, collect=None, poll_ms: int = 20, smoother=hot.HOT_SMOOTH_L1_JACOBI):
     """Run a stream of requests through one batch.
 
     ``requests``: indexable scene descriptions (positions, velocities, F, C,

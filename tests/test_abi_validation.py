@@ -105,10 +105,9 @@ def test_footprint_grows_with_the_scene_and_with_mixed_blocks():
     fl = hot.footprint(hot.params_of(large), large.x)
     fm = hot.footprint(hot.params_of(large, hot.HOT_MIXED), large.x)
     assert 0 < fs < fl < fm
-    # the Gauss-Seidel colour lists and diagonal-block inverses (default
-    # smoother) are counted: the l1 block-Jacobi scene needs less
-    fj = hot.footprint(hot.params_of(large, smoother=hot.HOT_SMOOTH_L1_JACOBI), large.x)
-    assert fj < fl
+    # the Gauss-Seidel colour lists and diagonal-block inverses are counted
+    fg = hot.footprint(hot.params_of(large, smoother=hot.HOT_SMOOTH_SGS), large.x)
+    assert fg > fl
     # at least the level-0 block rows: n0 rows of 1152 doubles
     import oracle as O
     n0 = O.active_fine_nodes(large).n

@@ -1,13 +1,14 @@
-"""The two V-cycle smoothers on the HIP path, through the C ABI, against the
-oracle.  The other GPU tests run the default, the paper's coloured symmetric
-block Gauss-Seidel (HOT_SMOOTH_SGS); this file adds
+"""The V-cycle smoothers on the HIP path, through the C ABI, against the
+oracle.  The other GPU tests run the default l1 block-Jacobi smoother; this
+file covers the paper's coloured symmetric block Gauss-Seidel
+(HOT_SMOOTH_SGS):
 
-* the rows ordered by colour (grid coordinate mod 3 per axis, ascending row
+* rows ordered by colour (grid coordinate mod 3 per axis, ascending row
   index within a colour), bit-exact at every smoothed level;
-* the l1 block-Jacobi alternative (HOT_SMOOTH_L1_JACOBI): one V-cycle element
-  by element, and full FP64 steps with every discrete decision of the solve
-  (halvings, fallbacks, skipped pairs, coarse-PCG counts, iteration count)
-  identical and x, v, F within 1e-10;
+* one V-cycle element by element (FP64 sums in another order);
+* full FP64 steps with every discrete decision of the solve (halvings,
+  fallbacks, skipped pairs, coarse-PCG counts, iteration count) identical and
+  x, v, F within 1e-10;
 * mixed precision with either smoother: the V-cycle differs from the FP64
   oracle by the BF16 block rounding only, and a step converged to a tight
   tolerance lands on the FP64 oracle's step.
@@ -20,7 +21,7 @@ from test_gpu_parity import SCENES, _grip_scene, _hot, oracle_prepare, rel
 
 pytestmark = pytest.mark.gpu
 
-SMOOTHERS = {"sgs": 0, "l1jacobi": 1}
+SMOOTHERS = {"l1jacobi": 0, "sgs": 1}
 
 
 def _scene(name):
@@ -28,54 +29,46 @@ def _scene(name):
 
 
 @pytest.fixture(scope="module", params=list(SCENES))
-def prepared_l1(request):
+def prepared_sgs(request):
     hot = _hot()
     sc = _scene(request.param)
     dt = O.time_step(sc)
     st, hz = oracle_prepare(sc, dt)
-    g = hot.Scene.from_scene(sc, smoother=hot.HOT_SMOOTH_L1_JACOBI)
+    g = hot.Scene.from_scene(sc, smoother=hot.HOT_SMOOTH_SGS)
     g.debug_prepare(dt)
     yield request.param, sc, dt, st, hz, g
     g.close()
 
 
-@pytest.mark.parametrize("name", list(SCENES))
-def test_color_rows_bit_exact(name):
+def test_color_rows_bit_exact(prepared_sgs):
     hot = _hot()
-    sc = _scene(name)
-    dt = O.time_step(sc)
-    st, hz = oracle_prepare(sc, dt)
-    g = hot.Scene.from_scene(sc)
-    try:
-        g.debug_prepare(dt)
-        for m in range(len(hz.levels) - 1):
-            lev = hz.levels[m]
-            want = np.lexsort((np.arange(lev.n), O.node_colors(lev)))
-            got = g.debug_read(hot.DBG_LEVEL_COLOR_ROWS, m, dtype=np.int32)
-            assert np.array_equal(got, want), f"level {m}"
-    finally:
-        g.close()
+    name, sc, dt, st, hz, g = prepared_sgs
+    for m in range(len(hz.levels) - 1):
+        lev = hz.levels[m]
+        want = np.lexsort((np.arange(lev.n), O.node_colors(lev)))
+        got = g.debug_read(hot.DBG_LEVEL_COLOR_ROWS, m, dtype=np.int32)
+        assert np.array_equal(got, want), f"level {m}"
 
 
-def test_vcycle_l1jacobi(prepared_l1):
-    name, sc, dt, st, hz, g = prepared_l1
+def test_vcycle_sgs(prepared_sgs):
+    name, sc, dt, st, hz, g = prepared_sgs
     n = st.lev0.n
     rng = np.random.Generator(np.random.PCG64(15))
     for k in range(2):
         b = rng.normal(size=3 * n) * hz.free[0]
-        uo = O.vcycle(hz, b, smoother="l1jacobi")
+        uo = O.vcycle(hz, b, smoother="sgs")
         ug = g.debug_apply(0, b)
         assert rel(ug, uo) < 1e-11, f"cycle {k}"
         assert np.all(ug[hz.free[0] == 0] == 0.0)
 
 
 @pytest.mark.parametrize("name", list(SCENES))
-def test_full_step_l1jacobi_fp64(name):
+def test_full_step_sgs_fp64(name):
     hot = _hot()
     sc = _scene(name)
     dt = O.time_step(sc)
-    out, info = O.step(sc, dt=dt, smoother="l1jacobi")
-    g = hot.Scene.from_scene(sc, smoother=hot.HOT_SMOOTH_L1_JACOBI)
+    out, info = O.step(sc, dt=dt, smoother="sgs")
+    g = hot.Scene.from_scene(sc, smoother=hot.HOT_SMOOTH_SGS)
     try:
         g.step(dt)
         res = g.read()
@@ -84,7 +77,7 @@ def test_full_step_l1jacobi_fp64(name):
     finally:
         g.close()
     log = info["log"]
-    print(f"{name}: l1 block-Jacobi iterations {stats['iters']}")
+    print(f"{name}: Gauss-Seidel iterations {stats['iters']}")
     assert stats["iters"] == info["iters"]
     assert list(logi[:, 0]) == log["alpha_halvings"]
     assert list(logi[:, 2]) == log["fallback"]

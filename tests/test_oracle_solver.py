@@ -94,7 +94,7 @@ def _hz(sc, dt, levels):
     return st, O.build_hierarchy(st, H0, nbr0, levels)
 
 
-def _dense_V(hz, sweeps=1, smoother="sgs"):
+def _dense_V(hz, sweeps=1, smoother="l1jacobi"):
     Ac = hz.A[-1].toarray()
     solve = lambda b: np.linalg.solve(Ac, b)
     N = hz.A[0].shape[0]
@@ -188,8 +188,8 @@ def test_converged_step_matches_dense_newton(model, walls, mats):
     st = O.prepare(sc, dt)
     H0, nbr0 = O.hessian_slots(st)
     hz = O.build_hierarchy(st, H0, nbr0, 2)
-    # the l1 block-Jacobi cycle here; the Gauss-Seidel cycle has its own pin
-    dv, info = O.solve(st, hz, tol=1e-12, history=8, max_iters=300, smoother="l1jacobi")
+    # the l1 block-Jacobi cycle; the Gauss-Seidel cycle has its own pin
+    dv, info = O.solve(st, hz, tol=1e-12, history=8, max_iters=300)
     ref = dense_newton(st)
     a, b = O.g2p(st, dv), O.g2p(st, ref)
     assert np.abs(a.v - b.v).max() < 1e-7 * np.abs(b.v).max()
