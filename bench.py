@@ -92,17 +92,18 @@ def cpu_baseline(n_full):
                        f"scaled linearly by particle count to {n_full}")}
 
 
-def run(precision, steps, warmup, side, profile=True, smoother=0):
+def run(precision, steps, warmup, side, profile=True, smoother=0, scene=None):
     """Warm up on a throwaway copy of the scene (kernels loaded, device memory
     in torch's cache), then time ``steps`` steps of a fresh scene from t = 0:
     with the default 20 steps, the whole twisting-bars job.  ``smoother`` is a
-    hot_smoother (0: l1 block-Jacobi, 1: coloured symmetric Gauss-Seidel)."""
+    hot_smoother (0: l1 block-Jacobi, 1: coloured symmetric Gauss-Seidel).
+    ``scene``: another workload in place of the twisting bars."""
     import torch
 
     import hot_scenes as hs
     from paper_1911_07913_amd import hot
 
-    sc = hs.twisting_bars(side=side)
+    sc = hs.twisting_bars(side=side) if scene is None else scene
     stream = torch.cuda.Stream()
     alloc = hot.TorchAllocator(0)
     if warmup > 0:
@@ -288,6 +289,8 @@ def main():
     ap.add_argument("--serving-precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-sgs", action="store_true",
                     help="skip the same job with the coloured Gauss-Seidel smoother")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the 8.2M-particle sphere-slab job")
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -362,6 +365,19 @@ def main():
             smoother_summary(run(p, a.steps, a.warmup, a.side,
                                  smoother=hot.HOT_SMOOTH_SGS), a.steps)
             for p in precs}
+    if not a.no_slab:
+        # the larger configuration: 8,192,000 particles, 30 steps, both precisions
+        import hot_scenes as hs
+        slab = {}
+        for p in (hot.HOT_MIXED, hot.HOT_FP64):
+            rs = run(p, 30, 1, a.side, profile=False, scene=hs.sphere_slab())
+            slab["mixed" if p == hot.HOT_MIXED else "fp64"] = {
+                "value": 30 / rs["seconds"], "unit": "steps/s",
+                "ms_per_step": 1000.0 * rs["seconds"] / 30,
+                "iters": [st["iters"] for st in rs["stats"]]}
+        line["sphere_slab_8M"] = {"workload": "sphere_slab: FCR von Mises slab 160x40x160 cells, "
+                                  "8192000 particles, 192^3 grid dx=1/192, 4-level Galerkin MG, "
+                                  "rigid sphere at 3 m/s, 30 steps", **slab}
     if a.serving_requests > 0:
         sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
               "both": [hot.HOT_MIXED, hot.HOT_FP64]}[a.serving_precision]

@@ -213,7 +213,7 @@ def twisting_bars(side=16, seed=1000, length=192, n_steps=20) -> Scene:
 
 
 def sphere_slab(seed=3000, n=192, slab=(160, 40, 160), y0=24, radius=0.1, speed=3.0,
-                levels=5, n_steps=30) -> Scene:
+                levels=4, n_steps=30) -> Scene:
     """Elastoplastic FCR slab (von Mises, yield 1e5 Pa) struck by a rigid sphere.
 
     192^3 grid, dx = 1/192, slab of 160x40x160 cells (8.19M particles), sphere of

@@ -12,6 +12,8 @@ scene:  node mass, v*, CN stiffness, the gradient at dv = 0 and the whole
 125-block row of the level-0 Hessian.  Finally one full step at this size
 must converge with a decreasing incremental potential.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -118,3 +120,42 @@ def test_full_size_step_converges_and_decreases_energy():
     assert status == 0 and st["converged"]
     assert st["E"] < st["E0"]
     assert st["cn"] <= st["cn_tol"] < st["cn0"]
+
+
+def test_sphere_slab_full_size_mixed():
+    """The 8,192,000-particle sphere slab (192^3 grid, dx = 1/192, 4 levels,
+    von Mises FCR, rigid sphere at 3 m/s) in mixed precision, as the
+    benchmark runs it: binning permutation and every level's node set
+    bit-exact against the oracle; two steps converge with decreasing
+    incremental potential, and every particle ends on or inside the yield
+    surface."""
+    hot = _hot()
+    sc = hs.sphere_slab()
+    _, perm = O.bin_particles(sc)
+    lev = O.active_fine_nodes(sc)
+    g = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
+    try:
+        g.debug_prepare(O.time_step(sc))
+        assert np.array_equal(g.debug_read(hot.DBG_PERM, dtype=np.int32), perm)
+        counts = []
+        for m in range(sc.mg_levels):
+            nodes = g.debug_read(hot.DBG_LEVEL_NODES, m, dtype=np.int32).astype(np.int64)
+            assert np.array_equal(nodes, lev.lin), f"level {m}"
+            counts.append(lev.n)
+            if m + 1 < sc.mg_levels:
+                _, lev = O.prolongation(lev)
+        assert counts == [1142467, 158447, 24037, 4232]
+        for k in range(2):
+            status = g.step()
+            st = g.stats
+            assert status == 0 and st["converged"], f"step {k}"
+            assert st["E"] < st["E0"]
+        F = g.read()["F"]
+    finally:
+        g.close()
+    mu, lam = O.lame(sc.materials[0]["E"], sc.materials[0]["nu"])
+    lim = math.sqrt(2.0 / 3.0) * sc.materials[0]["yield_stress"] / (2.0 * mu)
+    s = np.linalg.svd(F[:: 16], compute_uv=False)
+    eps = np.log(s)
+    nd = np.linalg.norm(eps - eps.mean(axis=1, keepdims=True), axis=1)
+    assert np.all(nd <= lim * (1.0 + 1e-9))
