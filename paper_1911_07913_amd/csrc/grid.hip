@@ -189,18 +189,32 @@ __global__ void k_fine_pattern(LevelView L, const int* __restrict__ counts) {
 
 // Number of structurally present blocks of a level (popcount of its pattern),
 // written as a double.  One work-group of 1024 threads.
-__global__ void k_pattern_count(LevelView L, double* out) {
-  __shared__ unsigned long long sh[16];
+// Structural block count of a level: popcount of its pattern words, summed
+// per block and added into an integer total (integer sums are exact in any
+// order), then stored as a double.
+constexpr int kPatWordsPerBlock = 256 * 16;
+
+__global__ void k_pattern_count(LevelView L, unsigned long long* total) {
+  __shared__ unsigned long long sh[4];
   unsigned long long c = 0;
-  long long nw = (long long)L.n * 4;
-  for (long long k = threadIdx.x; k < nw; k += 1024) c += __popc(L.pat[k]);
+  const long long nw = (long long)L.n * 4;
+  const long long w0 = (long long)blockIdx.x * kPatWordsPerBlock;
+  const long long w1 = w0 + kPatWordsPerBlock < nw ? w0 + kPatWordsPerBlock : nw;
+  for (long long k = w0 + threadIdx.x; k < w1; k += 256) c += __popc(L.pat[k]);
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
   __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(total, sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+__global__ void k_u64_slot(unsigned long long* p, int to_double) {
   if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int w = 0; w < 16; ++w) t += sh[w];
-    *out = (double)t;
+    if (to_double) {
+      const unsigned long long t = *p;
+      *reinterpret_cast<double*>(p) = (double)t;
+    } else {
+      *p = 0ull;
+    }
   }
 }
 
@@ -377,7 +391,13 @@ void launch_brick_compact(long long total, const int* flags, const int* scan, in
 }
 
 void launch_pattern_count(const LevelView& L, double* out, hipStream_t st) {
-  k_pattern_count<<<1, 1024, 0, st>>>(L, out);
+  // the result slot holds the integer total until it is converted
+  unsigned long long* t = reinterpret_cast<unsigned long long*>(out);
+  const long long nw = (long long)L.n * 4;
+  k_u64_slot<<<1, 64, 0, st>>>(t, 0);
+  if (nw > 0)
+    k_pattern_count<<<(unsigned)((nw + kPatWordsPerBlock - 1) / kPatWordsPerBlock), 256, 0, st>>>(L, t);
+  k_u64_slot<<<1, 64, 0, st>>>(t, 1);
 }
 
 size_t scan_temp_bytes(long long n) {
