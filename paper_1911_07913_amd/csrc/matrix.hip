@@ -465,17 +465,20 @@ __global__ __launch_bounds__(256) void k_residual(LevelView L, const V* __restri
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int i0 = (xcd_block(blockIdx.x, gridDim.x) * kRowWaves + wave) * R;
   if (i0 >= L.n) return;
+  // the output lane's b entry is loaded before the product, off its path
+  const int rr = lane / 3, c = lane - 3 * rr;
+  const int i = i0 + rr;
+  const bool out = lane < 3 * R && i < L.n;
+  const V bv = out ? b[3 * i + c] : (V)0;
   V y[R][3];
   rows_matvec<V, R>(L, i0, u4, lane, y);
-  if (lane < 3 * R) {
-    const int rr = lane / 3, c = lane - 3 * rr;
-    const int i = i0 + rr;
+  if (out) {
     V yv = y[0][0];
 #pragma unroll
     for (int q = 0; q < R; ++q)
       for (int e = 0; e < 3; ++e)
         if (q == rr && e == c) yv = y[q][e];
-    if (i < L.n) r[3 * i + c] = b[3 * i + c] - yv;
+    r[3 * i + c] = bv - yv;
   }
 }
 
