@@ -57,10 +57,10 @@ TRAFFIC = {
 SAMPLE = dict(side=6, length=24)
 
 
-def workload_name(side):
+def workload_name(side, smoother="l1 block-Jacobi"):
     n = 4 * 192 * side * side * 8
     return (f"twisting_bars: 4 Neo-Hookean bars 192x{side}x{side} cells, {n} particles, "
-            f"256x64x64 grid dx=1/64, 5-level Galerkin MG with l1 block-Jacobi smoothing, "
+            f"256x64x64 grid dx=1/64, 5-level Galerkin MG with {smoother} smoothing, "
             f"L-BFGS w=8, CN eps=1e-6")
 
 
@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--serving-precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--smoother", default="l1jacobi", choices=["l1jacobi", "sgs"],
+                    help="smoother of the main job (profiling runs)")
     ap.add_argument("--no-sgs", action="store_true",
                     help="skip the same job with the coloured Gauss-Seidel smoother")
     ap.add_argument("--no-slab", action="store_true",
@@ -312,9 +314,10 @@ def main():
         calibrate_copy()
     precs = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
              "both": [hot.HOT_FP64, hot.HOT_MIXED]}[a.precision]
+    main_sm = hot.HOT_SMOOTH_SGS if a.smoother == "sgs" else hot.HOT_SMOOTH_L1_JACOBI
     results = {}
     for p in precs:
-        results[p] = run(p, a.steps, a.warmup, a.side)
+        results[p] = run(p, a.steps, a.warmup, a.side, smoother=main_sm)
     main_p = precs[0]
     r = results[main_p]
     value = a.steps / r["seconds"]
@@ -332,9 +335,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_p == hot.HOT_FP64 else "f64+f32/bf16",
         "data": "synthetic",
-        "config": {"workload": workload_name(a.side), "particles": r["n"],
+        "config": {"workload": workload_name(a.side, "l1 block-Jacobi" if a.smoother == "l1jacobi"
+                                             else "coloured symmetric Gauss-Seidel"),
+                   "particles": r["n"],
                    "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed",
-                   "smoother": "l1 block-Jacobi"},
+                   "smoother": a.smoother},
         "roofline": roofline_of(r["prof"], r["n"]),
         "vcycle_roofline": vcycle_roofline(r["prof"]),
         "per_step": {
