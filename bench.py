@@ -300,7 +300,7 @@ def main():
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
-              "(the step is a single-GPU solver; see the sharding notes in DESIGN.md)",
+              "(the step is a single-GPU solver; sharding across GPUs is not built)",
               file=sys.stderr)
         return 2
     # torch first: libhot then binds to the HIP runtime torch already loaded,
