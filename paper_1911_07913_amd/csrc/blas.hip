@@ -46,28 +46,6 @@ __global__ void k_partial(long long n, int kind, const double* __restrict__ a,
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ void k_partial3(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                           double* __restrict__ partial) {
-  __shared__ double sh[kTpb / 64];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
-    double x = a[k], y = b[k];
-    s0 += x * y;
-    s1 += x * x;
-    s2 += y * y;
-  }
-  double t0 = block_sum(s0, sh);
-  __syncthreads();
-  double t1 = block_sum(s1, sh);
-  __syncthreads();
-  double t2 = block_sum(s2, sh);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = t0;
-    partial[gridDim.x + blockIdx.x] = t1;
-    partial[2 * gridDim.x + blockIdx.x] = t2;
-  }
-}
-
 // sum_i 1/2 m_i (|dv_i + alpha p_i|^2 - |dv_i|^2)
 __global__ void k_kinetic(int n, const double* __restrict__ m, const double* __restrict__ dv,
                           const double* __restrict__ p, double alpha, double* __restrict__ partial) {
@@ -236,45 +214,14 @@ __global__ void k_secant(long long n, const double* __restrict__ gnew, const dou
   }
 }
 
-__global__ void k_axpy_dev(long long n, const double* __restrict__ a, double sign,
-                           const double* __restrict__ x, double* __restrict__ y) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  double al = sign * a[0];
-  y[k] = y[k] + al * x[k];
-}
-__global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  y[k] = y[k] + a * x[k];
-}
 __global__ void k_scale_copy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   y[k] = a * x[k];
 }
-__global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                      double* __restrict__ y) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  y[k] = a[k] - b[k];
-}
-// alpha = rho * dot
-__global__ void k_lbfgs_alpha(const double* rho, const double* dot, double* alpha) {
-  alpha[0] = rho[0] * dot[0];
-}
-// coef = alpha - rho * dot  (alpha^a - beta of the second loop)
-__global__ void k_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef) {
-  double beta = rho[0] * dot[0];
-  coef[0] = alpha[0] - beta;
-}
 __global__ void k_to_f32(long long n, const double* __restrict__ x, float* __restrict__ y) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) y[k] = (float)x[k];
-}
-__global__ void k_to_f64(long long n, const float* __restrict__ x, double* __restrict__ y) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) y[k] = (double)x[k];
 }
 __global__ void k_bj_apply(int n, const double* __restrict__ Dinv, const double* __restrict__ x,
                            double* __restrict__ y, double sign) {
@@ -298,20 +245,11 @@ void launch_fill_double(long long n, double* p, double v, hipStream_t st) {
 }
 void launch_rho(const double* ys, double* rho, hipStream_t st) { k_rho<<<1, 1, 0, st>>>(ys, rho); }
 
-void launch_finish_sum(int nparts, const double* partial, double* out, hipStream_t st) {
-  k_finish<<<1, kTpb, 0, st>>>(nparts, 1, 0, partial, out);
-}
 void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
                 hipStream_t st) {
   const int nb = red_blocks(n);
   k_partial<<<nb, kTpb, 0, st>>>(n, 0, a, b, partial);
   k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
-}
-void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
-                  hipStream_t st) {
-  const int nb = red_blocks(n);
-  k_partial3<<<nb, kTpb, 0, st>>>(n, a, b, partial);
-  k_finish<<<1, kTpb, 0, st>>>(nb, 3, 0, partial, out);
 }
 void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st) {
   const int nb = red_blocks(n);
@@ -341,10 +279,6 @@ void launch_max_speed(int n, const double* v, double* partial, double* out, hipS
   k_maxspeed<<<nb, kTpb, 0, st>>>(n, v, partial);
   k_finish<<<1, kTpb, 0, st>>>(nb, 1, 1, partial, out);
 }
-void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
-                     hipStream_t st) {
-  if (n > 0) k_axpy_dev<<<blocks_for(n), kTpb, 0, st>>>(n, a_dev, sign, x, y);
-}
 void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
                            const double* xprev, double* v, const double* dnext, double* partial,
                            hipStream_t st) {
@@ -366,27 +300,11 @@ void launch_secant(long long n, const double* gnew, const double* g, double* y, 
   k_secant<<<nb, kTpb, 0, st>>>(n, gnew, g, y, sv, partial);
   k_finish<<<1, kTpb, 0, st>>>(nb, 3, 0, partial, out);
 }
-void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st) {
-  if (n > 0) k_axpy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);
-}
 void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st) {
   if (n > 0) k_scale_copy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);
 }
-void launch_sub(long long n, const double* a, const double* b, double* y, hipStream_t st) {
-  if (n > 0) k_sub<<<blocks_for(n), kTpb, 0, st>>>(n, a, b, y);
-}
-void launch_lbfgs_alpha(const double* rho, const double* dot, double* alpha, hipStream_t st) {
-  k_lbfgs_alpha<<<1, 1, 0, st>>>(rho, dot, alpha);
-}
-void launch_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef,
-                       hipStream_t st) {
-  k_lbfgs_coef<<<1, 1, 0, st>>>(rho, dot, alpha, coef);
-}
 void launch_to_f32(long long n, const double* x, float* y, hipStream_t st) {
   if (n > 0) k_to_f32<<<blocks_for(n), kTpb, 0, st>>>(n, x, y);
-}
-void launch_to_f64(long long n, const float* x, double* y, hipStream_t st) {
-  if (n > 0) k_to_f64<<<blocks_for(n), kTpb, 0, st>>>(n, x, y);
 }
 void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
                                hipStream_t st) {

@@ -239,8 +239,6 @@ void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t st)
 constexpr int kRedBlocks = 2048;  // most partials a reduction writes
 void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
                 hipStream_t st);
-void launch_dots3(long long n, const double* a, const double* b, double* partial, double* out,
-                  hipStream_t st);  // out[0]=a.b out[1]=a.a out[2]=b.b
 void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st);
 void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
                      hipStream_t st);  // sum(a - b)
@@ -249,14 +247,8 @@ void launch_kinetic_delta(int n, const double* mass, const double* dv, const dou
 void launch_cn_sq(int n, const double* g, const double* xi, double scale, double* partial,
                   double* out, hipStream_t st);
 void launch_max_speed(int n, const double* v, double* partial, double* out, hipStream_t st);
-void launch_finish_sum(int nparts, const double* partial, double* out, hipStream_t st);
-// y = a*x + y with a read from device (a_dev[idx] * sign) or immediate
-void launch_axpy_dev(long long n, const double* a_dev, double sign, const double* x, double* y,
-                     hipStream_t st);
-void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st);
+// y = a * x
 void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st);
-void launch_sub(long long n, const double* a, const double* b, double* y, hipStream_t st);
-void launch_lbfgs_alpha(const double* rho, const double* dot, double* alpha, hipStream_t st);
 // Fused two-loop step: v <- (init ? -init : v) + sign*coef[0]*xprev; partials
 // of dnext . v (any of init, xprev, dnext may be NULL).  Bit-identical to the
 // separate kernels.
@@ -273,10 +265,7 @@ void launch_step_update(long long n, const double* dv, double alpha, const doubl
 // y = gnew - g; out = {y.s, y.y, s.s}
 void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
                    double* partial, double* out, hipStream_t st);
-void launch_lbfgs_coef(const double* rho, const double* dot, const double* alpha, double* coef,
-                       hipStream_t st);
 void launch_to_f32(long long n, const double* x, float* y, hipStream_t st);
-void launch_to_f64(long long n, const float* x, double* y, hipStream_t st);
 void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
                                hipStream_t st);
 void launch_fill_double(long long n, double* p, double v, hipStream_t st);
