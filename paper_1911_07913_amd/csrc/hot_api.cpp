@@ -1046,10 +1046,10 @@ hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
     stats->t = s->t;
     stats->n_nodes = s->L[0].n;
     stats->n_levels = s->levels;
-    hipEventElapsedTime(&stats->ms_prepare, s->ev[0], s->ev[1]);
-    hipEventElapsedTime(&stats->ms_hierarchy, s->ev[1], s->ev[2]);
-    hipEventElapsedTime(&stats->ms_solve, s->ev[2], s->ev[3]);
-    hipEventElapsedTime(&stats->ms_g2p, s->ev[3], s->ev[4]);
+    // phase times are informational: a failed query reports 0
+    float* ph[4] = {&stats->ms_prepare, &stats->ms_hierarchy, &stats->ms_solve, &stats->ms_g2p};
+    for (int k = 0; k < 4; ++k)
+      if (hipEventElapsedTime(ph[k], s->ev[k], s->ev[k + 1]) != hipSuccess) *ph[k] = 0.0f;
   }
   return conv ? HOT_OK : HOT_W_NOT_CONVERGED;
 }
