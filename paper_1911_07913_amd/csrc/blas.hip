@@ -133,46 +133,57 @@ __device__ inline double finish_sum(int nparts, const double* __restrict__ parti
   return block_sum(s, sh);
 }
 
-// One step of either two-loop recursion, fused with the inner product the
-// next step needs:  v <- (init ? -init : v) + (sign * coef) x_prev, then the
-// block partials of d_next . v.  Element order, operand order and the
-// reduction tree are those of the separate scale/axpy/dot kernels, so the
-// result is bit-identical to running them one after another.
-__global__ void k_twoloop_update(long long n, const double* __restrict__ init,
-                                 const double* __restrict__ coef, double sign,
-                                 const double* __restrict__ xprev, double* __restrict__ v,
-                                 const double* __restrict__ dnext, double* __restrict__ partial) {
+// Start of either two-loop recursion: v <- -init (if init is given), then the
+// block partials of dnext . v.
+__global__ void k_twoloop_start(long long n, const double* __restrict__ init, double* __restrict__ v,
+                                const double* __restrict__ dnext, double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
-  const bool write = init || xprev;
-  const double al = xprev ? sign * coef[0] : 0.0;
   double acc = 0.0;
   for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
     double val = init ? -1.0 * init[k] : v[k];
-    if (xprev) val = val + al * xprev[k];
-    if (write) v[k] = val;
+    if (init) v[k] = val;
+    acc += dnext[k] * val;
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// One inner step of either two-loop recursion.  Every block first finishes
+// the previous inner product from its partials (the same fixed-order sum in
+// every block, so all blocks hold the same value d), then
+//   first loop  (alpha_in NULL): alpha = rho d,  v <- v - alpha x, alpha stored;
+//   second loop:                 coef = alpha_in - rho d,  v <- v + coef x,
+// and writes the block partials of dnext . v (if dnext is given) to partial.
+// prev and partial must be different buffers.
+__global__ void k_twoloop_step(long long n, int nparts, const double* __restrict__ prev,
+                               const double* __restrict__ rho, const double* __restrict__ alpha_in,
+                               double* __restrict__ alpha_out, const double* __restrict__ x,
+                               double* __restrict__ v, const double* __restrict__ dnext,
+                               double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  __shared__ double coef;
+  const double d = finish_sum(nparts, prev, sh);
+  if (threadIdx.x == 0) {
+    const double rd = rho[0] * d;
+    if (alpha_in) {
+      coef = alpha_in[0] - rd;
+    } else {
+      coef = -1.0 * rd;
+      if (blockIdx.x == 0) alpha_out[0] = rd;
+    }
+  }
+  __syncthreads();
+  const double al = coef;
+  double acc = 0.0;
+  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
+    double val = v[k];
+    val = val + al * x[k];
+    v[k] = val;
     if (dnext) acc += dnext[k] * val;
   }
   if (dnext) {
     double t = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
-  }
-}
-
-// dot_out = sum of the partials; first loop: alpha_out = rho dot; second
-// loop: coef_out = alpha_in - rho dot.
-__global__ void k_finish_lbfgs(int nparts, const double* __restrict__ partial,
-                               const double* __restrict__ rho, const double* __restrict__ alpha_in,
-                               double* __restrict__ dot_out, double* __restrict__ alpha_out,
-                               double* __restrict__ coef_out) {
-  __shared__ double sh[kTpb / 64];
-  double t = finish_sum(nparts, partial, sh);
-  if (threadIdx.x == 0) {
-    dot_out[0] = t;
-    if (alpha_out) alpha_out[0] = rho[0] * t;
-    if (coef_out) {
-      double beta = rho[0] * t;
-      coef_out[0] = alpha_in[0] - beta;
-    }
   }
 }
 
@@ -279,16 +290,18 @@ void launch_max_speed(int n, const double* v, double* partial, double* out, hipS
   k_maxspeed<<<nb, kTpb, 0, st>>>(n, v, partial);
   k_finish<<<1, kTpb, 0, st>>>(nb, 1, 1, partial, out);
 }
-void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
-                           const double* xprev, double* v, const double* dnext, double* partial,
-                           hipStream_t st) {
-  k_twoloop_update<<<red_blocks(n), kTpb, 0, st>>>(n, init, coef, sign, xprev, v, dnext, partial);
+void launch_twoloop_start(long long n, const double* init, double* v, const double* dnext,
+                          double* partial, hipStream_t st) {
+  k_twoloop_start<<<red_blocks(n), kTpb, 0, st>>>(n, init, v, dnext, partial);
 }
-void launch_finish_lbfgs(long long n, const double* partial, const double* rho,
-                         const double* alpha_in, double* dot_out, double* alpha_out,
-                         double* coef_out, hipStream_t st) {
-  k_finish_lbfgs<<<1, kTpb, 0, st>>>(red_blocks(n), partial, rho, alpha_in, dot_out, alpha_out,
-                                     coef_out);
+void launch_twoloop_step(long long n, const double* prev, const double* rho, const double* alpha_in,
+                         double* alpha_out, const double* x, double* v, const double* dnext,
+                         double* partial, hipStream_t st) {
+  k_twoloop_step<<<red_blocks(n), kTpb, 0, st>>>(n, red_blocks(n), prev, rho, alpha_in, alpha_out, x,
+                                                 v, dnext, partial);
+}
+void launch_finish_partials(long long n, const double* partial, double* out, hipStream_t st) {
+  k_finish<<<1, kTpb, 0, st>>>(red_blocks(n), 1, 0, partial, out);
 }
 void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
                         double* sv, hipStream_t st) {

@@ -125,7 +125,7 @@ struct hot_scene {
   DBuf dv, dvt, g, gnew, q, r, pcg_work, pcg_iters, vin, vout;
   DBuf cscratch;  // colour counting of the Gauss-Seidel set-up
   std::vector<DBuf> Sh, Yh;
-  DBuf ddot, dalpha, dcoef, drho, dscal, partial, tables;
+  DBuf dalpha, drho, dscal, partial, tables;
   // work lists: row segments (assembly) and cell bricks (particle-to-node sums)
   DBuf seg_begin, bmap, blist, bpartial;
   int n_seg = 0;
@@ -421,7 +421,7 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
   for (int a = 0; a < 3; ++a) nbt *= (double)((g0.pd[a] + kBrick - 1) / kBrick);
   A(nbt * 4);
   const double W = p->lbfgs_history + 1;
-  for (int k = 0; k < 4; ++k) A(W * 8);
+  for (int k = 0; k < 2; ++k) A(W * 8);
   A(NSCAL * 8); A(kRedBlocks * 3 * 8);  // scalars, partials
   A((double)(sizeof(MaterialDev) * kMaxMats + sizeof(BcDev) * kMaxBcs));  // tables
   A((double)c.bricks * 4); A((double)c.bricks * kBrickWin * 5 * 8);
@@ -855,37 +855,36 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
   std::vector<std::pair<int, int>> vc_range;
   while (!conv && it < s->prm.max_iters) {
     int vc0 = s->vcycles;
-    // -- two-loop recursion (each axpy fused with the next inner product)
+    // -- two-loop recursion: each inner step finishes the previous inner
+    //    product, updates the vector and starts the next inner product
+    double* pbuf[2] = {partial, partial + kRedBlocks};
+    int pb = 0;
     const int K = (int)hist.size();
     if (K == 0) {
       launch_scale_copy(N, -1.0, g, q, st);
     } else {
-      launch_twoloop_update(N, g, nullptr, 0.0, nullptr, q, P<double>(s->Sh[hist[K - 1]]),
-                            partial, st);
+      launch_twoloop_start(N, g, q, P<double>(s->Sh[hist[K - 1]]), pbuf[pb], st);
       for (int k = K - 1; k >= 0; --k) {
-        int a = hist[k];
-        launch_finish_lbfgs(N, partial, P<double>(s->drho) + a, nullptr, P<double>(s->ddot) + a,
-                            P<double>(s->dalpha) + a, nullptr, st);
+        const int a = hist[k];
         const double* dn = k > 0 ? P<double>(s->Sh[hist[k - 1]]) : nullptr;
-        launch_twoloop_update(N, nullptr, P<double>(s->dalpha) + a, -1.0, P<double>(s->Yh[a]), q,
-                              dn, partial, st);
+        launch_twoloop_step(N, pbuf[pb], P<double>(s->drho) + a, nullptr, P<double>(s->dalpha) + a,
+                            P<double>(s->Yh[a]), q, dn, pbuf[1 - pb], st);
+        pb = 1 - pb;
       }
     }
     TRY(vcycle(s, q, r));
     if (K == 0) {
       launch_dot(N, g, r, partial, dscal + S_GP, st);
     } else {
-      launch_twoloop_update(N, nullptr, nullptr, 0.0, nullptr, r, P<double>(s->Yh[hist[0]]),
-                            partial, st);
+      launch_twoloop_start(N, nullptr, r, P<double>(s->Yh[hist[0]]), pbuf[pb], st);
       for (int k = 0; k < K; ++k) {
-        int a = hist[k];
-        launch_finish_lbfgs(N, partial, P<double>(s->drho) + a, P<double>(s->dalpha) + a,
-                            P<double>(s->ddot) + a, nullptr, P<double>(s->dcoef) + a, st);
+        const int a = hist[k];
         const double* dn = k + 1 < K ? P<double>(s->Yh[hist[k + 1]]) : g;
-        launch_twoloop_update(N, nullptr, P<double>(s->dcoef) + a, 1.0, P<double>(s->Sh[a]), r, dn,
-                              partial, st);
+        launch_twoloop_step(N, pbuf[pb], P<double>(s->drho) + a, P<double>(s->dalpha) + a, nullptr,
+                            P<double>(s->Sh[a]), r, dn, pbuf[1 - pb], st);
+        pb = 1 - pb;
       }
-      launch_finish_lbfgs(N, partial, nullptr, nullptr, dscal + S_GP, nullptr, nullptr, st);
+      launch_finish_partials(N, pbuf[pb], dscal + S_GP, st);
     }
     // -- descent check and the first trial in one readback
     int trial = 1 - s->pc;
@@ -1061,8 +1060,8 @@ void destroy(hot_scene* s) {
                  &s->psi[0], &s->psi[1], &s->S[0], &s->S[1], &s->counts, &s->start,
                  &s->cursor, &s->flags, &s->scan, &s->scan_temp, &s->err, &s->mass,
                  &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
-                 &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->ddot, &s->dalpha,
-                 &s->dcoef, &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
+                 &s->pcg_work, &s->pcg_iters, &s->vin, &s->vout, &s->dalpha,
+                 &s->drho, &s->dscal, &s->partial, &s->tables, &s->seg_begin,
                  &s->bmap, &s->blist, &s->bpartial, &s->wnode, &s->tnodes, &s->tmap,
                  &s->tpat, &s->tH, &s->cscratch};
   for (DBuf* b : all) release(s, *b);
@@ -1279,8 +1278,7 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     if ((rc = ensure(s, s->bmap, bg.total * 4)) < 0) return bail(rc);
   }
   int W = params->lbfgs_history + 1;
-  if ((rc = ensure(s, s->ddot, W * 8)) < 0 || (rc = ensure(s, s->dalpha, W * 8)) < 0 ||
-      (rc = ensure(s, s->dcoef, W * 8)) < 0 || (rc = ensure(s, s->drho, W * 8)) < 0 ||
+  if ((rc = ensure(s, s->dalpha, W * 8)) < 0 || (rc = ensure(s, s->drho, W * 8)) < 0 ||
       (rc = ensure(s, s->dscal, NSCAL * 8)) < 0 || (rc = ensure(s, s->partial, kRedBlocks * 3 * 8)) < 0)
     return bail(rc);
   // upload (host staging in caller order; ids = caller indices)

@@ -249,16 +249,19 @@ void launch_cn_sq(int n, const double* g, const double* xi, double scale, double
 void launch_max_speed(int n, const double* v, double* partial, double* out, hipStream_t st);
 // y = a * x
 void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st);
-// Fused two-loop step: v <- (init ? -init : v) + sign*coef[0]*xprev; partials
-// of dnext . v (any of init, xprev, dnext may be NULL).  Bit-identical to the
-// separate kernels.
-void launch_twoloop_update(long long n, const double* init, const double* coef, double sign,
-                           const double* xprev, double* v, const double* dnext, double* partial,
-                           hipStream_t st);
-// dot_out = sum(partial); alpha_out = rho*dot; coef_out = alpha_in - rho*dot
-void launch_finish_lbfgs(long long n, const double* partial, const double* rho,
-                         const double* alpha_in, double* dot_out, double* alpha_out,
-                         double* coef_out, hipStream_t st);
+// Two-loop recursion (Alg. L-BFGS two-loop).  Start: v <- -init (init may be
+// NULL: v kept), partials of dnext . v.  Inner step: finish the previous inner
+// product d from prev (red_blocks(n) partials); first loop (alpha_in NULL):
+// alpha_out = rho d, v -= alpha x; second loop: v += (alpha_in - rho d) x;
+// then partials of dnext . v into partial (dnext may be NULL; partial must not
+// alias prev).
+void launch_twoloop_start(long long n, const double* init, double* v, const double* dnext,
+                          double* partial, hipStream_t st);
+void launch_twoloop_step(long long n, const double* prev, const double* rho, const double* alpha_in,
+                         double* alpha_out, const double* x, double* v, const double* dnext,
+                         double* partial, hipStream_t st);
+// out = fixed-order sum of the red_blocks(n) partials
+void launch_finish_partials(long long n, const double* partial, double* out, hipStream_t st);
 // dvt = dv + alpha p, sv = dvt - dv
 void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
                         double* sv, hipStream_t st);
