@@ -283,6 +283,7 @@ __device__ inline V comp(const typename Vec4Of<V>::type* v4, int pn, int c) {
 // structurally present iff some contributing fine slot is (the symbolic
 // R pattern P).  One wave per output row; lane l owns output slots l, l + 64.
 constexpr int kRapWaves = 4;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __device__ inline double emb_w(int b) { return b ? 0.5 : 1.0; }
 
@@ -297,10 +298,23 @@ __device__ inline void ballot_pattern(bool p0, bool p1, uint32_t* out, int lane)
   }
 }
 
+// The x-y half runs separably, x first: for each child offset by in y the
+// x-coarsened row
+//   U_by[(dX, sy, dz)] = sum_{bx, bx'} w(bx) w(bx') H~[(2X+bx, 2Y+by, z)][(2dX + bx' - bx, sy, dz)]
+// is accumulated in registers while the three child rows (bx = -1, 0, 1) pass
+// one at a time through the wave's LDS buffer (coalesced 16-byte loads); U_by
+// then replaces the child in the buffer, and
+//   T[(dX, dY, dz)] += sum_{by'} w(by) w(by') U_by[(dX, 2dY + by' - by, dz)].
+// A U slot is present iff one of its child slots is, a T slot iff one of its
+// U slots is: the same set as the direct sum.
 __global__ __launch_bounds__(256) void k_rap_xy(LevelView F, LevelView T) {
+  __shared__ __attribute__((aligned(16))) double buf_all[kRapWaves][kRowStride];
+  __shared__ uint8_t pres_all[kRapWaves][kSlotPad];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
-  if (t >= T.n) return;
+  if (t >= T.n) return;  // the wave only syncs with itself
+  double* buf = buf_all[wave];
+  uint8_t* pres = pres_all[wave];
   int X, Y, z;
   unpidx(T.g, T.nodes[t], X, Y, z);
   int child = -1;  // fine row of child a = (bx + 1) + 3 (by + 1), in lane a
@@ -310,55 +324,103 @@ __global__ __launch_bounds__(256) void k_rap_xy(LevelView F, LevelView T) {
   const bool v1 = S1 < kSlots;
   const int dX0 = S0 % 5 - 2, dY0 = (S0 / 5) % 5 - 2, dz0 = S0 / 25 - 2;
   const int dX1 = S1 % 5 - 2, dY1 = (S1 / 5) % 5 - 2, dz1 = S1 / 25 - 2;
+  constexpr int kLd = kRowStride / 128;  // 16-byte loads per lane per row
   double acc0[9], acc1[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc0[c] = acc1[c] = 0.0;
   bool p0 = false, p1 = false;
-  for (int a = 0; a < 9; ++a) {
-    const int i = __shfl(child, a, 64);
-    if (i < 0) continue;
-    const int bx = a % 3 - 1, by = a / 3 - 1;
-    const double wa = emb_w(bx) * emb_w(by);
-    const uint32_t w[4] = {F.pat[4 * i], F.pat[4 * i + 1], F.pat[4 * i + 2], F.pat[4 * i + 3]};
-    const double* Hrow = F.H + (long long)i * kRowStride;
-    const double f0 = (double)F.free_dof[3 * i], f1 = (double)F.free_dof[3 * i + 1],
-                 f2 = (double)F.free_dof[3 * i + 2];
-    const double fm[9] = {f0 * f0, f0 * f1, f0 * f2, f1 * f0, f1 * f1, f1 * f2,
-                          f2 * f0, f2 * f1, f2 * f2};
-    for (int bxp = -1; bxp <= 1; ++bxp)
-      for (int byp = -1; byp <= 1; ++byp) {
-        const double wb = wa * emb_w(bxp) * emb_w(byp);
+#pragma unroll 1
+  for (int by = -1; by <= 1; ++by) {
+    double u0[9], u1[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) u0[c] = u1[c] = 0.0;
+    bool q0 = false, q1 = false, any = false;
+    for (int bx = -1; bx <= 1; ++bx) {
+      const int i = __shfl(child, (bx + 1) + 3 * (by + 1), 64);
+      if (i < 0) continue;
+      any = true;
+      const dvec2* src = reinterpret_cast<const dvec2*>(F.H + (long long)i * kRowStride);
+      dvec2 ld[kLd];
+#pragma unroll
+      for (int k = 0; k < kLd; ++k) ld[k] = src[lane + 64 * k];
+      const uint32_t w[4] = {F.pat[4 * i], F.pat[4 * i + 1], F.pat[4 * i + 2], F.pat[4 * i + 3]};
+      const double f0 = (double)F.free_dof[3 * i], f1 = (double)F.free_dof[3 * i + 1],
+                   f2 = (double)F.free_dof[3 * i + 2];
+      const double fm[9] = {f0 * f0, f0 * f1, f0 * f2, f1 * f0, f1 * f1, f1 * f2,
+                            f2 * f0, f2 * f1, f2 * f2};
+      wave_sync();  // earlier reads of the buffer are done
+#pragma unroll
+      for (int k = 0; k < kLd; ++k) reinterpret_cast<dvec2*>(buf)[lane + 64 * k] = ld[k];
+      wave_sync();
+      for (int bxp = -1; bxp <= 1; ++bxp) {
+        const double wb = emb_w(bx) * emb_w(bxp);
         {
-          const int sx = 2 * dX0 + bxp - bx, sy = 2 * dY0 + byp - by;
-          if (sx >= -2 && sx <= 2 && sy >= -2 && sy <= 2) {
-            const int s = (sx + 2) + 5 * (sy + 2) + 25 * (dz0 + 2);
+          const int sx = 2 * dX0 + bxp - bx;
+          if (sx >= -2 && sx <= 2) {
+            const int s = (sx + 2) + 5 * (dY0 + 2) + 25 * (dz0 + 2);
             if (slot_present(w, s)) {
-              p0 = true;
+              q0 = true;
               const bool ctr = s == kCenter;
 #pragma unroll
               for (int c = 0; c < 9; ++c) {
-                const double h = Hrow[c * kSlotPad + s];
-                acc0[c] += wb * (ctr ? h * fm[c] : h);
+                const double h = buf[c * kSlotPad + s];
+                u0[c] += wb * (ctr ? h * fm[c] : h);
               }
             }
           }
         }
         if (v1) {
-          const int sx = 2 * dX1 + bxp - bx, sy = 2 * dY1 + byp - by;
-          if (sx >= -2 && sx <= 2 && sy >= -2 && sy <= 2) {
-            const int s = (sx + 2) + 5 * (sy + 2) + 25 * (dz1 + 2);
+          const int sx = 2 * dX1 + bxp - bx;
+          if (sx >= -2 && sx <= 2) {
+            const int s = (sx + 2) + 5 * (dY1 + 2) + 25 * (dz1 + 2);
             if (slot_present(w, s)) {
-              p1 = true;
+              q1 = true;
               const bool ctr = s == kCenter;
 #pragma unroll
               for (int c = 0; c < 9; ++c) {
-                const double h = Hrow[c * kSlotPad + s];
-                acc1[c] += wb * (ctr ? h * fm[c] : h);
+                const double h = buf[c * kSlotPad + s];
+                u1[c] += wb * (ctr ? h * fm[c] : h);
               }
             }
           }
         }
       }
+    }
+    if (!any) continue;  // uniform over the wave
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      buf[c * kSlotPad + S0] = u0[c];
+      if (v1) buf[c * kSlotPad + S1] = u1[c];
+    }
+    pres[S0] = q0 ? 1 : 0;
+    if (v1) pres[S1] = q1 ? 1 : 0;
+    wave_sync();
+    for (int byp = -1; byp <= 1; ++byp) {
+      const double wy = emb_w(by) * emb_w(byp);
+      {
+        const int sy = 2 * dY0 + byp - by;
+        if (sy >= -2 && sy <= 2) {
+          const int s = (dX0 + 2) + 5 * (sy + 2) + 25 * (dz0 + 2);
+          if (pres[s]) {
+            p0 = true;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc0[c] += wy * buf[c * kSlotPad + s];
+          }
+        }
+      }
+      if (v1) {
+        const int sy = 2 * dY1 + byp - by;
+        if (sy >= -2 && sy <= 2) {
+          const int s = (dX1 + 2) + 5 * (sy + 2) + 25 * (dz1 + 2);
+          if (pres[s]) {
+            p1 = true;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc1[c] += wy * buf[c * kSlotPad + s];
+          }
+        }
+      }
+    }
   }
   double* Tout = T.H + (long long)t * kRowStride;
 #pragma unroll
@@ -369,11 +431,14 @@ __global__ __launch_bounds__(256) void k_rap_xy(LevelView F, LevelView T) {
   ballot_pattern(p0, p1 && v1, T.pat + 4 * t, lane);
 }
 
+// The z half: the three child rows (bz = -1, 0, 1) pass one at a time
+// through the wave's LDS buffer (coalesced 16-byte loads), which then holds
+// the coarse row for its finalisation.
 __global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
-  __shared__ double acc_all[kRapWaves][kRowStride];
+  __shared__ __attribute__((aligned(16))) double acc_all[kRapWaves][kRowStride];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int I = xcd_block(blockIdx.x, gridDim.x) * kRapWaves + wave;
-  if (I >= C.n) return;
+  if (I >= C.n) return;  // the wave only syncs with itself
   double* accr = acc_all[wave];
   int X, Y, Z;
   unpidx(C.g, C.nodes[I], X, Y, Z);
@@ -383,6 +448,7 @@ __global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
   const bool v1 = S1 < kSlots;
   const int dX0 = S0 % 5 - 2, dY0 = (S0 / 5) % 5 - 2, dZ0 = S0 / 25 - 2;
   const int dX1 = S1 % 5 - 2, dY1 = (S1 / 5) % 5 - 2, dZ1 = S1 / 25 - 2;
+  constexpr int kLd = kRowStride / 128;  // 16-byte loads per lane per row
   double acc0[9], acc1[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc0[c] = acc1[c] = 0.0;
@@ -392,8 +458,15 @@ __global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
     if (tr < 0) continue;
     const int bz = a - 1;
     const double wa = emb_w(bz);
+    const dvec2* src = reinterpret_cast<const dvec2*>(T.H + (long long)tr * kRowStride);
+    dvec2 ld[kLd];
+#pragma unroll
+    for (int k = 0; k < kLd; ++k) ld[k] = src[lane + 64 * k];
     const uint32_t w[4] = {T.pat[4 * tr], T.pat[4 * tr + 1], T.pat[4 * tr + 2], T.pat[4 * tr + 3]};
-    const double* Trow = T.H + (long long)tr * kRowStride;
+    wave_sync();  // earlier reads of the buffer are done
+#pragma unroll
+    for (int k = 0; k < kLd; ++k) reinterpret_cast<dvec2*>(accr)[lane + 64 * k] = ld[k];
+    wave_sync();
     for (int bzp = -1; bzp <= 1; ++bzp) {
       const double wb = wa * emb_w(bzp);
       {
@@ -403,7 +476,7 @@ __global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
           if (slot_present(w, s)) {
             p0 = true;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) acc0[c] += wb * Trow[c * kSlotPad + s];
+            for (int c = 0; c < 9; ++c) acc0[c] += wb * accr[c * kSlotPad + s];
           }
         }
       }
@@ -414,12 +487,13 @@ __global__ __launch_bounds__(256) void k_rap_z(LevelView T, LevelView C) {
           if (slot_present(w, s)) {
             p1 = true;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) acc1[c] += wb * Trow[c * kSlotPad + s];
+            for (int c = 0; c < 9; ++c) acc1[c] += wb * accr[c * kSlotPad + s];
           }
         }
       }
     }
   }
+  wave_sync();  // the last child row is no longer read
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     accr[c * kSlotPad + S0] = acc0[c];
