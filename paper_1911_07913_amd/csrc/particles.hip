@@ -477,12 +477,17 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // Z_p[(r, g, d)][eps] = sum_b a_p[k][b] C_p[3g + b][3d + eps] (k = (r, ky, kz)),
 // a 27 x 27 x 3P product that the four waves compute as 2 x 2 tiles of FP64
 // 16x16x4 matrix-core instructions, accumulating in registers over the
-// column's particles.  Per cell column the sums go to a 3-row sliding window in
-// LDS.  After cell c, row c receives nothing more: it is finalised (mass,
-// Dirichlet projection, smoother inverse) and written once.  Every block of
-// every particle is computed exactly once; no atomics.
+// column's particles; each lane forms its own Z operands from a_k and C_p in
+// registers right before the matrix-core steps.  Per cell column the sums go
+// to a 3-row sliding window in LDS.  After cell c, row c receives nothing
+// more: it is finalised (mass, Dirichlet projection, smoother inverse) and
+// written once.  Every block of every particle is computed exactly once; no
+// atomics.  The kernel is bound by latency, not by a unit: LDS (38.6 KB) and
+// registers (at most 128) are sized so that four work-groups share a compute
+// unit.
 constexpr int kAsmChunk = 8;   // particles staged per pass
 constexpr int kPData = 57;     // f (3), F (9), C (45)
+constexpr int kPFf = 12;       // f and F
 constexpr int kStageRegs = (kAsmChunk * kPData + 255) / 256;
 
 __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
@@ -577,21 +582,17 @@ __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
-                                                         const int* __restrict__ seg_begin,
-                                                         const double* __restrict__ f,
-                                                         const double* __restrict__ Fn,
-                                                         const double* __restrict__ Cp,
-                                                         const int* __restrict__ cstart,
-                                                         const int* __restrict__ ccount,
-                                                         const double* __restrict__ mass,
-                                                         const int* __restrict__ fixed) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin,
+                      const double* __restrict__ f, const double* __restrict__ Fn,
+                      const double* __restrict__ Cp, const int* __restrict__ cstart,
+                      const int* __restrict__ ccount, const double* __restrict__ mass,
+                      const int* __restrict__ fixed) {
   constexpr int kMaxCx = kSegRows + 2;
   __shared__ double win[3][kRowStride];
-  __shared__ double pd[kAsmChunk][kPData];
-  // a_l padded to 4 and Z rows padded to 12 so both are read with 16-byte loads
-  __shared__ __attribute__((aligned(16))) double av[kAsmChunk][27][4];
-  __shared__ __attribute__((aligned(16))) double zv[kAsmChunk][3][3][12];
+  __shared__ double pf[kAsmChunk][kPFf];     // f, F of the staged particles
+  __shared__ double pc[kAsmChunk][45];       // their C
+  __shared__ double av[kAsmChunk][27][3];    // a_l of the staged particles
   __shared__ double red[12];
   __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
   __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
@@ -625,25 +626,9 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
     rmass[v] = mass[rb + v];
   }
   for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
-  // fixed roles: a phase (particle a_q, node a_l); Z phase items; block phase (r, l, g)
+  // a-phase role: particle a_q, stencil node a_l
   const int a_q = (tid < kAsmChunk * 27) ? tid / 27 : kAsmChunk, a_l = tid % 27;
   const int a_lx = a_l % 3, a_ly = (a_l / 3) % 3, a_lz = a_l / 9;
-  constexpr int kZItems = (kAsmChunk * 81 + 255) / 256;
-  int z_q[kZItems], z_r[kZItems], z_g[kZItems], z_de[kZItems], z_c0[kZItems], z_c1[kZItems],
-      z_c2[kZItems];
-#pragma unroll
-  for (int k = 0; k < kZItems; ++k) {
-    int u = tid + 256 * k;
-    z_q[k] = (u < kAsmChunk * 81) ? u / 81 : kAsmChunk;
-    int rem = u % 81;
-    z_r[k] = rem / 27;
-    int e = rem % 27;
-    z_g[k] = e / 9;
-    z_de[k] = e % 9;
-    z_c0[k] = tri9(3 * z_g[k], z_de[k]);
-    z_c1[k] = tri9(3 * z_g[k] + 1, z_de[k]) - z_c0[k];
-    z_c2[k] = tri9(3 * z_g[k] + 2, z_de[k]) - z_c0[k];
-  }
   // matrix-core roles: wave w owns output tile (rows 16 tile_m.., columns
   // 16 tile_n..) of the 27 x 27 product; lane l feeds A[l % 16][l / 16] and
   // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3
@@ -656,7 +641,7 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
   const int bn = tile_n * 16 + (lane & 15);      // B column: stencil node l
   const bool bn_ok = bn < 27;
   const int bnc = bn_ok ? bn : 0;
-  const int kq = lane >> 4;                      // k offset within a 4-step
+  const int kq = lane >> 4;                      // lane group: k offset within a step
   int dm_r[4], dm_e[4];                          // D rows held by this lane
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -668,20 +653,13 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
   const int dnx = dn % 3, dny = (dn / 3) % 3, dnz = dn / 9;
   // window slot of (node l, row r, column ky, kz) = dsl0 - r - 5 ky - 25 kz
   const int dsl0 = (dnx + 2) + 5 * (dny + 2) + 25 * (dnz + 2);
-  // zv[q][r][g][3d + e] and av[q][l][e] share the per-particle stride of 108
-  // doubles: operand k = (q, e) of step st sits at koff[st] past the lane's base
-  static_assert(sizeof(zv[0]) == sizeof(av[0]), "zv/av particle strides differ");
-  constexpr int kPStride = (int)(sizeof(av[0]) / sizeof(double));
-  const int zbase = am_r * 36 + am_g * 12 + 3 * am_d;
-  const int abase = bnc * 4;
-  int koff[kAsmChunk * 3 / 4];
+  // K order of a pass: step st, lane group kq -> particle q = 2 kq + st / 3,
+  // component e = st % 3, so a lane's six A operands come from two particles
+  int zoff[9];  // packed C index of (3 g + b, 3 d + e), entry 3 b + e
 #pragma unroll
-  for (int st = 0; st < kAsmChunk * 3 / 4; ++st) {
-    const int k = 4 * st + kq;
-    koff[st] = (k / 3) * kPStride + (k % 3);
-  }
-  const double* zflat = &zv[0][0][0][0];
-  const double* aflat = &av[0][0][0];
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) zoff[3 * b + e] = tri9(3 * am_g + b, 3 * am_d + e);
   FinRoles fr;
   fin_roles(tid, nxw, fr);
   __syncthreads();
@@ -741,9 +719,15 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
       v4d acc = {0.0, 0.0, 0.0, 0.0};
       for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
         const int np = min(kAsmChunk, cnt - t0);
+        __syncthreads();  // the previous pass's operand reads are done
 #pragma unroll
         for (int k = 0; k < kStageRegs; ++k)
-          if (sq[k] < np) pd[sq[k]][sw[k]] = regs[k];
+          if (sq[k] < np) {
+            if (sw[k] < kPFf)
+              pf[sq[k]][sw[k]] = regs[k];
+            else
+              pc[sq[k]][sw[k] - kPFf] = regs[k];
+          }
         __syncthreads();
         // prefetch the next chunk while this one is processed
         int nv, nt;
@@ -752,39 +736,42 @@ __global__ __launch_bounds__(256) void k_assemble_strip(SceneDev s, LevelView L,
         // a_l = F^T grad w_l for the 27 stencil nodes of each staged particle
         if (a_q < np) {
           double w0, d0, w1, d1, w2, d2;
-          wdw(a_lx, pd[a_q][0], s.inv_dx, w0, d0);
-          wdw(a_ly, pd[a_q][1], s.inv_dx, w1, d1);
-          wdw(a_lz, pd[a_q][2], s.inv_dx, w2, d2);
+          wdw(a_lx, pf[a_q][0], s.inv_dx, w0, d0);
+          wdw(a_ly, pf[a_q][1], s.inv_dx, w1, d1);
+          wdw(a_lz, pf[a_q][2], s.inv_dx, w2, d2);
           double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
-          const double* F = &pd[a_q][3];
+          const double* F = &pf[a_q][3];
           double* o = av[a_q][a_l];
           o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
           o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
           o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
         }
         __syncthreads();
-        // Z_r[gamma][delta eps] = sum_beta a_k,beta C[3 gamma + beta][3 delta + eps], k = (r, ky, kz)
-#pragma unroll
-        for (int k = 0; k < kZItems; ++k) {
-          if (z_q[k] < np && z_r[k] >= rlo && z_r[k] <= rhi) {
-            const double* a = av[z_q[k]][z_r[k] + 3 * ky + 9 * kz];
-            const double* Cq = &pd[z_q[k]][12];
-            zv[z_q[k]][z_r[k]][z_g[k]][z_de[k]] =
-                a[0] * Cq[z_c0[k]] + a[1] * Cq[z_c0[k] + z_c1[k]] + a[2] * Cq[z_c0[k] + z_c2[k]];
-          }
-        }
-        __syncthreads();
-        // B[(r, g, d)][l] += sum over the chunk's (p, eps), four at a time
+        // A operands Z_r[g][3d + e] = sum_b a_k[b] C[3g + b][3d + e], k = (r, ky, kz),
+        // then B[(r, g, d)][l] += sum over the chunk's (p, eps), four at a time
         {
           const bool a_ok = am_ok && am_r >= rlo && am_r <= rhi;
-          const int nk = 3 * np;
+          double za[6];
 #pragma unroll
-          for (int st = 0; st < kAsmChunk * 3 / 4; ++st) {
-            if (4 * st < nk) {  // uniform
-              const bool kin = 4 * st + kq < nk;
-              const double a = (kin && a_ok) ? zflat[zbase + koff[st]] : 0.0;
-              const double b = (kin && bn_ok) ? aflat[abase + koff[st]] : 0.0;
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          for (int j = 0; j < 2; ++j) {
+            const int q = 2 * kq + j;
+            if (a_ok && q < np) {
+              const double* a = av[q][am_r + 3 * ky + 9 * kz];
+              const double* Cq = pc[q];
+              const double a0 = a[0], a1 = a[1], a2 = a[2];
+#pragma unroll
+              for (int e = 0; e < 3; ++e)
+                za[3 * j + e] = a0 * Cq[zoff[e]] + a1 * Cq[zoff[3 + e]] + a2 * Cq[zoff[6 + e]];
+            } else {
+              za[3 * j] = za[3 * j + 1] = za[3 * j + 2] = 0.0;
+            }
+          }
+#pragma unroll
+          for (int st = 0; st < 6; ++st) {
+            if (st < 3 || np > 1) {  // uniform
+              const int q = 2 * kq + st / 3;
+              const double b = (q < np && bn_ok) ? av[q][bnc][st % 3] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], b, acc, 0, 0, 0);
             }
           }
         }
