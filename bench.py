@@ -155,7 +155,7 @@ class ServingRequests:
 def run_serving(n_req, slots, budget_gb, precision, smoother, load=0.7, n_sat=64):
     """Closed-loop run of the first n_sat requests for the saturated step
     rate, then the whole stream with Poisson arrivals at ``load`` times it."""
-    from paper_1911_07913_amd import serving
+    from paper_1911_07913_amd import hot, serving
     budget = int(budget_gb * (1 << 30))
     n_sat = min(n_sat, n_req)
     _, sat, _ = serving.serve(ServingRequests(n_sat), [0.0] * n_sat, budget, slots, precision,
@@ -165,8 +165,9 @@ def run_serving(n_req, slots, budget_gb, precision, smoother, load=0.7, n_sat=64
     arrivals = serving.poisson_arrivals(n_req, rate, seed=4000)
     records, summary, trace = serving.serve(ServingRequests(n_req), arrivals, budget, slots,
                                             precision, smoother=smoother)
-    summary.update(precision="fp64" if precision == 0 else "mixed",
-                   smoother="sgs" if smoother == 0 else "l1jacobi", slots=slots,
+    summary.update(precision="fp64" if precision == hot.HOT_FP64 else "mixed",
+                   smoother="l1jacobi" if smoother == hot.HOT_SMOOTH_L1_JACOBI else "sgs",
+                   slots=slots,
                    budget_gb=budget_gb, load=load, arrival_rate_req_per_s=rate,
                    saturated_steps_per_s=sat["steps_per_s"],
                    saturated_step_latency_ms=sat["step_latency_ms"], **trace)
