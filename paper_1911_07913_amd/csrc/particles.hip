@@ -307,19 +307,26 @@ __global__ __launch_bounds__(256) void k_particle_eval(SceneDev s, LevelView L, 
 }
 
 // Gradient pass 1 (Sec. 4.1 nodal forces): per brick, sum_p S_p grad w_ip
-// with S_p = V_p P(F_p) F_p^n^T.
-__global__ __launch_bounds__(64) void k_grad_brick(SceneDev s, Bricks B, const double* __restrict__ f,
-                                                   const double* __restrict__ S,
-                                                   const int* __restrict__ cstart,
-                                                   const int* __restrict__ ccount,
-                                                   double* __restrict__ partial) {
-  __shared__ double win[kBrickWin * 3];
-  const int b = blockIdx.x, lane = threadIdx.x;
-  for (int e = lane; e < kBrickWin * 3; e += 64) win[e] = 0.0;
+// with S_p = V_p P(F_p) F_p^n^T.  kGradWaves waves share a brick: wave w
+// walks the particles t = w, w + kGradWaves, ... of every cell into a window
+// of its own (the pass-1 rule above holds per wave), and the windows are
+// summed in wave order, so the result stays reproducible.
+constexpr int kGradWaves = 4;
+
+__global__ __launch_bounds__(64 * kGradWaves) void k_grad_brick(SceneDev s, Bricks B,
+                                                                const double* __restrict__ f,
+                                                                const double* __restrict__ S,
+                                                                const int* __restrict__ cstart,
+                                                                const int* __restrict__ ccount,
+                                                                double* __restrict__ partial) {
+  __shared__ double win[kGradWaves][kBrickWin * 3];
+  const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < kGradWaves * kBrickWin * 3; e += 64 * kGradWaves) (&win[0][0])[e] = 0.0;
   int cnt, st, lx, ly, lz;
   brick_cell(s, B, b, lane, cstart, ccount, cnt, st, lx, ly, lz);
-  wave_sync();
-  for (int t = 0;; ++t) {
+  __syncthreads();
+  double* wv = win[wave];
+  for (int t = wave;; t += kGradWaves) {
     bool act = t < cnt;
     if (!__any(act)) break;
     if (act) {
@@ -343,16 +350,21 @@ __global__ __launch_bounds__(64) void k_grad_brick(SceneDev s, Bricks B, const d
         double gx = dx[kx] * wy[ky] * wz[kz];
         double gy = wx[kx] * dy[ky] * wz[kz];
         double gz = wx[kx] * wy[ky] * dz[kz];
-        double* q = win + 3 * ((lx + kx) + kBrickNodes * ((ly + ky) + kBrickNodes * (lz + kz)));
+        double* q = wv + 3 * ((lx + kx) + kBrickNodes * ((ly + ky) + kBrickNodes * (lz + kz)));
         atomicAdd(q, s0 * gx + s1 * gy + s2 * gz);
         atomicAdd(q + 1, s3 * gx + s4 * gy + s5 * gz);
         atomicAdd(q + 2, s6 * gx + s7 * gy + s8 * gz);
       }
     }
   }
-  wave_sync();
+  __syncthreads();
   double* out = partial + (long long)b * kBrickWin * 3;
-  for (int e = lane; e < kBrickWin * 3; e += 64) out[e] = win[e];
+  for (int e = tid; e < kBrickWin * 3; e += 64 * kGradWaves) {
+    double acc = win[0][e];
+#pragma unroll
+    for (int w = 1; w < kGradWaves; ++w) acc += win[w][e];
+    out[e] = acc;
+  }
 }
 
 // Gradient pass 2: g_i = m_i dv_i + dt sum, zero on constrained nodes.
@@ -850,7 +862,8 @@ void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, co
                      const double* S, const int* cstart, const int* ccount, double* partial,
                      const double* mass, const int* fixed, const double* dv, double dt, double* g,
                      hipStream_t st) {
-  if (B.n > 0) k_grad_brick<<<B.n, 64, 0, st>>>(s, B, f, S, cstart, ccount, partial);
+  if (B.n > 0)
+    k_grad_brick<<<B.n, 64 * kGradWaves, 0, st>>>(s, B, f, S, cstart, ccount, partial);
   if (L0.n > 0)
     k_grad_nodes<<<blocks_for(L0.n), kTpb, 0, st>>>(L0, B, partial, mass, fixed, dv, dt, g);
 }
