@@ -72,21 +72,31 @@ __global__ void k_sort_segments(long long ncells, const int* __restrict__ start,
   }
 }
 
+// dst[i] = src[perm[i]] for all particle fields.  One wave moves 64
+// consecutive destination particles field by field, lane l copying entries
+// l, l + 64, ... of the wave's contiguous destination range, so that stores
+// are contiguous and loads walk each source particle's entries in order.
+template <typename T, int W>
+__device__ inline void permute_field(int i0, int cnt, int lane, const int* __restrict__ perm,
+                                     const T* __restrict__ src, T* __restrict__ dst) {
+  for (int e = lane; e < W * cnt; e += 64) {
+    const int q = e / W, c = e - W * q;
+    dst[(long long)W * (i0 + q) + c] = src[(long long)W * perm[i0 + q] + c];
+  }
+}
+
 __global__ void k_permute(int n, const int* __restrict__ perm, Particles src, Particles dst) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int p = perm[i];
-  for (int a = 0; a < 3; ++a) {
-    dst.x[3 * i + a] = src.x[3 * p + a];
-    dst.v[3 * i + a] = src.v[3 * p + a];
-  }
-  for (int a = 0; a < 9; ++a) {
-    dst.C[9 * i + a] = src.C[9 * p + a];
-    dst.F[9 * i + a] = src.F[9 * p + a];
-  }
-  dst.vol[i] = src.vol[p];
-  dst.mat[i] = src.mat[p];
-  dst.id[i] = src.id[p];
+  const int lane = threadIdx.x & 63;
+  const int i0 = (blockIdx.x * blockDim.x + threadIdx.x - lane);
+  if (i0 >= n) return;
+  const int cnt = min(64, n - i0);
+  permute_field<double, 3>(i0, cnt, lane, perm, src.x, dst.x);
+  permute_field<double, 3>(i0, cnt, lane, perm, src.v, dst.v);
+  permute_field<double, 9>(i0, cnt, lane, perm, src.C, dst.C);
+  permute_field<double, 9>(i0, cnt, lane, perm, src.F, dst.F);
+  permute_field<double, 1>(i0, cnt, lane, perm, src.vol, dst.vol);
+  permute_field<int, 1>(i0, cnt, lane, perm, src.mat, dst.mat);
+  permute_field<int, 1>(i0, cnt, lane, perm, src.id, dst.id);
 }
 
 // Active fine nodes: the 27 nodes of every non-empty base cell.
