@@ -33,13 +33,13 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// kind 0: sum a*b; 1: sum a; 2: sum (a - b)
+// kind 0: sum a*b; 1: sum a
 __global__ void k_partial(long long n, int kind, const double* __restrict__ a,
                           const double* __restrict__ b, double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
   for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
-    double v = (kind == 0) ? a[k] * b[k] : (kind == 1 ? a[k] : a[k] - b[k]);
+    double v = (kind == 0) ? a[k] * b[k] : a[k];
     s += v;
   }
   double t = block_sum(s, sh);
@@ -63,6 +63,42 @@ __global__ void k_kinetic(int n, const double* __restrict__ m, const double* __r
   }
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// The line search's energy change in one launch: blocks b < nb1 write the
+// partials of sum_p (psi_t - psi_c) over n particles, blocks b < nb2 those of
+// the kinetic change over n0 nodes, each with its own grid stride, so that
+// the kinetic partials equal those of k_kinetic launched with nb2 blocks.
+__global__ void k_energy_delta(long long n, const double* __restrict__ psi_t,
+                               const double* __restrict__ psi_c, int nb1, int n0,
+                               const double* __restrict__ m, const double* __restrict__ dv,
+                               const double* __restrict__ p, double alpha, int nb2,
+                               double* __restrict__ partial) {
+  __shared__ double sh[kTpb / 64];
+  const int b = blockIdx.x;
+  if (b < nb1) {
+    double s = 0.0;
+    for (long long k = (long long)b * kTpb + threadIdx.x; k < n; k += (long long)nb1 * kTpb)
+      s += psi_t[k] - psi_c[k];
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[b] = t;
+    __syncthreads();
+  }
+  if (b < nb2) {
+    double s = 0.0;
+    for (int i = b * kTpb + threadIdx.x; i < n0; i += nb2 * kTpb) {
+      double a2 = 0.0, b2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double d = dv[3 * i + c];
+        double t = d + alpha * p[3 * i + c];
+        a2 += t * t;
+        b2 += d * d;
+      }
+      s += 0.5 * m[i] * a2 - 0.5 * m[i] * b2;
+    }
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[nb1 + b] = t;
+  }
 }
 
 // sum_i |g_i / (scale * xi_i)|^2, the squared CN-scaled gradient norm.
@@ -133,6 +169,18 @@ __device__ inline double finish_sum(int nparts, const double* __restrict__ parti
   return block_sum(s, sh);
 }
 
+// out[0] = sum of partial[0, n1), out[1] = sum of partial[n1, n1 + n2), each
+// in the order of k_finish.
+__global__ void k_finish2(int n1, int n2, const double* __restrict__ partial,
+                          double* __restrict__ out) {
+  __shared__ double sh[kTpb / 64];
+  double t = finish_sum(n1, partial, sh);
+  if (threadIdx.x == 0) out[0] = t;
+  __syncthreads();
+  t = finish_sum(n2, partial + n1, sh);
+  if (threadIdx.x == 0) out[1] = t;
+}
+
 // Start of either two-loop recursion: v <- -init (if init is given), then the
 // block partials of dnext . v.
 __global__ void k_twoloop_start(long long n, const double* __restrict__ init, double* __restrict__ v,
@@ -199,9 +247,12 @@ __global__ void k_step_update(long long n, const double* __restrict__ dv, double
   sv[k] = t - dv[k];
 }
 
-// y = g_new - g with the partials of y.s, y.y, s.s (the k_partial3 order).
+// y = g_new - g with the partials of y.s, y.y, s.s (the k_partial3 order),
+// then those of the squared CN norm of g_new over the n0 nodes (the k_cn
+// loop with the same grid).
 __global__ void k_secant(long long n, const double* __restrict__ gnew, const double* __restrict__ g,
-                         double* __restrict__ y, const double* __restrict__ sv,
+                         double* __restrict__ y, const double* __restrict__ sv, int n0,
+                         const double* __restrict__ xi, double scale,
                          double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -223,6 +274,17 @@ __global__ void k_secant(long long n, const double* __restrict__ gnew, const dou
     partial[gridDim.x + blockIdx.x] = t1;
     partial[2 * gridDim.x + blockIdx.x] = t2;
   }
+  __syncthreads();
+  double sc = 0.0;
+  for (int i = blockIdx.x * kTpb + threadIdx.x; i < n0; i += (int)gridDim.x * kTpb) {
+    double d = scale * xi[i];
+    for (int c = 0; c < 3; ++c) {
+      double q = gnew[3 * i + c] / d;
+      sc += q * q;
+    }
+  }
+  double t3 = block_sum(sc, sh);
+  if (threadIdx.x == 0) partial[3 * gridDim.x + blockIdx.x] = t3;
 }
 
 __global__ void k_scale_copy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
@@ -267,12 +329,6 @@ void launch_sum(long long n, const double* a, double* partial, double* out, hipS
   k_partial<<<nb, kTpb, 0, st>>>(n, 1, a, nullptr, partial);
   k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
 }
-void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
-                     hipStream_t st) {
-  const int nb = red_blocks(n);
-  k_partial<<<nb, kTpb, 0, st>>>(n, 2, a, b, partial);
-  k_finish<<<1, kTpb, 0, st>>>(nb, 1, 0, partial, out);
-}
 void launch_kinetic_delta(int n, const double* mass, const double* dv, const double* p,
                           double alpha, double* partial, double* out, hipStream_t st) {
   const int nb = red_blocks(3LL * n);
@@ -307,11 +363,20 @@ void launch_step_update(long long n, const double* dv, double alpha, const doubl
                         double* sv, hipStream_t st) {
   if (n > 0) k_step_update<<<blocks_for(n), kTpb, 0, st>>>(n, dv, alpha, p, dvt, sv);
 }
-void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
-                   double* partial, double* out, hipStream_t st) {
+void launch_secant_cn(long long n, const double* gnew, const double* g, double* y, const double* sv,
+                      int n0, const double* xi, double scale, double* partial, double* out,
+                      hipStream_t st) {
   const int nb = red_blocks(n);
-  k_secant<<<nb, kTpb, 0, st>>>(n, gnew, g, y, sv, partial);
-  k_finish<<<1, kTpb, 0, st>>>(nb, 3, 0, partial, out);
+  k_secant<<<nb, kTpb, 0, st>>>(n, gnew, g, y, sv, n0, xi, scale, partial);
+  k_finish<<<1, kTpb, 0, st>>>(nb, 4, 0, partial, out);
+}
+void launch_energy_delta(long long n, const double* psi_t, const double* psi_c, int n0,
+                         const double* mass, const double* dv, const double* p, double alpha,
+                         double* partial, double* out, hipStream_t st) {
+  const int nb1 = red_blocks(n), nb2 = red_blocks(3LL * n0);
+  k_energy_delta<<<std::max(nb1, nb2), kTpb, 0, st>>>(n, psi_t, psi_c, nb1, n0, mass, dv, p, alpha,
+                                                      nb2, partial);
+  k_finish2<<<1, kTpb, 0, st>>>(nb1, nb2, partial, out);
 }
 void launch_scale_copy(long long n, double a, const double* x, double* y, hipStream_t st) {
   if (n > 0) k_scale_copy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);

@@ -422,7 +422,7 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
   A(nbt * 4);
   const double W = p->lbfgs_history + 1;
   for (int k = 0; k < 2; ++k) A(W * 8);
-  A(NSCAL * 8); A(kRedBlocks * 3 * 8);  // scalars, partials
+  A(NSCAL * 8); A(kRedBlocks * 4 * 8);  // scalars, partials
   A((double)(sizeof(MaterialDev) * kMaxMats + sizeof(BcDev) * kMaxBcs));  // tables
   A((double)c.bricks * 4); A((double)c.bricks * kBrickWin * 5 * 8);
   // levels
@@ -703,9 +703,9 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
         PROF(s, HOT_PROF_SGS0, sgs_smooth(s, m, bs[m], us[m]));
       else
         sgs_smooth(s, m, bs[m], us[m]);
-    } else {
+    } else if (m == 0) {
       launch_jacobi_first(Lm, mx, bs[m], us[m], st);
-    }
+    }  // levels m > 0 got their first smoothing from the restriction
     for (int k = 1; k < sweeps && !gs; ++k) {
       if (m == 0)
         PROF(s, HOT_PROF_SMOOTH0, launch_smooth(Lm, mx, bs[m], us[m], s->L[m].t.p, st));
@@ -718,7 +718,9 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
       PROF(s, HOT_PROF_RESIDUAL0, launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st));
     else
       launch_residual(Lm, mx, bs[m], us[m], s->L[m].r.p, st);
-    launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], st);
+    const bool first = !gs && m + 2 < M;  // level m + 1 is smoothed, not solved
+    launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], first ? us[m + 1] : nullptr,
+                    st);
   }
   int slot = std::min(s->vcycles, s->prm.max_iters * 3 + 15);
   HIPCHK(launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p,
@@ -889,8 +891,8 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     // -- descent check and the first trial in one readback
     int trial = 1 - s->pc;
     TRY(eval_trial(s, dv, r, 1.0, trial));
-    launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
-    launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
+    launch_energy_delta(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), n0,
+                        P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEP, st);
     TRY(readback(s));
     double gp = s->hscal[S_GP];
     int fb = 0;
@@ -910,8 +912,8 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
         gp = s->hscal[S_GP];
       }
       TRY(eval_trial(s, dv, r, 1.0, trial));
-      launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial, dscal + S_DEP, st);
-      launch_kinetic_delta(n0, P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEK, st);
+      launch_energy_delta(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), n0,
+                          P<double>(s->mass), dv, r, 1.0, partial, dscal + S_DEP, st);
       TRY(readback(s));
       ++fallbacks;
     }
@@ -922,9 +924,8 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     for (halvings = 0; halvings <= 30; ++halvings) {
       if (halvings > 0) {
         TRY(eval_trial(s, dv, r, alpha, trial));
-        launch_sum_diff(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), partial,
-                        dscal + S_DEP, st);
-        launch_kinetic_delta(n0, P<double>(s->mass), dv, r, alpha, partial, dscal + S_DEK, st);
+        launch_energy_delta(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), n0,
+                            P<double>(s->mass), dv, r, alpha, partial, dscal + S_DEP, st);
         TRY(readback(s));
       }
       dE = s->hscal[S_DEP] + s->hscal[S_DEK];
@@ -953,9 +954,9 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     dvt = P<double>(s->dvt);
     s->pc = trial;
     TRY(gradient(s, dv, s->pc, gnew));
-    launch_secant(N, gnew, g, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), partial,
-                  dscal + S_YS, st);
-    launch_cn_sq(n0, gnew, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
+    // y.s, y.y, s.s and the CN norm land in S_YS, S_YY, S_SS, S_CN
+    launch_secant_cn(N, gnew, g, P<double>(s->Yh[slot]), P<double>(s->Sh[slot]), n0,
+                     P<double>(s->xi), cn_scale, partial, dscal + S_YS, st);
     TRY(readback(s));
     double ys = s->hscal[S_YS], yy = s->hscal[S_YY], ss = s->hscal[S_SS];
     bool keep = ys > 1e-12 * std::sqrt(yy * ss);
@@ -1279,7 +1280,7 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
   }
   int W = params->lbfgs_history + 1;
   if ((rc = ensure(s, s->dalpha, W * 8)) < 0 || (rc = ensure(s, s->drho, W * 8)) < 0 ||
-      (rc = ensure(s, s->dscal, NSCAL * 8)) < 0 || (rc = ensure(s, s->partial, kRedBlocks * 3 * 8)) < 0)
+      (rc = ensure(s, s->dscal, NSCAL * 8)) < 0 || (rc = ensure(s, s->partial, kRedBlocks * 4 * 8)) < 0)
     return bail(rc);
   // upload (host staging in caller order; ids = caller indices)
   std::vector<char> host(per);

@@ -216,8 +216,10 @@ void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u,
                    hipStream_t st);
 // compact FP64 copy of a level's dense iterate
 void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out, hipStream_t st);
+// bc = P~^T r; with uc given, also the coarse level's first smoothing from
+// zero, uc = D~^{-1} bc on its dense grid (what launch_jacobi_first writes)
 void launch_restrict(const LevelView& F, const LevelView& Cv, bool mixed, const void* r,
-                     void* bc, hipStream_t st);
+                     void* bc, void* uc, hipStream_t st);
 void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, const void* uc,
                         void* u, hipStream_t st);
 // Coarsest solve; iters_out receives the iteration count, or -1 if a grid
@@ -240,8 +242,6 @@ constexpr int kRedBlocks = 2048;  // most partials a reduction writes
 void launch_dot(long long n, const double* a, const double* b, double* partial, double* out,
                 hipStream_t st);
 void launch_sum(long long n, const double* a, double* partial, double* out, hipStream_t st);
-void launch_sum_diff(long long n, const double* a, const double* b, double* partial, double* out,
-                     hipStream_t st);  // sum(a - b)
 void launch_kinetic_delta(int n, const double* mass, const double* dv, const double* p,
                           double alpha, double* partial, double* out, hipStream_t st);
 void launch_cn_sq(int n, const double* g, const double* xi, double scale, double* partial,
@@ -265,9 +265,16 @@ void launch_finish_partials(long long n, const double* partial, double* out, hip
 // dvt = dv + alpha p, sv = dvt - dv
 void launch_step_update(long long n, const double* dv, double alpha, const double* p, double* dvt,
                         double* sv, hipStream_t st);
-// y = gnew - g; out = {y.s, y.y, s.s}
-void launch_secant(long long n, const double* gnew, const double* g, double* y, const double* sv,
-                   double* partial, double* out, hipStream_t st);
+// y = gnew - g; out = {y.s, y.y, s.s, sum_i |gnew_i / (scale xi_i)|^2} (n0 nodes);
+// partial holds 4 red_blocks(n) values
+void launch_secant_cn(long long n, const double* gnew, const double* g, double* y, const double* sv,
+                      int n0, const double* xi, double scale, double* partial, double* out,
+                      hipStream_t st);
+// out = {sum_p (psi_t - psi_c) over n particles, kinetic change over n0 nodes}
+// (the sum of differences and the launch_kinetic_delta sum, bit for bit)
+void launch_energy_delta(long long n, const double* psi_t, const double* psi_c, int n0,
+                         const double* mass, const double* dv, const double* p, double alpha,
+                         double* partial, double* out, hipStream_t st);
 void launch_to_f32(long long n, const double* x, float* y, hipStream_t st);
 void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
                                hipStream_t st);

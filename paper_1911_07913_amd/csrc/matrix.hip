@@ -724,7 +724,8 @@ __global__ __launch_bounds__(256) void k_sgs_color(LevelView L, const int* __res
 // small coarse grids).
 template <typename V>
 __global__ __launch_bounds__(256) void k_restrict(LevelView F, LevelView C,
-                                                  const V* __restrict__ r, V* __restrict__ bc) {
+                                                  const V* __restrict__ r, V* __restrict__ bc,
+                                                  typename Vec4Of<V>::type* __restrict__ uc4) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int a = lane & 31;
   const int J = ((blockIdx.x * 4 + wave) << 1) + (lane >> 5);
@@ -750,6 +751,15 @@ __global__ __launch_bounds__(256) void k_restrict(LevelView F, LevelView C,
     bc[3 * J] = s0;
     bc[3 * J + 1] = s1;
     bc[3 * J + 2] = s2;
+    if (uc4) {  // the coarse level's first smoothing from zero, as k_jacobi_first
+      const V* Di = MatOf<V>::Dinv(C) + 9 * (long long)J;
+      typename Vec4Of<V>::type o;
+      o.x = Di[0] * s0 + Di[1] * s1 + Di[2] * s2;
+      o.y = Di[3] * s0 + Di[4] * s1 + Di[5] * s2;
+      o.z = Di[6] * s0 + Di[7] * s1 + Di[8] * s2;
+      o.w = 0;
+      uc4[C.nodes[J]] = o;
+    }
   }
 }
 
@@ -1368,13 +1378,14 @@ void launch_smooth(const LevelView& L, bool mixed, const void* b, const void* u,
     sweep_launch<double>(true, L, (const double*)b, u, uo, st);
 }
 void launch_restrict(const LevelView& F, const LevelView& C, bool mixed, const void* r, void* bc,
-                     hipStream_t st) {
+                     void* uc, hipStream_t st) {
   if (C.n == 0) return;
   if (mixed)
-    k_restrict<float><<<(unsigned)((C.n + 7) / 8), 256, 0, st>>>(F, C, (const float*)r, (float*)bc);
+    k_restrict<float><<<(unsigned)((C.n + 7) / 8), 256, 0, st>>>(F, C, (const float*)r, (float*)bc,
+                                                                (float4*)uc);
   else
     k_restrict<double><<<(unsigned)((C.n + 7) / 8), 256, 0, st>>>(F, C, (const double*)r,
-                                                                 (double*)bc);
+                                                                 (double*)bc, (double4*)uc);
 }
 void launch_prolong_add(const LevelView& F, const LevelView& C, bool mixed, const void* uc, void* u,
                         hipStream_t st) {
