@@ -658,8 +658,8 @@ hot_status prepare(hot_scene* s, double dt) {
   if (s->prof)
     for (int m = 0; m < std::min(s->levels, 2); ++m)
       launch_pattern_count(view(s, m), P<double>(s->dscal) + S_NNZ + m, st);
-  if (s->mixed)
-    for (int m = 0; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
+  if (s->mixed)  // level 0's BF16 copy comes from the assembly itself
+    for (int m = 1; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
   if (s->prm.smoother == HOT_SMOOTH_SGS && s->levels > 1) TRY(prepare_sgs(s));
   size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
   TRY(ensure(s, s->pcg_work, pcg));

@@ -18,13 +18,6 @@ inline unsigned blocks_for(long long n, int tpb = kTpb) {
 }
 
 // ---------------------------------------------------------------- BF16
-__device__ inline uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(r >> 16);
-}
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
 template <typename V, typename M>
 __device__ inline V ldm(const M* p);
 template <>

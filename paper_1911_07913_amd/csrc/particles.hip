@@ -539,7 +539,9 @@ __device__ inline void fin_roles(int tid, int nxw, FinRoles& fr) {
 // Block-level finalisation of level-0 row i held in LDS (256 threads): mass
 // on the diagonal, Dirichlet projection (constrained row -> m_i I, blocks to
 // constrained neighbours -> 0), exact-zero diagonal rule, write-out, scalar
-// diagonal and the l1 block-Jacobi inverse.  nbf holds the constrained flags
+// diagonal and the l1 block-Jacobi inverse.  In mixed precision (L.Hb set)
+// the BF16 blocks and FP32 copies of the diagonal and inverse are written
+// here too, as the level conversion would.  nbf holds the constrained flags
 // of the 5x5 y-z neighbourhood of the segment's x-line, x-major from xw0.
 __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
                                           const LevelView& L, const uint8_t* nbf,
@@ -562,16 +564,19 @@ __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
       acc[(4 * g) * kSlotPad + kCenter] = zero ? 1.0 : d;
       L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
       L.diag[3 * i + g] = zero ? 1.0 : d;
+      if (L.Hb) L.diag32[3 * i + g] = (float)(zero ? 1.0 : d);
     }
   }
   __syncthreads();
   double l1[3] = {0.0, 0.0, 0.0};
   double* Hrow = L.H + (long long)i * kRowStride;
+  uint16_t* Hbrow = L.Hb ? L.Hb + (long long)i * kRowStride : nullptr;
 #pragma unroll
   for (int k = 0; k < kFinItems; ++k) {
     if (fr.idx[k] >= 0) {
       double v = acc[fr.idx[k]];
       Hrow[fr.idx[k]] = v;
+      if (Hbrow) Hbrow[fr.idx[k]] = f32_to_bf16((float)v);
       const double av = fabs(v);
       l1[0] += (fr.g[k] == 0) ? av : 0.0;
       l1[1] += (fr.g[k] == 1) ? av : 0.0;
@@ -590,6 +595,8 @@ __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
     double Di[9];
     inv3(Dt, Di);
     for (int k = 0; k < 9; ++k) L.Dinv[(long long)i * 9 + k] = Di[k];
+    if (L.Hb)
+      for (int k = 0; k < 9; ++k) L.Dinv32[(long long)i * 9 + k] = (float)Di[k];
   }
   __syncthreads();
 }
