@@ -247,7 +247,7 @@ __global__ void k_step_update(long long n, const double* __restrict__ dv, double
   sv[k] = t - dv[k];
 }
 
-// y = g_new - g with the partials of y.s, y.y, s.s (the k_partial3 order),
+// y = g_new - g with the block partials of y.s, y.y, s.s (in that order),
 // then those of the squared CN norm of g_new over the n0 nodes (the k_cn
 // loop with the same grid).
 __global__ void k_secant(long long n, const double* __restrict__ gnew, const double* __restrict__ g,
