@@ -194,9 +194,12 @@ void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, co
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
                 const double* dv, double dt, double* wnode, hipStream_t st);
+// level-0 Hessian: the particles' a_l operands into Ag ([n][27][3], scratch),
+// then the row segments' blocks
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        const double* f, const double* F, const double* Cp, const int* cstart,
-                        const int* ccount, const double* mass, const int* fixed, hipStream_t st);
+                        int n, const double* f, const double* F, const double* Cp, double* Ag,
+                        const int* cstart, const int* ccount, const double* mass, const int* fixed,
+                        hipStream_t st);
 
 // matrix.hip
 void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);

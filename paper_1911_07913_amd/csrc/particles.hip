@@ -490,7 +490,8 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // a 27 x 27 x 3P product that the four waves compute as 2 x 2 tiles of FP64
 // 16x16x4 matrix-core instructions, accumulating in registers over the
 // column's particles; each lane forms its own Z operands from a_k and C_p in
-// registers right before the matrix-core steps.  Per cell column the sums go
+// registers right before the matrix-core steps.  The a_l come precomputed
+// (k_particle_agrad) and are staged with C_p as two contiguous ranges.  Per cell column the sums go
 // to a 3-row sliding window in LDS.  After cell c, row c receives nothing
 // more: it is finalised (mass, Dirichlet projection, smoother inverse) and
 // written once.  Every block of every particle is computed exactly once; no
@@ -498,9 +499,10 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // registers (at most 128) are sized so that four work-groups share a compute
 // unit.
 constexpr int kAsmChunk = 8;   // particles staged per pass
-constexpr int kPData = 57;     // f (3), F (9), C (45)
-constexpr int kPFf = 12;       // f and F
-constexpr int kStageRegs = (kAsmChunk * kPData + 255) / 256;
+constexpr int kPA = 81;        // a_l (27 x 3) per particle
+constexpr int kPC = 45;        // C per particle
+constexpr int kARegs = (kAsmChunk * kPA + 255) / 256;
+constexpr int kCRegs = (kAsmChunk * kPC + 255) / 256;
 
 __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
   double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
@@ -508,6 +510,27 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
   double d0 = (f - 1.5) * inv_dx, d1 = -2.0 * b * inv_dx, d2 = c * inv_dx;
   w = (k == 0) ? w0 : ((k == 1) ? w1 : w2);
   dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
+}
+
+// The assembly's right-hand operands a_lp = F_p^n^T grad w_lp for the 27
+// stencil nodes l of every particle, [n][27][3], once per step (the assembly
+// visits each particle from up to 9 x-lines).  One thread per (particle, node).
+__global__ void k_particle_agrad(SceneDev s, long long n27, const double* __restrict__ f,
+                                 const double* __restrict__ Fn, double* __restrict__ A) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n27) return;
+  const long long p = e / 27;
+  const int l = (int)(e - 27 * p);
+  double w0, d0, w1, d1, w2, d2;
+  wdw(l % 3, f[3 * p], s.inv_dx, w0, d0);
+  wdw((l / 3) % 3, f[3 * p + 1], s.inv_dx, w1, d1);
+  wdw(l / 9, f[3 * p + 2], s.inv_dx, w2, d2);
+  double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
+  const double* F = Fn + 9 * p;
+  double* o = A + 3 * e;
+  o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
+  o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
+  o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
 }
 
 // Entries (c, s) of a block row owned by one of 256 threads, decomposed once:
@@ -603,15 +626,14 @@ __device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin,
-                      const double* __restrict__ f, const double* __restrict__ Fn,
-                      const double* __restrict__ Cp, const int* __restrict__ cstart,
+                      const double* __restrict__ Ag, const double* __restrict__ Cp,
+                      const int* __restrict__ cstart,
                       const int* __restrict__ ccount, const double* __restrict__ mass,
                       const int* __restrict__ fixed) {
   constexpr int kMaxCx = kSegRows + 2;
   __shared__ double win[3][kRowStride];
-  __shared__ double pf[kAsmChunk][kPFf];     // f, F of the staged particles
-  __shared__ double pc[kAsmChunk][45];       // their C
   __shared__ double av[kAsmChunk][27][3];    // a_l of the staged particles
+  __shared__ double pc[kAsmChunk][kPC];      // their C
   __shared__ double red[12];
   __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
   __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
@@ -645,9 +667,6 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
     rmass[v] = mass[rb + v];
   }
   for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
-  // a-phase role: particle a_q, stencil node a_l
-  const int a_q = (tid < kAsmChunk * 27) ? tid / 27 : kAsmChunk, a_l = tid % 27;
-  const int a_lx = a_l % 3, a_ly = (a_l / 3) % 3, a_lz = a_l / 9;
   // matrix-core roles: wave w owns output tile (rows 16 tile_m.., columns
   // 16 tile_n..) of the 27 x 27 product; lane l feeds A[l % 16][l / 16] and
   // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3
@@ -697,35 +716,27 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
     nv = -1;
     nt = 0;
   };
-  // staging roles: value e = tid + 256k of a chunk is entry w of particle q
-  int sq[kStageRegs], sw[kStageRegs];
-#pragma unroll
-  for (int k = 0; k < kStageRegs; ++k) {
-    int e = tid + 256 * k;
-    sq[k] = e / kPData;
-    sw[k] = e - sq[k] * kPData;
-  }
-  auto fetch = [&](int v, int t0, double* r) {
+  // staging: a chunk's particles are consecutive, so its a_l and C values are
+  // two contiguous ranges; thread tid moves entries tid + 256 k of each
+  auto fetch = [&](int v, int t0, double* ra, double* rc) {
     if (v < 0) return;
     const int np = min(kAsmChunk, mcnt[v] - t0);
     const long long st = mst[v] + t0;
 #pragma unroll
-    for (int k = 0; k < kStageRegs; ++k) {
-      if (sq[k] < np) {
-        const long long pp = st + sq[k];
-        const int w = sw[k];
-        const double* src = (w < 3) ? (f + 3 * pp + w)
-                                    : ((w < 12) ? (Fn + 9 * pp + (w - 3)) : (Cp + 45 * pp + (w - 12)));
-        r[k] = *src;
-      }
-    }
-  };
-  double regs[kStageRegs];
+    for (int k = 0; k < kARegs; ++k)
+      if (tid + 256 * k < kPA * np) ra[k] = Ag[kPA * st + tid + 256 * k];
 #pragma unroll
-  for (int k = 0; k < kStageRegs; ++k) regs[k] = 0.0;
+    for (int k = 0; k < kCRegs; ++k)
+      if (tid + 256 * k < kPC * np) rc[k] = Cp[kPC * st + tid + 256 * k];
+  };
+  double ra[kARegs], rc[kCRegs];
+#pragma unroll
+  for (int k = 0; k < kARegs; ++k) ra[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kCRegs; ++k) rc[k] = 0.0;
   int jv, jt;
   next_job(-1, 0, jv, jt);
-  fetch(jv, jt, regs);
+  fetch(jv, jt, ra, rc);
   int next_row = rb;
   for (int ci = 0; ci < ncx; ++ci) {
     const int c = xa - 2 + ci;
@@ -740,32 +751,16 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
         const int np = min(kAsmChunk, cnt - t0);
         __syncthreads();  // the previous pass's operand reads are done
 #pragma unroll
-        for (int k = 0; k < kStageRegs; ++k)
-          if (sq[k] < np) {
-            if (sw[k] < kPFf)
-              pf[sq[k]][sw[k]] = regs[k];
-            else
-              pc[sq[k]][sw[k] - kPFf] = regs[k];
-          }
+        for (int k = 0; k < kARegs; ++k)
+          if (tid + 256 * k < kPA * np) (&av[0][0][0])[tid + 256 * k] = ra[k];
+#pragma unroll
+        for (int k = 0; k < kCRegs; ++k)
+          if (tid + 256 * k < kPC * np) (&pc[0][0])[tid + 256 * k] = rc[k];
         __syncthreads();
         // prefetch the next chunk while this one is processed
         int nv, nt;
         next_job(v, t0, nv, nt);
-        fetch(nv, nt, regs);
-        // a_l = F^T grad w_l for the 27 stencil nodes of each staged particle
-        if (a_q < np) {
-          double w0, d0, w1, d1, w2, d2;
-          wdw(a_lx, pf[a_q][0], s.inv_dx, w0, d0);
-          wdw(a_ly, pf[a_q][1], s.inv_dx, w1, d1);
-          wdw(a_lz, pf[a_q][2], s.inv_dx, w2, d2);
-          double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
-          const double* F = &pf[a_q][3];
-          double* o = av[a_q][a_l];
-          o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
-          o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
-          o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
-        }
-        __syncthreads();
+        fetch(nv, nt, ra, rc);
         // A operands Z_r[g][3d + e] = sum_b a_k[b] C[3g + b][3d + e], k = (r, ky, kz),
         // then B[(r, g, d)][l] += sum over the chunk's (p, eps), four at a time
         {
@@ -885,11 +880,13 @@ void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, 
 }
 
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        const double* f, const double* F, const double* Cp, const int* cstart,
-                        const int* ccount, const double* mass, const int* fixed, hipStream_t st) {
+                        int n, const double* f, const double* F, const double* Cp, double* Ag,
+                        const int* cstart, const int* ccount, const double* mass, const int* fixed,
+                        hipStream_t st) {
+  const long long n27 = 27LL * n;
+  if (n27 > 0) k_particle_agrad<<<blocks_for(n27), kTpb, 0, st>>>(s, n27, f, F, Ag);
   if (n_seg > 0)
-    k_assemble_strip<<<n_seg, 256, 0, st>>>(s, L0, seg_begin, f, F, Cp, cstart, ccount, mass,
-                                            fixed);
+    k_assemble_strip<<<n_seg, 256, 0, st>>>(s, L0, seg_begin, Ag, Cp, cstart, ccount, mass, fixed);
 }
 
 }  // namespace hot
