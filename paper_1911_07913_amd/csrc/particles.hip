@@ -495,9 +495,9 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // to a 3-row sliding window in LDS.  After cell c, row c receives nothing
 // more: it is finalised (mass, Dirichlet projection, smoother inverse) and
 // written once.  Every block of every particle is computed exactly once; no
-// atomics.  The kernel is bound by latency, not by a unit: LDS (38.6 KB) and
-// registers (at most 128) are sized so that four work-groups share a compute
-// unit.
+// atomics.  The kernel is bound by latency, not by a unit: LDS (under 40 KB)
+// and registers (at most 128) are sized so that four work-groups share a
+// compute unit.
 constexpr int kAsmChunk = 8;   // particles staged per pass
 constexpr int kPA = 81;        // a_l (27 x 3) per particle
 constexpr int kPC = 45;        // C per particle
