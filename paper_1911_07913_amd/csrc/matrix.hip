@@ -31,6 +31,36 @@ __device__ inline V wave_sum_t(V v) {
   return v;
 }
 
+// The same wave sum on the DPP paths (no LDS round trips), for the sweeps:
+// pairs, quads, half-rows and rows of 16 lanes by DPP moves, then the four
+// row sums in a fixed order.  Every lane gets the identical value; all 64
+// lanes must be active.
+template <int Ctrl>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+template <int Ctrl>
+__device__ inline double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), Ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), Ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <typename V>
+__device__ inline V wave_sum_dpp(V v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm(1, 0, 3, 2)
+  v += dpp_mov<0x4E>(v);   // quad_perm(2, 3, 0, 1)
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 template <typename V>
 struct MatOf;
 template <>
@@ -232,9 +262,9 @@ __device__ inline void rows_matvec_g(const LevelView& L, RowOf row_of,
         a2 += h[r][k][6] * x0 + h[r][k][7] * x1 + h[r][k][8] * x2;
       }
     }
-    y[r][0] = wave_sum_t(a0);
-    y[r][1] = wave_sum_t(a1);
-    y[r][2] = wave_sum_t(a2);
+    y[r][0] = wave_sum_dpp(a0);
+    y[r][1] = wave_sum_dpp(a1);
+    y[r][2] = wave_sum_dpp(a2);
   }
 }
 
