@@ -10,10 +10,10 @@ constexpr int kTpb = 256;
 inline unsigned blocks_for(long long n, int tpb = kTpb) {
   return (unsigned)((n + tpb - 1) / tpb);
 }
-// Blocks of a reduction over n terms: about two terms per thread, between 64
+// Blocks of a reduction over n terms: about four terms per thread, between 64
 // and kRedBlocks.  Fixed for a given n, so sums are reproducible.
 inline int red_blocks(long long n) {
-  long long b = (n + 2 * kTpb - 1) / (2 * kTpb);
+  long long b = (n + 4 * kTpb - 1) / (4 * kTpb);
   return (int)std::min<long long>(kRedBlocks, std::max<long long>(64, b));
 }
 
