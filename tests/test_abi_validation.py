@@ -58,7 +58,7 @@ def _box():
 
 @pytest.mark.parametrize("case", ["nan_x", "outside", "E_zero", "nu_half", "bad_mat_id",
                                   "nan_v", "vol_zero", "nh_inverted", "snow_lo_above_1",
-                                  "snow_with_yield"])
+                                  "snow_with_yield", "empty"])
 def test_invalid_scenes_are_refused(case):
     hot = _hot()
     sc = _box()
@@ -84,6 +84,9 @@ def test_invalid_scenes_are_refused(case):
     elif case == "snow_with_yield":
         sc.materials[0]["snow_clamp"] = (0.99, 1.001)
         sc.materials[0]["yield_stress"] = 100.0
+    elif case == "empty":
+        for f in ("x", "v", "F", "C", "vol0", "mat_id"):
+            setattr(sc, f, np.ascontiguousarray(getattr(sc, f)[:0]))
     st, msg = _init(hot, sc)
     assert st == hot.HOT_E_INVALID, (case, st, msg)
     assert msg

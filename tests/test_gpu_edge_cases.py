@@ -1,0 +1,84 @@
+"""Degenerate and ragged inputs through the C ABI against the oracle, each
+stepped once in FP64 with every discrete decision of the solve identical
+and x, v, F within 1e-10:
+
+* one stretched particle alone in the grid (27 active nodes);
+* a box in which one cell holds 29 particles, so that one cell column spans
+  four 8-particle assembly chunks (the last partial), plus one isolated
+  particle away from the box (a second, disconnected node island).
+"""
+import numpy as np
+import pytest
+
+import hot_scenes as hs
+import oracle as O
+from test_gpu_parity import _hot, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _take(sc, idx):
+    for f in ("x", "v", "F", "C", "vol0", "mat_id"):
+        setattr(sc, f, np.ascontiguousarray(getattr(sc, f)[idx]))
+    return sc
+
+
+def _append(sc, x, v):
+    k = x.shape[0]
+    sc.x = np.concatenate([sc.x, x])
+    sc.v = np.concatenate([sc.v, v])
+    sc.F = np.concatenate([sc.F, np.repeat(np.eye(3)[None], k, 0)])
+    sc.C = np.concatenate([sc.C, np.zeros((k, 3, 3))])
+    sc.vol0 = np.concatenate([sc.vol0, np.full(k, sc.vol0[0])])
+    sc.mat_id = np.concatenate([sc.mat_id, np.zeros(k, np.int32)])
+    return sc
+
+
+def single_particle():
+    sc = hs.small_box(seed=141, cells=(10, 10, 10), box_lo=(4, 4, 4), box_hi=(5, 5, 5), levels=2)
+    sc = _take(sc, [0])
+    sc.F[0] = np.diag([1.2, 0.9, 1.1])  # stressed, so the solve has work to do
+    return sc
+
+
+def crowded_cell_and_island():
+    sc = hs.small_box(seed=142, cells=(14, 14, 14), box_lo=(3, 3, 3), box_hi=(7, 7, 7), walls=2,
+                      levels=2, F_spread=0.1)
+    rng = np.random.Generator(np.random.PCG64(143))
+    dx = sc.dx
+    # 21 more particles whose base cell is (5, 5, 5): x / dx in [5.55, 6.45)
+    crowd = (5.55 + 0.9 * rng.random((21, 3))) * dx
+    island = np.array([[10.2, 10.3, 4.6]]) * dx
+    xs = np.concatenate([crowd, island])
+    vs = 0.1 * rng.normal(size=xs.shape)
+    return _append(sc, xs, vs)
+
+
+CASES = {"single_particle": single_particle, "crowded_cell_and_island": crowded_cell_and_island}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_degenerate_step_fp64(name):
+    hot = _hot()
+    sc = CASES[name]()
+    dt = O.time_step(sc)
+    out, info = O.step(sc, dt=dt)
+    g = hot.Scene.from_scene(sc)
+    try:
+        status = g.step(dt)
+        res = g.read()
+        logi = g.debug_read(hot.DBG_LOG_INT, dtype=np.int32).reshape(-1, 4)
+        stats = dict(g.stats)
+    finally:
+        g.close()
+    log = info["log"]
+    print(f"{name}: n = {sc.n}, {stats['iters']} iterations")
+    assert status == 0 and info["converged"]
+    assert stats["iters"] == info["iters"]
+    assert list(logi[:, 0]) == log["alpha_halvings"]
+    assert list(logi[:, 2]) == log["fallback"]
+    assert list(logi[: len(log["skipped"]), 1]) == log["skipped"]
+    assert list(logi[:, 3]) == [sum(c) for c in log["cg"]]
+    assert rel(res["x"], out.x) < 1e-10
+    assert rel(res["v"], out.v) < 1e-10
+    assert rel(res["F"], out.F) < 1e-10
