@@ -453,9 +453,17 @@ def prepare(scene, dt, t=0.0):
     mom = np.stack([np.bincount(st.idx.ravel(), weights=(mw * vapic[:, :, a]).ravel(),
                                 minlength=n) for a in range(3)], -1)
     xi_p = cn_xi(st.mu, st.lam)
-    st.xi = np.bincount(st.idx.ravel(), weights=(mw * xi_p[:, None]).ravel(), minlength=n) / st.m
-    st.vn = mom / st.m[:, None]
-    st.vstar = st.vn + dt * np.asarray(scene.gravity)[None, :]
+    # A stencil node can receive no mass at all when every particle reaching
+    # it sits where its weight vanishes (fractional position exactly 1/2 on
+    # an axis): it carries no momentum equation, gets v* = 0 and xi = 0, and
+    # its exactly zero Hessian diagonal constrains it (reading: nodes without
+    # mass are outside the grid equations of the transfer, Sec. 3.1).
+    has_m = st.m > 0.0
+    m_safe = np.where(has_m, st.m, 1.0)
+    xi_sum = np.bincount(st.idx.ravel(), weights=(mw * xi_p[:, None]).ravel(), minlength=n)
+    st.xi = np.where(has_m, xi_sum / m_safe, 0.0)
+    st.vn = np.where(has_m[:, None], mom / m_safe[:, None], 0.0)
+    st.vstar = np.where(has_m[:, None], st.vn + dt * np.asarray(scene.gravity)[None, :], 0.0)
     st.fixed, vbc = bc_nodes(scene, st.lev0, t + dt)
     st.vstar[st.fixed] = vbc[st.fixed]
     st.free = ~st.fixed
@@ -749,9 +757,11 @@ def vcycle(hz, b, sweeps=1, coarse_solver=None, log=None, smoother="l1jacobi"):
 
 
 def cn_norm(st, g):
-    """||g_hat||_2 with g_hat_i = g_i / (24 dx^2 xi_i dt) (Eq. nodewiseCN)."""
-    scale = 24.0 * st.scene.dx ** 2 * st.xi * st.dt
-    return float(math.sqrt(np.sum((g / scale[:, None]) ** 2)))
+    """||g_hat||_2 with g_hat_i = g_i / (24 dx^2 xi_i dt) (Eq. nodewiseCN),
+    over the nodes that carry mass (xi_i > 0; see prepare)."""
+    live = st.xi > 0.0
+    scale = 24.0 * st.scene.dx ** 2 * st.xi[live] * st.dt
+    return float(math.sqrt(np.sum((g[live] / scale[:, None]) ** 2)))
 
 
 def two_loop(hist, g, apply_H0):

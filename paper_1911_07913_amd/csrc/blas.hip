@@ -101,12 +101,15 @@ __global__ void k_energy_delta(long long n, const double* __restrict__ psi_t,
   }
 }
 
-// sum_i |g_i / (scale * xi_i)|^2, the squared CN-scaled gradient norm.
+// sum_i |g_i / (scale * xi_i)|^2, the squared CN-scaled gradient norm, over
+// the nodes that carry mass (xi_i > 0: a node without mass has xi_i = 0 and
+// no equation).
 __global__ void k_cn(int n, const double* __restrict__ g, const double* __restrict__ xi, double scale,
                      double* __restrict__ partial) {
   __shared__ double sh[kTpb / 64];
   double s = 0.0;
   for (int i = blockIdx.x * kTpb + threadIdx.x; i < n; i += (int)gridDim.x * kTpb) {
+    if (!(xi[i] > 0.0)) continue;
     double d = scale * xi[i];
     for (int c = 0; c < 3; ++c) {
       double q = g[3 * i + c] / d;
@@ -277,6 +280,7 @@ __global__ void k_secant(long long n, const double* __restrict__ gnew, const dou
   __syncthreads();
   double sc = 0.0;
   for (int i = blockIdx.x * kTpb + threadIdx.x; i < n0; i += (int)gridDim.x * kTpb) {
+    if (!(xi[i] > 0.0)) continue;  // no mass, no equation (as k_cn)
     double d = scale * xi[i];
     for (int c = 0; c < 3; ++c) {
       double q = gnew[3 * i + c] / d;

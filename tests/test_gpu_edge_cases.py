@@ -5,7 +5,9 @@ and x, v, F within 1e-10:
 * one stretched particle alone in the grid (27 active nodes);
 * a box in which one cell holds 29 particles, so that one cell column spans
   four 8-particle assembly chunks (the last partial), plus one isolated
-  particle away from the box (a second, disconnected node island).
+  particle away from the box (a second, disconnected node island);
+* a box with a third of its particles on the planes where the base cell
+  changes (near-tie binning decisions).
 """
 import numpy as np
 import pytest
@@ -54,7 +56,22 @@ def crowded_cell_and_island():
     return _append(sc, xs, vs)
 
 
-CASES = {"single_particle": single_particle, "crowded_cell_and_island": crowded_cell_and_island}
+def on_cell_faces():
+    """A box with a third of its particles moved onto the planes where the
+    base cell changes (x / dx - 1/2 an integer, up to rounding of the
+    products): the binning decision there is a near tie, taken with the same
+    IEEE operations on both sides."""
+    sc = hs.small_box(seed=144, cells=(12, 12, 12), box_lo=(3, 3, 3), box_hi=(8, 8, 8), walls=2,
+                      levels=2, F_spread=0.05)
+    k = np.arange(0, sc.n, 3)
+    a = k % 3
+    t = sc.x[k, a] / sc.dx
+    sc.x[k, a] = (np.round(t - 0.5) + 0.5) * sc.dx
+    return sc
+
+
+CASES = {"single_particle": single_particle, "crowded_cell_and_island": crowded_cell_and_island,
+         "on_cell_faces": on_cell_faces}
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -5,6 +5,8 @@ dx^2/4 I, sum of gradients 0 and sum x_i grad w^T = I (quadratic B-spline,
 Sec. 6).  Invariants: P2G/G2P conserve mass, linear and angular momentum
 (APIC, Sec. 3.1), and reproduce affine velocity fields exactly.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -116,3 +118,31 @@ def test_deformation_update_matches_velocity_gradient_of_affine_field():
     dv = xi @ A.T - st.vstar
     F = O.deformation(st, dv)
     assert np.abs(F - (np.eye(3) + st.dt * A) @ sc.F).max() < 1e-13
+
+
+def test_massless_stencil_node():
+    """A particle exactly where a weight vanishes (fractional position 1/2)
+    reaches a node with zero weight and zero gradient.  If no other particle
+    reaches that node it carries no mass: the transfer leaves it at v* = 0
+    and xi = 0 instead of 0/0, mass and momentum sums still equal the
+    particles', and the CN norm and the whole step stay finite."""
+    sc = hs.small_box(seed=23, cells=(10, 10, 10), box_lo=(4, 4, 4), box_hi=(5, 5, 5),
+                      walls=None, noise=0.0, levels=2)
+    for f in ("x", "v", "F", "C", "vol0", "mat_id"):
+        setattr(sc, f, np.ascontiguousarray(getattr(sc, f)[:1]))
+    sc.x[0] = (np.array([4.5, 4.5, 4.5]) + np.array([0.25, 0.0, 0.5])) * sc.dx
+    sc.F[0] = np.diag([1.1, 0.95, 1.05])
+    t = (sc.x[0] - np.asarray(sc.origin)) / sc.dx
+    frac = t - np.floor(t - 0.5)
+    assert np.any(frac == 0.5)          # the set-up really sits on the plane
+    st = _prep(sc)
+    massless = st.m == 0.0
+    assert massless.sum() == 9           # the 3x3 far layer of that axis
+    assert np.all(st.vstar[massless] == 0.0) and np.all(st.xi[massless] == 0.0)
+    assert np.all(np.isfinite(st.vstar)) and np.all(np.isfinite(st.xi))
+    assert abs(st.m.sum() - st.mp.sum()) < 1e-13 * st.mp.sum()
+    P_grid = (st.m[:, None] * st.vn).sum(0)
+    assert np.abs(P_grid - st.mp[0] * sc.v[0]).max() < 1e-13 * (np.abs(sc.v[0]).max() * st.mp[0] + 1e-300)
+    assert math.isfinite(O.cn_norm(st, np.zeros_like(st.vstar)))
+    out, info = O.step(sc, dt=1e-3)
+    assert info["converged"] and np.all(np.isfinite(out.x)) and np.all(np.isfinite(out.F))
