@@ -7,7 +7,9 @@ and x, v, F within 1e-10:
   four 8-particle assembly chunks (the last partial), plus one isolated
   particle away from the box (a second, disconnected node island);
 * a box with a third of its particles on the planes where the base cell
-  changes (near-tie binning decisions).
+  changes (near-tie binning decisions, and nodes left without mass);
+* fixed-corotated and Neo-Hookean particles in one box, with particles at
+  both ends of the valid region on every axis.
 """
 import numpy as np
 import pytest
@@ -70,8 +72,22 @@ def on_cell_faces():
     return sc
 
 
+def mixed_models_at_region_edges():
+    """Fixed-corotated and Neo-Hookean particles side by side (the material
+    branch diverges inside a wave), plus particles at both ends of the valid
+    region on each axis (x / dx exactly 2 and exactly cells - 3)."""
+    sc = hs.small_box(seed=145, cells=(12, 12, 12), box_lo=(3, 3, 3), box_hi=(8, 8, 8), walls=None,
+                      levels=2, n_mats=2, E=2e4, F_spread=0.05)
+    sc.materials[1]["model"] = hs.NEOHOOKEAN
+    lo, hi = 2.0 * sc.dx, (sc.grid_cells[0] - 3) * sc.dx
+    edge = np.array([[lo, 5.5 * sc.dx, 5.5 * sc.dx], [hi, 5.5 * sc.dx, 5.5 * sc.dx],
+                     [5.5 * sc.dx, lo, 5.5 * sc.dx], [5.5 * sc.dx, hi, 5.5 * sc.dx],
+                     [5.5 * sc.dx, 5.5 * sc.dx, lo], [5.5 * sc.dx, 5.5 * sc.dx, hi]])
+    return _append(sc, edge, np.zeros_like(edge))
+
+
 CASES = {"single_particle": single_particle, "crowded_cell_and_island": crowded_cell_and_island,
-         "on_cell_faces": on_cell_faces}
+         "on_cell_faces": on_cell_faces, "mixed_models_at_region_edges": mixed_models_at_region_edges}
 
 
 @pytest.mark.parametrize("name", list(CASES))
