@@ -115,3 +115,31 @@ def test_degenerate_step_fp64(name):
     assert rel(res["x"], out.x) < 1e-10
     assert rel(res["v"], out.v) < 1e-10
     assert rel(res["F"], out.F) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_degenerate_step_mixed(name):
+    """Mixed precision (BF16 blocks, FP32 V-cycle) on the same inputs, held
+    to the bar of reading R23: its distance to a tightly converged step
+    (the oracle at 1e-10) is at most twice the FP64 step's, or 1e-6."""
+    hot = _hot()
+    sc = CASES[name]()
+    dt = O.time_step(sc)
+    out, info = O.step(sc, dt=dt)
+    tight = CASES[name]()
+    tight.tol = 1e-10
+    ref, rinfo = O.step(tight, dt=dt)
+    g = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
+    try:
+        status = g.step(dt)
+        res = g.read()
+        stats = dict(g.stats)
+    finally:
+        g.close()
+    tx, tv = rel(out.x, ref.x), rel(out.v, ref.v)
+    mx, mv = rel(res["x"], ref.x), rel(res["v"], ref.v)
+    print(f"{name}: iterations mixed {stats['iters']}, fp64 {info['iters']}, tight {rinfo['iters']}; "
+          f"to the tight step: fp64 x {tx:.2e} v {tv:.2e}, mixed x {mx:.2e} v {mv:.2e}")
+    assert status == 0 and stats["converged"] and rinfo["converged"]
+    assert mx <= max(1e-6, 2.0 * tx)
+    assert mv <= max(1e-6, 2.0 * tv)
