@@ -90,13 +90,19 @@ CASES = {"single_particle": single_particle, "crowded_cell_and_island": crowded_
          "on_cell_faces": on_cell_faces, "mixed_models_at_region_edges": mixed_models_at_region_edges}
 
 
+SMOOTHERS = {"l1jacobi": 0, "sgs": 1}
+
+
+@pytest.mark.parametrize("smoother", list(SMOOTHERS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_degenerate_step_fp64(name):
+def test_degenerate_step_fp64(name, smoother):
+    """FP64 step with either smoother (tiny levels leave Gauss-Seidel colours
+    without rows)."""
     hot = _hot()
     sc = CASES[name]()
     dt = O.time_step(sc)
-    out, info = O.step(sc, dt=dt)
-    g = hot.Scene.from_scene(sc)
+    out, info = O.step(sc, dt=dt, smoother=smoother)
+    g = hot.Scene.from_scene(sc, smoother=SMOOTHERS[smoother])
     try:
         status = g.step(dt)
         res = g.read()
@@ -105,7 +111,7 @@ def test_degenerate_step_fp64(name):
     finally:
         g.close()
     log = info["log"]
-    print(f"{name}: n = {sc.n}, {stats['iters']} iterations")
+    print(f"{name} ({smoother}): n = {sc.n}, {stats['iters']} iterations")
     assert status == 0 and info["converged"]
     assert stats["iters"] == info["iters"]
     assert list(logi[:, 0]) == log["alpha_halvings"]
