@@ -28,8 +28,8 @@ def small_requests():
     return [hs.serving_scene(i, seed_base=4500, n_min=2000, n_max=24000) for i in range(N_REQ)]
 
 
-def alone(hot, sc, precision):
-    g = hot.Scene.from_scene(sc, precision=precision)
+def alone(hot, sc, precision, smoother=0):
+    g = hot.Scene.from_scene(sc, precision=precision, smoother=smoother)
     try:
         for _ in range(STEPS):
             g.step()
@@ -38,11 +38,12 @@ def alone(hot, sc, precision):
         g.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_results_identical_alone_and_in_the_mix(precision):
+@pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (1, 1)],
+                         ids=["fp64", "mixed", "mixed-gauss-seidel"])
+def test_results_identical_alone_and_in_the_mix(precision, smoother):
     hot, serving = _mods()
     reqs = small_requests()
-    ref = [alone(hot, sc, precision) for sc in reqs]
+    ref = [alone(hot, sc, precision, smoother) for sc in reqs]
     got = {}
 
     def collect(k, scene):
@@ -50,7 +51,8 @@ def test_results_identical_alone_and_in_the_mix(precision):
 
     arrivals = serving.poisson_arrivals(N_REQ, rate=200.0, seed=7)
     records, summary, trace = serving.serve(reqs, arrivals, budget_bytes=8 << 30, max_slots=4,
-                                            precision=precision, n_steps=STEPS, collect=collect)
+                                            precision=precision, n_steps=STEPS, collect=collect,
+                                            smoother=smoother)
     print(summary, trace)
     assert len(records) == N_REQ and summary["failed"] == 0
     assert trace["peak_resident"] > 1, "requests never overlapped"
