@@ -121,3 +121,34 @@ def test_snow_clamp_steps_fp64():
             cur = out
     finally:
         g.close()
+
+
+def test_snow_clamp_step_mixed():
+    """The snow clamp after a mixed-precision solve: the clamp runs on the
+    FP64 particle state, so the GPU's F keeps its singular values inside
+    [0.99, 1.001]; the step meets R23's bar against a tight oracle step."""
+    hot = _hot()
+    make = lambda: hs.small_box(seed=104, cells=(12, 12, 12), box_lo=(3, 3, 3), box_hi=(9, 8, 8),
+                                walls=2, levels=2, F_spread=0.05)
+    sc = make()
+    sc.materials[0]["snow_clamp"] = (0.99, 1.001)
+    dt = O.time_step(sc)
+    out, info = O.step(sc, dt=dt)
+    tight = make()
+    tight.materials[0]["snow_clamp"] = (0.99, 1.001)
+    tight.tol = 1e-10
+    ref, rinfo = O.step(tight, dt=dt)
+    g = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
+    try:
+        status = g.step(dt)
+        res = g.read()
+    finally:
+        g.close()
+    assert status == 0 and rinfo["converged"]
+    s = np.linalg.svd(res["F"], compute_uv=False)
+    assert s.min() >= 0.99 - 1e-12 and s.max() <= 1.001 + 1e-12
+    tx, tv = rel(out.x, ref.x), rel(out.v, ref.v)
+    mx, mv = rel(res["x"], ref.x), rel(res["v"], ref.v)
+    print(f"snow mixed: to the tight step fp64 x {tx:.2e} v {tv:.2e}, mixed x {mx:.2e} v {mv:.2e}")
+    assert mx <= max(1e-6, 2.0 * tx)
+    assert mv <= max(1e-6, 2.0 * tv)
