@@ -12,7 +12,9 @@ quantities are computed with vectorised numpy over particles, scatters use
 material finite differences and closed forms, pattern counts in closed form,
 Galerkin vs dense products and vs the composite-kernel re-discretisation,
 V-cycle symmetry and exactness, two-loop vs dense BFGS, converged step vs a
-dense projected-Newton minimiser).  Whole-trajectory values are parity
+dense projected-Newton minimiser, boundary conditions and the time-step rule
+in closed form, l1 block-Jacobi special cases and contraction, coarsest PCG
+vs the brute-force Krylov minimiser).  Whole-trajectory values are parity
 unpinned beyond these pieces: the paper prints no worked example.
 """
 from __future__ import annotations
