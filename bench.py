@@ -42,16 +42,15 @@ BOUND = {"smooth0": "hbm", "residual0": "hbm", "sgs0": "hbm", "rap0": "hbm", "pa
 FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 9 + 27 * 81 + 378 * 27)}
 
 CSRC = os.path.join(ROOT, "paper_1911_07913_amd", "csrc")
-# committed PMC summaries: per-launch HBM traffic of a kernel, valid while the
-# sources it was measured on are unchanged
-TRAFFIC = {
-    "assemble_h0": ("assemble_h0_twisting_bars_1p5M_fp64_pmc.md",
-                    ["particles.hip", "mpm_math.h", "hot_internal.h"]),
-    "smooth0": ("vcycle_level0_twisting_bars_1p5M_fp64_pmc.md",
-                ["matrix.hip", "mpm_math.h", "hot_internal.h"]),
-    "residual0": ("vcycle_level0_twisting_bars_1p5M_fp64_pmc.md",
-                  ["matrix.hip", "mpm_math.h", "hot_internal.h"]),
-}
+# committed PMC summaries: per-launch HBM traffic of a kernel in the precision
+# it was measured in, valid while the sources it was measured on are unchanged
+_ASM_SRC = ["particles.hip", "mpm_math.h", "hot_internal.h"]
+_SWEEP_SRC = ["matrix.hip", "mpm_math.h", "hot_internal.h"]
+TRAFFIC = {(k, prec): (f"{stem}_twisting_bars_1p5M_{prec}_pmc.md", src)
+           for prec in ("fp64", "mixed")
+           for k, stem, src in (("assemble_h0", "assemble_h0", _ASM_SRC),
+                                ("smooth0", "vcycle_level0", _SWEEP_SRC),
+                                ("residual0", "vcycle_level0", _SWEEP_SRC))}
 
 # CPU-baseline sample: same scene family, 4 bars of 24x6x6 cells
 SAMPLE = dict(side=6, length=24)
@@ -183,13 +182,13 @@ def source_hash(files):
     return h.hexdigest()
 
 
-def traffic_of(kernel):
+def traffic_of(kernel, precision):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from
-    the committed PMC summary, or None when there is none or the kernel's
-    sources changed since it was taken."""
-    if kernel not in TRAFFIC:
+    the committed PMC summary, or None when there is none for this kernel in
+    this precision or the kernel's sources changed since it was taken."""
+    if (kernel, precision) not in TRAFFIC:
         return None
-    fname, files = TRAFFIC[kernel]
+    fname, files = TRAFFIC[(kernel, precision)]
     path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
@@ -205,13 +204,13 @@ def traffic_of(kernel):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def roofline_of(prof, n_particles):
+def roofline_of(prof, n_particles, precision):
     """Roofline of the dominant traced kernel (largest summed launch time)."""
     name, (ms, launches, nbytes) = max(prof.items(), key=lambda kv: kv[1][0])
     if launches == 0:
         return None
     avg_s = ms * 1e-3 / launches
-    traffic = traffic_of(name)
+    traffic = traffic_of(name, precision)
     if BOUND[name] == "alu":
         flops = FLOP_PER_PARTICLE[name] * n_particles
         achieved = flops / avg_s / 1e12
@@ -227,7 +226,7 @@ def roofline_of(prof, n_particles):
             "algorithmic_bytes_per_launch": nbytes / launches}
 
 
-def vcycle_roofline(prof):
+def vcycle_roofline(prof, precision):
     """HBM roofline of the level-0 V-cycle passes (smoothing, Gauss-Seidel or
     Jacobi, and the residual), the bandwidth-bound kernels each quasi-Newton
     iteration repeats."""
@@ -244,11 +243,11 @@ def vcycle_roofline(prof):
         t, n, b = prof[k]
         out[k] = {"avg_launch_ms": t / n if n else None,
                   "algorithmic_bytes_per_launch": b / n if n else None,
-                  "traffic": traffic_of(k)}
+                  "traffic": traffic_of(k, precision)}
     return out
 
 
-def smoother_summary(r, steps):
+def smoother_summary(r, steps, precision):
     """The same job with the paper's coloured symmetric Gauss-Seidel smoother:
     rate, iteration counts and the level-0 V-cycle passes' algorithmic
     bandwidth."""
@@ -256,8 +255,8 @@ def smoother_summary(r, steps):
             "ms_per_step": 1000.0 * r["seconds"] / steps,
             "iters": [s["iters"] for s in r["stats"]],
             "cg_iters": [s["cg_iters_total"] for s in r["stats"]],
-            "roofline": roofline_of(r["prof"], r["n"]),
-            "vcycle_roofline": vcycle_roofline(r["prof"])}
+            "roofline": roofline_of(r["prof"], r["n"], precision),
+            "vcycle_roofline": vcycle_roofline(r["prof"], precision)}
 
 
 def calibrate_copy(nbytes=1 << 30):
@@ -310,6 +309,10 @@ def main():
     from paper_1911_07913_amd import hot
     hot.lib()
     assert torch.cuda.is_available(), "no HIP device"
+
+    def prec_name(p):
+        return "fp64" if p == hot.HOT_FP64 else "mixed"
+
     torch.cuda.set_device(0)
     if a.calibrate_copy:
         calibrate_copy()
@@ -339,10 +342,10 @@ def main():
         "config": {"workload": workload_name(a.side, "l1 block-Jacobi" if a.smoother == "l1jacobi"
                                              else "coloured symmetric Gauss-Seidel"),
                    "particles": r["n"],
-                   "precision": "fp64" if main_p == hot.HOT_FP64 else "mixed",
+                   "precision": prec_name(main_p),
                    "smoother": a.smoother},
-        "roofline": roofline_of(r["prof"], r["n"]),
-        "vcycle_roofline": vcycle_roofline(r["prof"]),
+        "roofline": roofline_of(r["prof"], r["n"], prec_name(main_p)),
+        "vcycle_roofline": vcycle_roofline(r["prof"], prec_name(main_p)),
         "per_step": {
             "iters": [s["iters"] for s in stats],
             "cg_iters": [s["cg_iters_total"] for s in stats],
@@ -363,13 +366,13 @@ def main():
         line["mixed"] = {"value": a.steps / rm["seconds"], "unit": "steps/s",
                          "ms_per_step": 1000.0 * rm["seconds"] / a.steps,
                          "iters": [s["iters"] for s in rm["stats"]],
-                         "roofline": roofline_of(rm["prof"], rm["n"]),
-                         "vcycle_roofline": vcycle_roofline(rm["prof"])}
+                         "roofline": roofline_of(rm["prof"], rm["n"], "mixed"),
+                         "vcycle_roofline": vcycle_roofline(rm["prof"], "mixed")}
     if not a.no_sgs:
         line["smoother_sgs"] = {
-            ("fp64" if p == hot.HOT_FP64 else "mixed"):
+            prec_name(p):
             smoother_summary(run(p, a.steps, a.warmup, a.side,
-                                 smoother=hot.HOT_SMOOTH_SGS), a.steps)
+                                 smoother=hot.HOT_SMOOTH_SGS), a.steps, prec_name(p))
             for p in precs}
     if not a.no_slab:
         # the larger configuration: 8,192,000 particles, 30 steps, both precisions

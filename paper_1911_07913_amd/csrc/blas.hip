@@ -205,14 +205,30 @@ __global__ void k_twoloop_start(long long n, const double* __restrict__ init, do
 //   first loop  (alpha_in NULL): alpha = rho d,  v <- v - alpha x, alpha stored;
 //   second loop:                 coef = alpha_in - rho d,  v <- v + coef x,
 // and writes the block partials of dnext . v (if dnext is given) to partial.
-// prev and partial must be different buffers.
+// prev and partial must be different buffers.  A thread's first kPre terms
+// are loaded before the finishing sum, so that their latency overlaps it; the
+// arithmetic and its order are those of the plain grid-stride loop.
 __global__ void k_twoloop_step(long long n, int nparts, const double* __restrict__ prev,
                                const double* __restrict__ rho, const double* __restrict__ alpha_in,
                                double* __restrict__ alpha_out, const double* __restrict__ x,
                                double* __restrict__ v, const double* __restrict__ dnext,
                                double* __restrict__ partial) {
+  constexpr int kPre = 4;
   __shared__ double sh[kTpb / 64];
   __shared__ double coef;
+  const long long k0 = (long long)blockIdx.x * kTpb + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kTpb;
+  double pv[kPre], px[kPre], pd[kPre];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const long long k = k0 + j * stride;
+    pv[j] = px[j] = pd[j] = 0.0;
+    if (k < n) {
+      pv[j] = v[k];
+      px[j] = x[k];
+      if (dnext) pd[j] = dnext[k];
+    }
+  }
   const double d = finish_sum(nparts, prev, sh);
   if (threadIdx.x == 0) {
     const double rd = rho[0] * d;
@@ -226,7 +242,17 @@ __global__ void k_twoloop_step(long long n, int nparts, const double* __restrict
   __syncthreads();
   const double al = coef;
   double acc = 0.0;
-  for (long long k = (long long)blockIdx.x * kTpb + threadIdx.x; k < n; k += (long long)gridDim.x * kTpb) {
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const long long k = k0 + j * stride;
+    if (k < n) {
+      double val = pv[j];
+      val = val + al * px[j];
+      v[k] = val;
+      if (dnext) acc += pd[j] * val;
+    }
+  }
+  for (long long k = k0 + kPre * stride; k < n; k += stride) {
     double val = v[k];
     val = val + al * x[k];
     v[k] = val;
