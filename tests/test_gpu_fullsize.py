@@ -10,7 +10,9 @@ they hold every particle of i's stencil and every particle of the stencils
 of those particles' nodes), so the oracle's value is exact for the full
 scene:  node mass, v*, CN stiffness, the gradient at dv = 0 and the whole
 125-block row of the level-0 Hessian.  Finally one full step at this size
-must converge with a decreasing incremental potential.
+must converge with a decreasing incremental potential, and its
+grid-to-particle transfer must conserve momentum against the grid's own
+final velocities and advance positions by dt times the new velocity.
 """
 import math
 
@@ -109,17 +111,35 @@ def test_sampled_nodes_p2g_gradient_and_hessian_rows(full):
 
 
 def test_full_size_step_converges_and_decreases_energy():
+    """One full step converges with a decreasing incremental potential, and
+    its grid-to-particle transfer keeps the properties that hold at any size
+    (Sec. 3): the B-spline weights sum to one and the node masses are the
+    particles' weighted masses, so the particles' total momentum equals the
+    grid's, sum_i m_i (v*_i + dv_i); positions advance by dt times the new
+    particle velocity."""
     hot = _hot()
     sc = hs.twisting_bars(side=16)
     g = hot.Scene.from_scene(sc)
     try:
         status = g.step()
         st = g.stats
+        out = g.read(F=False, Cm=False)
+        m_i = g.debug_read(hot.DBG_NODE_MASS)
+        v_i = g.debug_read(hot.DBG_NODE_VSTAR).reshape(-1, 3) + g.debug_read(hot.DBG_DV).reshape(-1, 3)
     finally:
         g.close()
     assert status == 0 and st["converged"]
     assert st["E"] < st["E0"]
     assert st["cn"] <= st["cn_tol"] < st["cn0"]
+    dens = np.array([mt["density"] for mt in sc.materials])
+    m_p = dens[sc.mat_id] * sc.vol0
+    p_particles = m_p @ out["v"]
+    p_grid = m_i @ v_i
+    scale = float(m_p @ np.linalg.norm(out["v"], axis=1))
+    assert np.max(np.abs(p_particles - p_grid)) <= 1e-11 * scale
+    assert abs(m_i.sum() - m_p.sum()) <= 1e-12 * m_p.sum()
+    xs = float(np.abs(sc.x).max())
+    assert np.max(np.abs(out["x"] - (sc.x + st["dt"] * out["v"]))) <= 4e-16 * xs
 
 
 def test_sphere_slab_full_size_mixed():
