@@ -1596,8 +1596,12 @@ struct hot_batch {
 extern "C" {
 
 hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out) {
-  if (!out || max_slots < 1 || max_slots > 256 || hbm_budget_bytes == 0)
-    return fail(HOT_E_INVALID, "bad arguments");
+  // A coarsest-level solve with grid barriers launches at most 1/16 of the
+  // device's resident work-groups, so 16 scenes stepping at once still have
+  // every work-group of every such solve resident; more slots could leave a
+  // solve spinning on work-groups that never start.
+  if (!out || max_slots < 1 || max_slots > 16 || hbm_budget_bytes == 0)
+    return fail(HOT_E_INVALID, "bad arguments (max_slots must be in [1, 16])");
   hot_batch* b = new hot_batch();
   b->budget = hbm_budget_bytes;
   b->t0 = hot_batch::clock::now();
