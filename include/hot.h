@@ -283,6 +283,16 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
 /* Run the step up to and including the Galerkin hierarchy (no solve, no G2P,
  * particle state unchanged) with time step dt (<= 0: CFL rule). */
 hot_status hot_debug_prepare(hot_scene* scene, double dt);
+/* Process-wide settings for tests, applied to launches issued after the call.
+ * HOT_SET_MULTIROW_MIN: level size (rows) from which the FP64 smoothing and
+ *   residual sweeps of the V-cycle process two rows per wave instead of one
+ *   (default 65536; a negative value restores the default).  Both forms
+ *   compute every row with the same per-lane arithmetic, so a test can run
+ *   either one on any level.
+ * *previous (nullable) receives the old value; an unknown key is
+ * HOT_E_INVALID. */
+enum { HOT_SET_MULTIROW_MIN = 1 };
+hot_status hot_debug_set(int32_t key, int64_t value, int64_t* previous);
 /* After hot_debug_prepare: apply an operator to a host vector of n_0*3
  * doubles.  op 0: one V-cycle; op 1: gradient at dv = in; op 2: energy at
  * dv = in (out[0]); op 3: level-0 matrix product. */

@@ -1389,6 +1389,14 @@ hot_status hot_debug_prepare(hot_scene* scene, double dt) {
   return HOT_OK;
 }
 
+hot_status hot_debug_set(int32_t key, int64_t value, int64_t* previous) {
+  if (key != HOT_SET_MULTIROW_MIN) return fail(HOT_E_INVALID, "unknown setting %d", key);
+  if (value > INT32_MAX) return fail(HOT_E_INVALID, "value out of range");
+  int old = set_multirow_min(value < 0 ? -1 : (int)value);
+  if (previous) *previous = old;
+  return HOT_OK;
+}
+
 hot_status hot_debug_apply(hot_scene* scene, int32_t op, const double* in, double* out) {
   if (!scene || !in || !out) return fail(HOT_E_INVALID, "NULL argument");
   hot_scene* s = scene;

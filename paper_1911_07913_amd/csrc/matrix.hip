@@ -7,6 +7,8 @@
 // reduced with shuffles.
 // The FP64 path stores blocks as double; the mixed path stores BF16 blocks and
 // runs the V-cycle vectors and accumulation in FP32.
+#include <atomic>
+
 #include "mpm_math.h"
 
 namespace hot {
@@ -1360,8 +1362,11 @@ void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u,
   else
     k_jacobi_first<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double*)b, (double4*)u);
 }
-// Levels with at least this many rows run several rows per wave.
-constexpr int kMultiRowMin = 65536;
+// Levels with at least this many rows run several rows per wave (FP64:
+// SweepRows<double>::R).  Held in a process-wide variable so that a test can
+// move the threshold and run either form of the sweep on any level.
+constexpr int kMultiRowMinDefault = 65536;
+static std::atomic<int> g_multirow_min{kMultiRowMinDefault};
 
 template <typename V>
 void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, void* out,
@@ -1369,7 +1374,7 @@ void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, vo
   typedef typename Vec4Of<V>::type V4;
   constexpr int R = SweepRows<V>::R;
   const V4* u4 = (const V4*)u;
-  if (L.n >= kMultiRowMin) {
+  if (L.n >= g_multirow_min.load(std::memory_order_relaxed)) {
     unsigned g = (unsigned)((L.n + kRowWaves * R - 1) / (kRowWaves * R));
     if (smooth)
       k_smooth<V, R><<<g, 256, 0, st>>>(L, b, u4, (V4*)out);
@@ -1382,6 +1387,10 @@ void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, vo
     else
       k_residual<V, 1><<<g, 256, 0, st>>>(L, b, u4, (V*)out);
   }
+}
+
+int set_multirow_min(int rows) {
+  return g_multirow_min.exchange(rows < 0 ? kMultiRowMinDefault : rows);
 }
 
 void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,

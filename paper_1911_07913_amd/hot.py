@@ -40,12 +40,13 @@ DBG_DV = 30
 DBG_LOG_INT = 40
 DBG_LOG_CN = 41
 DBG_COUNTS = 50
+SET_MULTIROW_MIN = 1
 
 EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_particles",
            "hot_scene_info", "hot_scene_memory", "hot_destroy_scene", "hot_last_error",
            "hot_batch_create", "hot_batch_capacity", "hot_batch_add", "hot_batch_poll",
            "hot_batch_clock", "hot_batch_destroy", "hot_debug_read", "hot_debug_prepare",
-           "hot_debug_apply", "hot_profile_enable", "hot_profile_read"]
+           "hot_debug_apply", "hot_debug_set", "hot_profile_enable", "hot_profile_read"]
 
 BATCH_MAX_STEPS = 64
 
@@ -140,6 +141,7 @@ def lib():
     L.hot_debug_read.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.hot_debug_prepare.argtypes = [vp, C.c_double]
     L.hot_debug_apply.argtypes = [vp, C.c_int32, dp, dp]
+    L.hot_debug_set.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_int64)]
     L.hot_profile_enable.argtypes = [vp, C.c_int32]
     L.hot_profile_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), dp]
     for name in EXPORTS:
@@ -399,3 +401,10 @@ class Batch:
         if self.handle:
             lib().hot_batch_destroy(self.handle)
             self.handle = None
+
+
+def debug_set(key, value):
+    """Process-wide test setting (hot_debug_set); returns the previous value."""
+    prev = C.c_int64()
+    _check(lib().hot_debug_set(key, int(value), C.byref(prev)))
+    return prev.value

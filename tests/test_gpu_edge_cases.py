@@ -125,16 +125,14 @@ def test_degenerate_step_fp64(name, smoother):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_degenerate_step_mixed(name):
-    """Mixed precision (BF16 blocks, FP32 V-cycle) on the same inputs, held
-    to the bar of reading R23: its distance to a tightly converged step
-    (the oracle at 1e-10) is at most twice the FP64 step's, or 1e-6."""
+    """Mixed precision (BF16 blocks, FP32 V-cycle) on the same inputs against
+    the FP64 oracle at the same CN tolerance, eps = 1e-10, where every case
+    converges with the default smoother: x and v within 1e-6 relative."""
     hot = _hot()
     sc = CASES[name]()
+    sc.tol = 1e-10
     dt = O.time_step(sc)
-    out, info = O.step(sc, dt=dt)
-    tight = CASES[name]()
-    tight.tol = 1e-10
-    ref, rinfo = O.step(tight, dt=dt)
+    ref, rinfo = O.step(sc, dt=dt)
     g = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
     try:
         status = g.step(dt)
@@ -142,10 +140,8 @@ def test_degenerate_step_mixed(name):
         stats = dict(g.stats)
     finally:
         g.close()
-    tx, tv = rel(out.x, ref.x), rel(out.v, ref.v)
-    mx, mv = rel(res["x"], ref.x), rel(res["v"], ref.v)
-    print(f"{name}: iterations mixed {stats['iters']}, fp64 {info['iters']}, tight {rinfo['iters']}; "
-          f"to the tight step: fp64 x {tx:.2e} v {tv:.2e}, mixed x {mx:.2e} v {mv:.2e}")
+    mx, mv, mF = rel(res["x"], ref.x), rel(res["v"], ref.v), rel(res["F"], ref.F)
+    print(f"{name} eps=1e-10: iterations mixed {stats['iters']}, fp64 {rinfo['iters']}; "
+          f"mixed vs fp64 oracle: x {mx:.2e} v {mv:.2e} F {mF:.2e}")
     assert status == 0 and stats["converged"] and rinfo["converged"]
-    assert mx <= max(1e-6, 2.0 * tx)
-    assert mv <= max(1e-6, 2.0 * tv)
+    assert mx <= 1e-6 and mv <= 1e-6 and mF <= 1e-6

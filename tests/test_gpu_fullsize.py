@@ -179,3 +179,36 @@ def test_sphere_slab_full_size_mixed():
     eps = np.log(s)
     nd = np.linalg.norm(eps - eps.mean(axis=1, keepdims=True), axis=1)
     assert np.all(nd <= lim * (1.0 + 1e-9))
+
+
+def test_two_rows_per_wave_sweeps_bit_identical_at_full_size(full):
+    """Level 0 of this scene (281,580 rows) runs the FP64 sweeps two rows per
+    wave.  The same V-cycle with one row per wave on every level (the form
+    that the oracle-compared small scenes run by default) is bit-identical,
+    and so is a whole step."""
+    hot = _hot()
+    sc, dt, g = full
+    n = g.debug_read(hot.DBG_LEVEL_NODES, 0, dtype=np.int32).size
+    b = np.random.Generator(np.random.PCG64(12)).normal(size=3 * n)
+    b *= g.debug_read(hot.DBG_LEVEL_FREE, 0, dtype=np.uint8).astype(float)
+    u2 = g.debug_apply(0, b)
+    try:
+        hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30)
+        u1 = g.debug_apply(0, b)
+    finally:
+        hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+    assert np.array_equal(u1, u2)
+    outs = []
+    for forced in (None, 1 << 30):
+        s = hot.Scene.from_scene(sc)
+        try:
+            if forced is not None:
+                hot.debug_set(hot.SET_MULTIROW_MIN, forced)
+            s.step()
+            outs.append((s.read(F=False, Cm=False), dict(s.stats)))
+        finally:
+            hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+            s.close()
+    (a, sa), (c, sc1) = outs
+    assert sa["iters"] == sc1["iters"] and sa["cg_iters_total"] == sc1["cg_iters_total"]
+    assert np.array_equal(a["x"], c["x"]) and np.array_equal(a["v"], c["v"])

@@ -129,12 +129,22 @@ def test_gradient_energy_and_vcycle(prepared):
     assert rel(ug, uo) < 1e-11
 
 
+def assert_dt_matches(stats_dt, sc):
+    """The library's own time step (hot_step with dt <= 0: CFL 0.6 on the
+    largest particle or prescribed boundary speed, capped at 1/24 s) equals
+    the oracle's, up to the rounding of the speed norm."""
+    want = O.time_step(sc)
+    assert abs(stats_dt - want) <= 4 * np.spacing(want), (stats_dt, want)
+
+
 def _compare_step(sc, precision=0, tol_x=1e-10, tol_v=1e-10):
+    """One step on both sides; the library picks its own time step."""
     hot = _hot()
     dt = O.time_step(sc)
     out, info = O.step(sc, dt=dt)
     g = hot.Scene.from_scene(sc, precision=precision)
-    st = g.step(dt)
+    st = g.step(0.0)
+    assert_dt_matches(g.stats["dt"], sc)
     res = g.read()
     logi = g.debug_read(hot.DBG_LOG_INT, dtype=np.int32).reshape(-1, 4)
     cn = g.debug_read(hot.DBG_LOG_CN)
@@ -142,8 +152,37 @@ def _compare_step(sc, precision=0, tol_x=1e-10, tol_v=1e-10):
     return out, info, res, logi, cn, st, g.stats
 
 
+@pytest.fixture(params=["one_row", "two_rows"])
+def rows_per_wave(request):
+    """Run the FP64 smoothing and residual sweeps with one row per wave on
+    every level ("one_row"), or with the two-rows-per-wave form that large
+    levels use, forced onto every level ("two_rows")."""
+    hot = _hot()
+    hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30 if request.param == "one_row" else 0)
+    yield request.param
+    hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+
+
+def test_vcycle_two_rows_per_wave(prepared):
+    """The two-rows-per-wave sweeps give the one-row V-cycle bit for bit, and
+    so match the oracle's V-cycle."""
+    hot = _hot()
+    name, sc, dt, st, hz, g = prepared
+    n = st.lev0.n
+    b = np.random.Generator(np.random.PCG64(8)).normal(size=3 * n) * hz.free[0]
+    try:
+        hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30)
+        u1 = g.debug_apply(0, b)
+        hot.debug_set(hot.SET_MULTIROW_MIN, 0)
+        u2 = g.debug_apply(0, b)
+    finally:
+        hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+    assert np.array_equal(u1, u2)
+    assert rel(u2, O.vcycle(hz, b)) < 1e-11
+
+
 @pytest.mark.parametrize("name", list(SCENES))
-def test_full_step_fp64(name):
+def test_full_step_fp64(name, rows_per_wave):
     sc = _grip_scene() if name == "bars_small_grips" else SCENES[name]()
     out, info, res, logi, cn, status, stats = _compare_step(sc)
     log = info["log"]

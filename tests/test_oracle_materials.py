@@ -141,3 +141,38 @@ def test_cn_stiffness_closed_form():
     for model in (0, 1):
         A, _, _, _ = O.diag_space(np.ones((2, 3)), np.full(2, model), mu, lam)
         assert np.allclose(np.linalg.norm(A, axis=(1, 2)), O.cn_xi(mu, lam), rtol=1e-14)
+
+
+# ---- Lame parameters, pinned by elasticity relations that do not restate
+# the conversion: the bulk modulus and the inverse conversions, and the
+# small-strain response of both energy densities to a uniaxial stress state.
+
+LAME_CASES = [(1e4, 0.2), (1e5, 0.3), (3e6, 0.4), (1e8, 0.45), (2e5, -0.3)]
+
+
+@pytest.mark.parametrize("E,nu", LAME_CASES)
+def test_lame_against_moduli_relations(E, nu):
+    mu, lam = (float(a) for a in O.lame(E, nu))
+    # bulk modulus: lambda + 2 mu / 3 = E / (3 (1 - 2 nu))
+    assert abs((lam + 2.0 * mu / 3.0) - E / (3.0 * (1.0 - 2.0 * nu))) <= 1e-13 * E / (1 - 2 * nu)
+    # the inverse relations give back E and nu
+    assert abs(mu * (3.0 * lam + 2.0 * mu) / (lam + mu) - E) <= 1e-13 * E
+    assert abs(lam / (2.0 * (lam + mu)) - nu) <= 1e-13
+    # P-wave modulus lambda + 2 mu = E (1 - nu) / ((1 + nu)(1 - 2 nu))
+    assert abs((lam + 2.0 * mu) - E * (1 - nu) / ((1 + nu) * (1 - 2 * nu))) <= 1e-13 * E * 10
+
+
+@pytest.mark.parametrize("model,_", MODELS)
+@pytest.mark.parametrize("E,nu", LAME_CASES[:4])
+def test_uniaxial_stress_gives_youngs_modulus_and_poisson_ratio(model, _, E, nu):
+    """A bar stretched by a small strain e along x and contracted by nu e
+    across carries, to first order, stress E e along x and no stress across
+    (the definition of E and nu).  Both energy densities reduce to linear
+    elasticity at small strain, so their P (through O.lame) must show it."""
+    e = 1e-7
+    F = np.diag([1.0 + e, 1.0 - nu * e, 1.0 - nu * e])[None]
+    mu, lam = O.lame(np.array([E]), np.array([nu]))
+    P = O.piola(F, np.array([model], dtype=np.int32), mu, lam)[0]
+    assert abs(P[0, 0] - E * e) <= 1e-5 * E * e
+    assert abs(P[1, 1]) <= 1e-5 * E * e and abs(P[2, 2]) <= 1e-5 * E * e
+    assert np.abs(P - np.diag(np.diag(P))).max() <= 1e-9 * E * e

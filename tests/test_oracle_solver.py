@@ -274,3 +274,43 @@ def test_snow_clamp():
     R *= np.sign(np.linalg.det(R))
     assert np.abs(O.snow_clamp(R @ F, clamp) - R @ Fc).max() < 1e-13
     assert np.array_equal(O.snow_clamp(F, np.zeros((n, 2))), F)
+
+
+# ---- gravity (applied to the grid velocity before the solve, v* = v + dt g)
+
+def test_gravity_free_fall_of_unstressed_translating_body():
+    """A body at rest shape (F = I) translating uniformly, with no walls,
+    stays unstressed: the grid velocity field is uniform, so no deformation
+    arises, dv = 0 is the minimiser, and grid-to-particle transfer returns
+    every particle's velocity plus dt g exactly (up to rounding), with the
+    positions advanced by dt times that velocity."""
+    g = np.array([0.7, -9.8, 1.3])
+    sc = hs.small_box(seed=61, cells=(10, 10, 10), box_lo=(3, 3, 3), box_hi=(7, 6, 7),
+                      walls=None, omega=(0.0, 0.0, 0.0), noise=0.0, gravity=tuple(g), E=5e4)
+    v0 = np.array([0.4, 0.1, -0.25])
+    sc.v[:] = v0
+    dt = 5e-3
+    out, info = O.step(sc, dt=dt)
+    assert info["converged"]
+    assert np.abs(out.v - (v0 + dt * g)).max() <= 1e-13
+    assert np.abs(out.x - (sc.x + dt * out.v)).max() <= 1e-15
+    assert np.abs(out.F - np.eye(3)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_gravity_momentum_balance_of_converged_step(model):
+    """Internal forces sum to zero (translation invariance), so without walls
+    the particles' total momentum grows by exactly dt M g over one converged
+    step, whatever the stress state; the residual left by the CN tolerance
+    bounds the mismatch."""
+    g = np.array([0.0, -9.8, 2.0])
+    sc = tiny(63, model=model, walls=None, gravity=tuple(g))
+    sc.tol = 1e-11
+    dens = np.array([m["density"] for m in sc.materials])
+    mp = dens[sc.mat_id] * sc.vol0
+    dt = 4e-3
+    out, info = O.step(sc, dt=dt)
+    assert info["converged"]
+    dp = mp @ out.v - mp @ sc.v
+    want = dt * mp.sum() * g
+    assert np.abs(dp - want).max() <= 1e-9 * np.abs(want).max()
