@@ -190,6 +190,34 @@ const char* hot_last_error(void);
  * init (the hot_scene_footprint figure). */
 hot_status hot_scene_memory(const hot_scene* scene, size_t* live_bytes, size_t* estimate_bytes);
 
+/* ---- stepping without device allocation ----------------------------------
+ * For callers that cannot allocate device memory where they step: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and status codes as hot_step (bit-identical
+ * output), but the call makes no hipMalloc or hipFree and calls no
+ * allocating library routine:
+ *   - the scene's own buffers (particles, grids, hierarchy, solver vectors)
+ *     must already be large enough, as sized by hot_init_scene and earlier
+ *     hot_step calls (which keep 25% headroom).  A step that would need one
+ *     to grow (a scene's first step, or more active nodes than any earlier
+ *     step had) returns HOT_E_NOMEM before writing past it; the particle
+ *     state and scene time are unchanged, and a hot_step call sizes the
+ *     buffers;
+ *   - the per-call scratch (reduction partial sums, the scalar block, an
+ *     error flag, the coarsest-level PCG vectors, grid barrier and
+ *     iteration counts) comes from one fixed 1 MiB device array per GPU,
+ *     held from the first call on that GPU until the process ends.  A step
+ *     whose coarsest level needs more (above about 6,700 rows), or whose
+ *     max_iters needs more PCG counters than fit, is refused with
+ *     HOT_E_INVALID and a message naming the size;
+ *   - every call on one GPU shares that array, which keeps the last call's
+ *     contents; each call writes every scratch value before reading it.
+ *     Calls that overlap in time on one GPU (several host threads, or
+ *     several streams) race on the array and must be serialised by the
+ *     caller;
+ *   - kernel tracing (hot_profile_enable) must be off: HOT_E_INVALID. */
+hot_status hot_step_noalloc(hot_scene* scene, double dt, hot_step_stats* stats);
+
 /* ---- serving: continuous batching of independent scenes ------------------
  * Steps of many independent scenes (the paper's per-frame solve applied to
  * a stream of requests) share one GPU.  A batch owns an HBM budget and

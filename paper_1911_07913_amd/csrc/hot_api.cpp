@@ -62,6 +62,7 @@ void default_free(void* p, void*) {
 struct DBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool borrowed = false;  // a range of the no-allocation scratch array: never freed or grown
 };
 
 enum {
@@ -133,6 +134,7 @@ struct hot_scene {
   double* hscal = nullptr;
   int* herr = nullptr;
   int node_cap = 0;
+  bool no_alloc = false;  // inside hot_step_noalloc: a buffer that must grow is an error
   // last-step logs
   std::vector<int> log_int;
   std::vector<double> log_cn;
@@ -155,6 +157,16 @@ namespace {
 hot_status ensure(hot_scene* s, DBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (b.cap >= bytes) return HOT_OK;
+  if (b.borrowed)
+    return fail(HOT_E_INVALID,
+                "the step needs %zu bytes of per-call scratch here, more than the %zu the "
+                "no-allocation entry point holds",
+                bytes, b.cap);
+  if (s->no_alloc)
+    return fail(HOT_E_NOMEM,
+                "hot_step_noalloc: a %zu-byte scene buffer would have to grow to %zu bytes "
+                "(hot_step sizes it)",
+                b.cap, bytes);
   if (b.p) {
     // keep the stream ordered: free only after pending work completes
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(HOT_E_DEVICE, "sync failed");
@@ -177,7 +189,7 @@ T* P(const DBuf& b) {
 }
 
 void release(hot_scene* s, DBuf& b) {
-  if (b.p) s->alloc.free(b.p, s->alloc.ctx);
+  if (b.p && !b.borrowed) s->alloc.free(b.p, s->alloc.ctx);
   b.p = nullptr;
   b.cap = 0;
 }
@@ -1355,6 +1367,95 @@ hot_status hot_scene_memory(const hot_scene* scene, size_t* live_bytes, size_t* 
 }
 
 void hot_destroy_scene(hot_scene* scene) { destroy(scene); }
+
+// ---------------------------------------------------------------- stepping without allocation
+}  // extern "C"
+
+// Per-call scratch of hot_step_noalloc, one fixed array per device: the
+// reduction partial sums, the scalar block, the error flag, the coarse-PCG
+// iteration counts and the coarsest-level PCG vectors and grid barrier.
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of device `dev`'s copy of `scratch` (in host code the
+// array's name is only a stand-in), looked up once per device with that
+// device current.
+hot_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HOT_E_DEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(HOT_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HOT_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// For its lifetime, the scene's per-call buffers are ranges of the scratch
+// array and no scene buffer may grow.
+class BorrowScratch {
+ public:
+  BorrowScratch(hot_scene* s, unsigned char* base, size_t iters_bytes) : s_(s) {
+    DBuf* bufs[kN] = {&s->dscal, &s->err, &s->partial, &s->pcg_iters, &s->pcg_work};
+    const size_t part = round256((size_t)kRedBlocks * 4 * 8);
+    const size_t off[kN] = {0, 256, 512, 512 + part, 512 + part + iters_bytes};
+    const size_t cap[kN] = {256, 256, part, iters_bytes,
+                            kNoAllocScratchBytes - (512 + part + iters_bytes)};
+    for (int k = 0; k < kN; ++k) {
+      bufs_[k] = bufs[k];
+      saved_[k] = *bufs[k];
+      bufs[k]->p = base + off[k];
+      bufs[k]->cap = cap[k];
+      bufs[k]->borrowed = true;
+    }
+    s->no_alloc = true;
+  }
+  ~BorrowScratch() {
+    for (int k = 0; k < kN; ++k) *bufs_[k] = saved_[k];
+    s_->no_alloc = false;
+  }
+  static size_t fixed_bytes() { return 512 + round256((size_t)kRedBlocks * 4 * 8); }
+
+ private:
+  static constexpr int kN = 5;
+  hot_scene* s_;
+  DBuf* bufs_[kN];
+  DBuf saved_[kN];
+};
+
+}  // namespace
+
+extern "C" {
+
+hot_status hot_step_noalloc(hot_scene* scene, double dt, hot_step_stats* stats) {
+  if (!scene) return fail(HOT_E_INVALID, "scene is NULL");
+  if (!std::isfinite(dt)) return fail(HOT_E_INVALID, "dt must be finite");
+  if (scene->prof)
+    return fail(HOT_E_INVALID, "hot_step_noalloc: kernel tracing creates events; disable it");
+  HIPCHK(hipSetDevice(scene->device));
+  unsigned char* base = nullptr;
+  TRY(scratch_address(scene->device, &base));
+  // one coarse-PCG count per V-cycle (at most 3 per iteration)
+  const size_t iters = round256(((size_t)scene->prm.max_iters * 3 + 16) * 4);
+  if (BorrowScratch::fixed_bytes() + iters + 4096 > kNoAllocScratchBytes)
+    return fail(HOT_E_INVALID,
+                "hot_step_noalloc: max_iters = %d needs %zu bytes of counters; the scratch "
+                "holds %zu bytes in all",
+                scene->prm.max_iters, iters, kNoAllocScratchBytes);
+  BorrowScratch borrow(scene, base, iters);
+  return do_step(scene, dt, stats);
+}
 
 // ---------------------------------------------------------------- tracing
 hot_status hot_profile_enable(hot_scene* scene, int32_t enable) {

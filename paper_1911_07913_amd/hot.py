@@ -46,7 +46,8 @@ EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_partic
            "hot_scene_info", "hot_scene_memory", "hot_destroy_scene", "hot_last_error",
            "hot_batch_create", "hot_batch_capacity", "hot_batch_add", "hot_batch_poll",
            "hot_batch_clock", "hot_batch_destroy", "hot_debug_read", "hot_debug_prepare",
-           "hot_debug_apply", "hot_debug_set", "hot_profile_enable", "hot_profile_read"]
+           "hot_debug_apply", "hot_debug_set", "hot_profile_enable", "hot_profile_read",
+           "hot_step_noalloc"]
 
 BATCH_MAX_STEPS = 64
 
@@ -123,6 +124,7 @@ def lib():
                                  C.POINTER(hot_material), C.c_int32, C.POINTER(hot_bc), C.c_int32,
                                  C.POINTER(hot_allocator), vp, C.POINTER(vp)]
     L.hot_step.argtypes = [vp, C.c_double, C.POINTER(hot_step_stats)]
+    L.hot_step_noalloc.argtypes = [vp, C.c_double, C.POINTER(hot_step_stats)]
     L.hot_read_particles.argtypes = [vp, C.c_int64, dp, dp, dp, dp]
     L.hot_scene_info.argtypes = [vp, C.POINTER(C.c_int64), dp]
     L.hot_destroy_scene.argtypes = [vp]
@@ -279,6 +281,15 @@ class Scene:
         """hot_step; returns the status (0 or HOT_W_NOT_CONVERGED) and keeps the stats."""
         s = hot_step_stats()
         st = _check(lib().hot_step(self.handle, dt, C.byref(s)))
+        self.stats = s.as_dict()
+        return st
+
+    def step_noalloc(self, dt=0.0):
+        """hot_step_noalloc: hot_step without device allocation (the scene's
+        buffers must already be sized; per-call scratch from the library's
+        fixed device array)."""
+        s = hot_step_stats()
+        st = _check(lib().hot_step_noalloc(self.handle, dt, C.byref(s)))
         self.stats = s.as_dict()
         return st
 
