@@ -39,6 +39,8 @@ FP64_PEAK_TFLOPS = 78.6
 # (378 x 27 FMA): 12,636 FMA = 25,272 flop.
 BOUND = {"smooth0": "hbm", "residual0": "hbm", "sgs0": "hbm", "rap0": "hbm", "particle_eval": "hbm",
          "gradient": "hbm", "assemble_h0": "alu", "particle_hessian": "alu"}
+# traced spans that hold several kernels (not candidates for the dominant kernel)
+COMPOSITE = {"vcycle"}
 FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 9 + 27 * 81 + 378 * 27)}
 
 CSRC = os.path.join(ROOT, "paper_1911_07913_amd", "csrc")
@@ -52,8 +54,11 @@ TRAFFIC = {(k, prec): (f"{stem}_twisting_bars_1p5M_{prec}_pmc.md", src)
                                 ("smooth0", "vcycle_level0", _SWEEP_SRC),
                                 ("residual0", "vcycle_level0", _SWEEP_SRC))}
 
-# CPU-baseline sample: same scene family, 4 bars of 24x6x6 cells
-SAMPLE = dict(side=6, length=24)
+# CPU-baseline sample: the headline scene's particles in the cell slab
+# x in [38, 42) of all four bars (32,768 particles), where the first grip's
+# rotating nodes meet the free span, so that the sample's solve has work
+SAMPLE_CELLS_X = (38, 42)
+SAMPLE_ITERS = 3
 
 
 def workload_name(side, smoother="l1 block-Jacobi"):
@@ -63,32 +68,107 @@ def workload_name(side, smoother="l1 block-Jacobi"):
             f"L-BFGS w=8, CN eps=1e-6")
 
 
-def cpu_worker():
-    """Oracle timing on the bounded sample (run in a single-threaded child)."""
+def cpu_worker(side):
+    """Oracle timing on the bounded sample (run in a single-threaded child):
+    the per-step set-up (binning, P2G, level-0 Hessian, Galerkin hierarchy)
+    and the cost of one quasi-Newton iteration, on the headline scene's
+    particles in a thin mid-span slab."""
+    import numpy as np
+
     import hot_scenes as hs
     import oracle as O
-    sc = hs.twisting_bars(**SAMPLE, n_steps=1)
+    sc = hs.twisting_bars(side=side, n_steps=1)
+    cell_x = np.floor(sc.x[:, 0] / sc.dx)
+    keep = (cell_x >= SAMPLE_CELLS_X[0]) & (cell_x < SAMPLE_CELLS_X[1])
+    for f in ("x", "v", "F", "C", "vol0", "mat_id"):
+        setattr(sc, f, getattr(sc, f)[keep].copy())
+    dt = O.time_step(sc)
     t0 = time.perf_counter()
-    out, info = O.step(sc)
+    st = O.prepare(sc, dt)
+    H0, nbr0 = O.hessian_slots(st)
+    hz = O.build_hierarchy(st, H0, nbr0, sc.mg_levels)
     t1 = time.perf_counter()
-    print(json.dumps(dict(seconds=t1 - t0, n=sc.n, iters=info["iters"])))
+    # the solve's own set-up (smoother inverses, first energy and gradient),
+    # then exactly SAMPLE_ITERS iterations (tolerance 0)
+    O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=0)
+    t2 = time.perf_counter()
+    dv, info = O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=SAMPLE_ITERS)
+    t3 = time.perf_counter()
+    O.g2p(st, dv)
+    t4 = time.perf_counter()
+    it = max(info["iters"], 1)
+    print(json.dumps(dict(setup=(t2 - t0) + (t4 - t3), per_iter=((t3 - t2) - (t2 - t1)) / it,
+                          iters=info["iters"], n=sc.n, seconds=t4 - t0)))
 
 
-def cpu_baseline(n_full):
+def cpu_baseline(n_full, side, job_iters):
+    """The oracle's steps/s on the whole timed job, from the bounded sample:
+    each step costs the set-up plus its quasi-Newton iterations (the counts
+    the GPU job took; the oracle takes the same decisions), both scaled from
+    the sample to the full particle count."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
     env["HIP_VISIBLE_DEVICES"] = ""
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker"], env=env,
-                       capture_output=True, text=True, timeout=900)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker",
+                        "--side", str(side)], env=env, capture_output=True, text=True,
+                       timeout=900)
     if r.returncode != 0:
         return dict(error=r.stderr[-500:])
     d = json.loads(r.stdout.strip().splitlines()[-1])
-    sec_full = d["seconds"] * n_full / d["n"]
-    return {"value": 1.0 / sec_full, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one oracle step of 4 bars 24x6x6 cells ({d['n']} particles, "
-                       f"{d['iters']} L-BFGS iterations) took {d['seconds']:.1f} s on 1 core; "
-                       f"scaled linearly by particle count to {n_full}")}
+    scale = n_full / d["n"]
+    sec = sum((d["setup"] + k * d["per_iter"]) * scale for k in job_iters)
+    return {"value": len(job_iters) / sec, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on the {d['n']} particles of the headline scene in cells "
+                       f"x in [{SAMPLE_CELLS_X[0]}, {SAMPLE_CELLS_X[1]}) on 1 core: per-step "
+                       f"set-up (binning, P2G, Hessian, hierarchy, G2P) {d['setup']:.2f} s, "
+                       f"{d['per_iter']:.3f} s per quasi-Newton iteration ({d['iters']} "
+                       f"timed); the job's {sum(job_iters)} iterations over "
+                       f"{len(job_iters)} steps, both costs scaled by particle count to "
+                       f"{n_full}: {sec:.0f} s")}
+
+
+def mixed_step_errors(side, steps):
+    """Per-step error of the mixed-precision step against the FP64 step from
+    the same state.  Before each step of the FP64 job its state (x, v, F, C)
+    seeds a mixed-precision scene; both take one step (the same CFL time step,
+    from the same velocities) and the mixed positions and velocities are
+    compared with the FP64 ones: max |dx| / max |x|, max |dv| / max |v|, and
+    max |dx| over the largest FP64 displacement.  The FP64 GPU step stands in
+    for the FP64 oracle at this size (it matches the oracle within 1e-10 at
+    every size the tests compare)."""
+    import numpy as np
+
+    import hot_scenes as hs
+    from paper_1911_07913_amd import hot
+    sc = hs.twisting_bars(side=side)
+    g = hot.Scene.from_scene(sc)
+    out = {"x": [], "v": [], "x_displacement": [], "iters_mixed": [], "iters_fp64": []}
+    try:
+        for _ in range(steps):
+            st = g.read()
+            cur = sc.copy()
+            cur.x, cur.v, cur.F, cur.C = st["x"], st["v"], st["F"], st["C"]
+            gm = hot.Scene.from_scene(cur, precision=hot.HOT_MIXED)
+            try:
+                gm.step()
+                im = gm.stats["iters"]
+                rm = gm.read(F=False, Cm=False)
+            finally:
+                gm.close()
+            g.step()
+            r64 = g.read(F=False, Cm=False)
+            out["x"].append(float(np.abs(rm["x"] - r64["x"]).max() / np.abs(r64["x"]).max()))
+            out["v"].append(float(np.abs(rm["v"] - r64["v"]).max() / np.abs(r64["v"]).max()))
+            out["x_displacement"].append(float(np.abs(rm["x"] - r64["x"]).max() /
+                                               max(np.abs(r64["x"] - st["x"]).max(), 1e-300)))
+            out["iters_mixed"].append(im)
+            out["iters_fp64"].append(g.stats["iters"])
+    finally:
+        g.close()
+    out["max"] = {"x": max(out["x"]), "v": max(out["v"]),
+                  "x_displacement": max(out["x_displacement"])}
+    return out
 
 
 def run(precision, steps, warmup, side, profile=True, smoother=0, scene=None):
@@ -206,7 +286,8 @@ def traffic_of(kernel, precision):
 
 def roofline_of(prof, n_particles, precision):
     """Roofline of the dominant traced kernel (largest summed launch time)."""
-    name, (ms, launches, nbytes) = max(prof.items(), key=lambda kv: kv[1][0])
+    name, (ms, launches, nbytes) = max(((k, v) for k, v in prof.items() if k not in COMPOSITE),
+                                       key=lambda kv: kv[1][0])
     if launches == 0:
         return None
     avg_s = ms * 1e-3 / launches
@@ -227,23 +308,28 @@ def roofline_of(prof, n_particles, precision):
 
 
 def vcycle_roofline(prof, precision):
-    """HBM roofline of the level-0 V-cycle passes (smoothing, Gauss-Seidel or
-    Jacobi, and the residual), the bandwidth-bound kernels each quasi-Newton
-    iteration repeats."""
+    """HBM roofline of the whole V-cycle (every level's smoothing, residual,
+    restriction and prolongation, the coarsest Jacobi-PCG and the precision
+    conversions, traced as one span per cycle), with the level-0 passes
+    (smoothing, Gauss-Seidel or Jacobi, and the residual) broken out."""
+    if "vcycle" not in prof or prof["vcycle"][1] == 0 or prof["vcycle"][0] <= 0:
+        return None
+    t, n, b = prof["vcycle"]
+    achieved = b / (t * 1e-3) / 1e9
+    out = {"span": "whole V-cycle", "bound": "hbm", "achieved": achieved,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "avg_cycle_ms": t / n, "cycles": n, "algorithmic_bytes_per_cycle": b / n}
     ks = [k for k in ("sgs0", "smooth0", "residual0") if k in prof and prof[k][1] > 0]
     ms = sum(prof[k][0] for k in ks)
-    launches = sum(prof[k][1] for k in ks)
     nbytes = sum(prof[k][2] for k in ks)
-    if launches == 0 or ms <= 0:
-        return None
-    achieved = nbytes / (ms * 1e-3) / 1e9
-    out = {"kernels": ks, "bound": "hbm", "achieved": achieved,
-           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
-    for k in ks:
-        t, n, b = prof[k]
-        out[k] = {"avg_launch_ms": t / n if n else None,
-                  "algorithmic_bytes_per_launch": b / n if n else None,
-                  "traffic": traffic_of(k, precision)}
+    if ms > 0:
+        out["level0_passes"] = {"kernels": ks, "achieved": nbytes / (ms * 1e-3) / 1e9,
+                                "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        for k in ks:
+            t, n, b = prof[k]
+            out["level0_passes"][k] = {"avg_launch_ms": t / n if n else None,
+                                       "algorithmic_bytes_per_launch": b / n if n else None,
+                                       "traffic": traffic_of(k, precision)}
     return out
 
 
@@ -293,10 +379,12 @@ def main():
                     help="skip the same job with the coloured Gauss-Seidel smoother")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the 8.2M-particle sphere-slab job")
+    ap.add_argument("--no-mixed-error", action="store_true",
+                    help="skip the per-step mixed-vs-FP64 error pass (untimed)")
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
-        cpu_worker()
+        cpu_worker(a.side)
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
@@ -368,6 +456,8 @@ def main():
                          "iters": [s["iters"] for s in rm["stats"]],
                          "roofline": roofline_of(rm["prof"], rm["n"], "mixed"),
                          "vcycle_roofline": vcycle_roofline(rm["prof"], "mixed")}
+        if not a.no_mixed_error:
+            line["mixed"]["step_error_vs_fp64"] = mixed_step_errors(a.side, a.steps)
     if not a.no_sgs:
         line["smoother_sgs"] = {
             prec_name(p):
@@ -402,7 +492,7 @@ def main():
         line["serving_sgs"] = run_serving(a.serving_requests, a.serving_slots,
                                           a.serving_budget_gb, sp[0], hot.HOT_SMOOTH_SGS)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(r["n"])
+        line["cpu_baseline"] = cpu_baseline(r["n"], a.side, [s["iters"] for s in stats])
     print(json.dumps(line), flush=True)
     return 0
 

@@ -275,7 +275,9 @@ enum {
   HOT_PROF_GRAD = 5,       /* gradient gather */
   HOT_PROF_PHESS = 6,      /* per-particle projected stress derivative */
   HOT_PROF_SGS0 = 7,       /* level-0 symmetric Gauss-Seidel smoothing (53 colour passes) */
-  HOT_PROF_COUNT = 8
+  HOT_PROF_VCYCLE = 8,     /* one whole V-cycle: every level's smoothing, residual and
+                              transfers, the coarsest solve, the precision conversions */
+  HOT_PROF_COUNT = 9
 };
 hot_status hot_profile_enable(hot_scene* scene, int32_t enable);
 hot_status hot_profile_read(const hot_scene* scene, int32_t kernel, double* total_ms,

@@ -135,6 +135,7 @@ struct hot_scene {
   int* herr = nullptr;
   int node_cap = 0;
   bool no_alloc = false;  // inside hot_step_noalloc: a buffer that must grow is an error
+  double cg_per_cycle = 1.0;  // last solve's coarsest-PCG iterations per V-cycle
   // last-step logs
   std::vector<int> log_int;
   std::vector<double> log_cn;
@@ -666,9 +667,9 @@ hot_status prepare(hot_scene* s, double dt) {
     else
       launch_rap(view(s, m), T, view(s, m + 1), st);
   }
-  // structural block counts of levels 0 and 1 (the traced kernels' bytes)
+  // structural block counts of every level (the traced kernels' bytes)
   if (s->prof)
-    for (int m = 0; m < std::min(s->levels, 2); ++m)
+    for (int m = 0; m < s->levels; ++m)
       launch_pattern_count(view(s, m), P<double>(s->dscal) + S_NNZ + m, st);
   if (s->mixed)  // level 0's BF16 copy comes from the assembly itself
     for (int m = 1; m < s->levels; ++m) launch_to_bf16(view(s, m), st);
@@ -688,7 +689,7 @@ hot_status prepare(hot_scene* s, double dt) {
 // coloured symmetric block Gauss-Seidel smoothing and an inexact Jacobi-PCG
 // coarsest solve.  In the mixed policy the
 // cycle runs on FP32 vectors over BF16 blocks; q and r stay FP64.
-hot_status vcycle(hot_scene* s, const double* q, double* r) {
+hot_status vcycle_body(hot_scene* s, const double* q, double* r) {
   hipStream_t st = s->stream;
   const bool mx = s->mixed;
   const int M = s->levels;
@@ -760,6 +761,11 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
   return HOT_OK;
 }
 
+hot_status vcycle(hot_scene* s, const double* q, double* r) {
+  PROF(s, HOT_PROF_VCYCLE, TRY(vcycle_body(s, q, r)));
+  return HOT_OK;
+}
+
 // ---------------------------------------------------------------- solve
 hot_status eval_trial(hot_scene* s, const double* dv, const double* p, double alpha, int out) {
   Particles& pt = s->P[s->cur];
@@ -777,6 +783,45 @@ hot_status gradient(hot_scene* s, const double* dv, int sbuf, double* g) {
                        P<int>(s->start), P<int>(s->counts), P<double>(s->bpartial),
                        P<double>(s->mass), P<int>(s->fixed), dv, s->dt_prepared, g, s->stream));
   return HOT_OK;
+}
+
+// Algorithmic bytes of one whole V-cycle.  Every non-coarsest level m runs
+// (l1 block-Jacobi) a residual pass and a post-smoothing pass over its
+// structural blocks, with the vectors each reads and writes once (the same
+// counts as the traced level-0 kernels), the first smoothing from zero on
+// level 0 (b and D~^-1 in, u out; coarser levels get it from the
+// restriction), the restriction (r in; b and, unless the next level is the
+// coarsest, D~^-1 and u of the next level) and the prolongation (coarse u in,
+// u in and out); with Gauss-Seidel, two smoothings of the traced level-0
+// form and a clearing of u instead of the first smoothing.  The coarsest
+// Jacobi-PCG reads its matrix and five vectors once per iteration (the
+// step's average iteration count per cycle).  Mixed precision adds the FP32
+// conversion of the input; the FP64 output is written once.
+double vcycle_bytes(hot_scene* s) {
+  const bool mx = s->mixed, gs = s->prm.smoother == HOT_SMOOTH_SGS;
+  const double vs = mx ? 4.0 : 8.0, ms = mx ? 18.0 : 72.0;
+  const int M = s->levels;
+  const double n0 = s->L[0].n;
+  double b = mx ? 36.0 * n0 : 0.0;
+  for (int m = 0; m + 1 < M; ++m) {
+    const LevelH& L = s->L[m];
+    const double n = L.n, nnz = s->hscal[S_NNZ + m], nc = s->L[m + 1].n;
+    if (gs) {
+      const double f = 2.0 - (double)(L.coff[kColors] - L.coff[kColors - 1]) / std::max(n, 1.0);
+      b += 4.0 * vs * n + 2.0 * f * (ms * nnz + (mx ? 85.0 : 107.0) * n);
+    } else {
+      if (m == 0) b += 16.0 * vs * n;
+      b += ms * nnz + (mx ? 40.0 : 76.0) * n;   // residual
+      b += ms * nnz + (mx ? 79.0 : 151.0) * n;  // post-smoothing
+    }
+    const bool first = !gs && m + 2 < M;
+    b += 3.0 * vs * n + 3.0 * vs * nc + (first ? 13.0 * vs * nc : 0.0);  // restriction
+    b += 4.0 * vs * nc + 8.0 * vs * n;                                    // prolongation
+  }
+  const double nc = s->L[M - 1].n, nnzc = s->hscal[S_NNZ + M - 1];
+  b += std::max(s->cg_per_cycle, 1.0) * (ms * nnzc + 15.0 * vs * nc);
+  b += 4.0 * vs * n0 + 24.0 * n0;
+  return b;
 }
 
 // Algorithmic bytes one launch of a traced kernel must move (structural
@@ -804,6 +849,7 @@ double prof_launch_bytes(hot_scene* s, int kind) {
     case HOT_PROF_EVAL: return 192.0 * np + 72.0 * n0;
     case HOT_PROF_GRAD: return 96.0 * np + 64.0 * n0;
     case HOT_PROF_PHESS: return 472.0 * np + 24.0 * n0;
+    case HOT_PROF_VCYCLE: return vcycle_bytes(s);
   }
   return 0.0;
 }
@@ -1006,6 +1052,11 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
     cg_total += sum;
   }
   *converged = conv;
+  {
+    long long all = 0;
+    for (int v = 0; v < nv; ++v) all += pcg[v];
+    s->cg_per_cycle = nv > 0 ? (double)all / nv : 1.0;
+  }
   if (stats) {
     stats->E = E;
     stats->cn = cn;

@@ -52,7 +52,7 @@ EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_partic
 BATCH_MAX_STEPS = 64
 
 PROF_KERNELS = {0: "smooth0", 1: "residual0", 2: "assemble_h0", 3: "rap0", 4: "particle_eval",
-                5: "gradient", 6: "particle_hessian", 7: "sgs0"}
+                5: "gradient", 6: "particle_hessian", 7: "sgs0", 8: "vcycle"}
 
 
 class hot_material(C.Structure):
