@@ -212,44 +212,65 @@ def run(precision, steps, warmup, side, profile=True, smoother=0, scene=None):
 
 
 class ServingRequests:
-    """The serving request stream, generated on demand (host memory holds only
-    requests not yet admitted)."""
+    """The serving request stream.  Every request's particle data is
+    generated before the run starts (in parallel threads), as a client would
+    hold it on arrival, so that generating inputs never counts as admission
+    wait; host memory of a request is released once it is admitted."""
 
-    def __init__(self, n, seed_base=4000):
-        self.n, self.seed_base, self.cache = n, seed_base, {}
+    def __init__(self, n, seed_base=4000, workers=8):
+        import hot_scenes as hs
+        from concurrent.futures import ThreadPoolExecutor
+        self.n, self.seed_base = n, seed_base
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            scenes = list(ex.map(lambda k: hs.serving_scene(k, seed_base=seed_base), range(n)))
+        self.cache = dict(enumerate(scenes))
 
     def __len__(self):
         return self.n
 
     def __getitem__(self, k):
-        import hot_scenes as hs
-        if k not in self.cache:
-            self.cache[k] = hs.serving_scene(k, seed_base=self.seed_base)
         return self.cache[k]
 
     def release(self, k):
         self.cache.pop(k, None)
 
 
-def run_serving(n_req, slots, budget_gb, precision, smoother, load=0.7, n_sat=64):
-    """Closed-loop run of the first n_sat requests for the saturated step
-    rate, then the whole stream with Poisson arrivals at ``load`` times it."""
+def run_serving(n_req, slots, budget_gb, precision, smoother, load=0.7, submit=True, graph=True,
+                rate=None, sat=None):
+    """Closed-loop run of the whole stream (every request arriving at t = 0)
+    for the saturated step rate, then the stream with Poisson arrivals at
+    ``load`` times it.  ``submit`` and ``graph``: the serving design (the
+    batch creating each scene on its slot thread from its device pool, and
+    captured V-cycle graphs), or the loop creating scenes itself and every
+    kernel launched eagerly.  ``rate`` (requests/s) and ``sat`` (a summary of
+    an earlier closed-loop run of the same design): use that arrival rate
+    instead of ``load`` times this design's own saturated rate."""
     from paper_1911_07913_amd import hot, serving
     budget = int(budget_gb * (1 << 30))
-    n_sat = min(n_sat, n_req)
-    _, sat, _ = serving.serve(ServingRequests(n_sat), [0.0] * n_sat, budget, slots, precision,
-                              smoother=smoother)
+    if sat is None:
+        _, sat, _ = serving.serve(ServingRequests(n_req), [0.0] * n_req, budget, slots,
+                                  precision, smoother=smoother, submit=submit, graph=graph)
     steps_per_req = 10
-    rate = load * sat["steps_per_s"] / steps_per_req
+    if rate is None:
+        rate = load * sat["steps_per_s"] / steps_per_req
+    load = rate * steps_per_req / sat["steps_per_s"]
     arrivals = serving.poisson_arrivals(n_req, rate, seed=4000)
     records, summary, trace = serving.serve(ServingRequests(n_req), arrivals, budget, slots,
-                                            precision, smoother=smoother)
+                                            precision, smoother=smoother, submit=submit,
+                                            graph=graph)
+    req_p50 = summary["request_latency_ms"]["p50"]
     summary.update(precision="fp64" if precision == hot.HOT_FP64 else "mixed",
                    smoother="l1jacobi" if smoother == hot.HOT_SMOOTH_L1_JACOBI else "sgs",
+                   design=("slot threads create scenes from the batch's device pool; "
+                           "V-cycles as captured HIP graphs") if submit and graph else
+                          ("loop creates each scene and admits it; eager launches"),
+                   admission_wait_share_p50=(summary["admission_wait_ms"]["p50"] / req_p50
+                                             if req_p50 else None),
                    slots=slots,
                    budget_gb=budget_gb, load=load, arrival_rate_req_per_s=rate,
                    saturated_steps_per_s=sat["steps_per_s"],
                    saturated_step_latency_ms=sat["step_latency_ms"], **trace)
+    summary["_sat"] = sat
     return summary
 
 
@@ -484,13 +505,22 @@ def main():
         # fully parallel pass of l1 block-Jacobi beats the 53 colour passes of
         # Gauss-Seidel (measured: serving_sgs)
         l1 = hot.HOT_SMOOTH_L1_JACOBI
-        line["serving"] = run_serving(a.serving_requests, a.serving_slots, a.serving_budget_gb,
-                                      sp[0], l1)
+        args = (a.serving_requests, a.serving_slots, a.serving_budget_gb)
+        line["serving"] = run_serving(*args, sp[0], l1)
+        # the round-trip design for comparison: the loop creates each scene on
+        # its own thread, every kernel is launched eagerly
+        line["serving_thread_per_slot"] = run_serving(*args, sp[0], l1, submit=False,
+                                                      graph=False)
+        # the serving design at the comparison design's arrival rate
+        line["serving_at_thread_per_slot_rate"] = run_serving(
+            *args, sp[0], l1, rate=line["serving_thread_per_slot"]["arrival_rate_req_per_s"],
+            sat=line["serving"]["_sat"])
         if len(sp) > 1:
-            line["serving_fp64"] = run_serving(a.serving_requests, a.serving_slots,
-                                               a.serving_budget_gb, sp[1], l1)
-        line["serving_sgs"] = run_serving(a.serving_requests, a.serving_slots,
-                                          a.serving_budget_gb, sp[0], hot.HOT_SMOOTH_SGS)
+            line["serving_fp64"] = run_serving(*args, sp[1], l1)
+        line["serving_sgs"] = run_serving(*args, sp[0], hot.HOT_SMOOTH_SGS)
+        for k in list(line):
+            if k.startswith("serving") and isinstance(line[k], dict):
+                line[k].pop("_sat", None)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["n"], a.side, [s["iters"] for s in stats])
     print(json.dumps(line), flush=True)

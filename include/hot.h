@@ -128,7 +128,12 @@ typedef struct {
   int32_t smoother_sweeps; /* smoothing sweeps per level and direction (1) */
   int32_t precision;       /* hot_precision */
   int32_t smoother;        /* hot_smoother */
-  int32_t reserved[2];     /* must be zero */
+  int32_t graph;           /* 1: each step's V-cycles run as one captured HIP
+                              graph (captured at the step's first cycle, then
+                              launched once per cycle; same kernels and
+                              results as 0, fewer launches from the host).
+                              Ignored while kernel tracing is on. */
+  int32_t reserved;        /* must be zero */
 } hot_params;
 
 typedef struct {
@@ -249,11 +254,44 @@ typedef struct {
   double t_admit;     /* admission time */
   double t_step_end[HOT_BATCH_MAX_STEPS]; /* completion time of each of the first 64 steps */
   char message[160];  /* error text when status < 0 */
+  hot_scene* scene;   /* the request's scene (hot_batch_add: the caller's; hot_batch_submit:
+                         the one the batch created, now owned by the caller, who reads and
+                         destroys it; NULL if its creation failed) */
+  double t_created;   /* when the scene was ready to step (hot_batch_submit: after its
+                         creation on the slot thread; hot_batch_add: t_admit) */
 } hot_batch_result;
+
+/* The arguments of hot_init_scene, for a request whose scene the batch
+ * creates (hot_batch_submit). */
+typedef struct {
+  const hot_params* params;
+  int64_t n;
+  const double* x;
+  const double* v;
+  const double* F;    /* nullable */
+  const double* C;    /* nullable */
+  const double* vol0;
+  const int32_t* mat_id;
+  const hot_material* mats;
+  int32_t n_mats;
+  const hot_bc* bcs;
+  int32_t n_bcs;
+} hot_scene_desc;
 typedef struct hot_batch hot_batch;
 hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out);
 hot_status hot_batch_capacity(hot_batch* batch, size_t* free_bytes, int32_t* free_slots);
 hot_status hot_batch_add(hot_batch* batch, hot_scene* scene, int32_t n_steps, int64_t tag);
+/* Admit a request as a scene description: the same admission rule, with the
+ * reservation taken from hot_scene_footprint, but the slot's thread creates
+ * the scene itself (hot_init_scene, validation included) with device memory
+ * from the batch's pool and a stream of its own, then runs its steps.  The
+ * admission path does no device work.  The arrays desc points to must stay
+ * valid until the request's result is collected (*desc and *desc->params are
+ * copied).  The result carries the scene; the caller reads it and destroys it
+ * (its buffers return to the pool) before destroying the batch.  A scene that
+ * fails validation comes back with the error in status and message. */
+hot_status hot_batch_submit(hot_batch* batch, const hot_scene_desc* desc, int32_t n_steps,
+                            int64_t tag);
 hot_status hot_batch_poll(hot_batch* batch, hot_batch_result* results, int32_t cap,
                           int32_t* n_done, int32_t* n_resident, int32_t wait_ms);
 double hot_batch_clock(const hot_batch* batch);

@@ -8,6 +8,9 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
+#include <memory>
+#include <unordered_map>
 #include <mutex>
 #include <cmath>
 #include <cstdarg>
@@ -135,6 +138,8 @@ struct hot_scene {
   int* herr = nullptr;
   int node_cap = 0;
   bool no_alloc = false;  // inside hot_step_noalloc: a buffer that must grow is an error
+  hipGraphExec_t vc_exec = nullptr;  // captured V-cycle (hot_params.graph)
+  bool vc_stale = true;              // vc_exec holds an earlier step's cycle
   double cg_per_cycle = 1.0;  // last solve's coarsest-PCG iterations per V-cycle
   // last-step logs
   std::vector<int> log_int;
@@ -258,6 +263,22 @@ LevelView view(hot_scene* s, int m) {
   return v;
 }
 
+// Coarse-PCG iteration log of a step: one entry per V-cycle (at most three per
+// quasi-Newton iteration, plus headroom), the last entry clamping overflow,
+// then the device-side cursor.
+int pcg_log_cap(const hot_scene* s) { return s->prm.max_iters * 3 + 15; }
+size_t pcg_log_bytes(int max_iters) { return ((size_t)max_iters * 3 + 17) * 4; }
+IterLog pcg_log(hot_scene* s) {
+  const int cap = pcg_log_cap(s);
+  return IterLog{P<int>(s->pcg_iters), cap, P<int>(s->pcg_iters) + cap + 1};
+}
+
+void drop_vcycle_graph(hot_scene* s) {
+  if (s->vc_exec) (void)hipGraphExecDestroy(s->vc_exec);
+  s->vc_exec = nullptr;
+  s->vc_stale = true;
+}
+
 double lame_mu(double E, double nu) { return E / (2.0 * (1.0 + nu)); }
 double lame_lam(double E, double nu) { return E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)); }
 
@@ -308,7 +329,8 @@ hot_status validate_params(const hot_params* p) {
     return fail(HOT_E_INVALID, "unknown precision");
   if (p->smoother != HOT_SMOOTH_L1_JACOBI && p->smoother != HOT_SMOOTH_SGS)
     return fail(HOT_E_INVALID, "unknown smoother");
-  if (p->reserved[0] || p->reserved[1]) return fail(HOT_E_INVALID, "reserved fields must be zero");
+  if (p->graph != 0 && p->graph != 1) return fail(HOT_E_INVALID, "graph must be 0 or 1");
+  if (p->reserved) return fail(HOT_E_INVALID, "reserved field must be zero");
   return HOT_OK;
 }
 
@@ -564,6 +586,7 @@ hot_status alloc_nodes0(hot_scene* s, int n) {
 // Galerkin hierarchy: everything of a step that precedes the solve.
 hot_status prepare(hot_scene* s, double dt) {
   hipStream_t st = s->stream;
+  s->vc_stale = true;  // level sizes change with every step
   const int n = s->n;
   const GridGeom& g0 = s->sd.g0;
   Particles& src = s->P[s->cur];
@@ -676,7 +699,9 @@ hot_status prepare(hot_scene* s, double dt) {
   if (s->prm.smoother == HOT_SMOOTH_SGS && s->levels > 1) TRY(prepare_sgs(s));
   size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
   TRY(ensure(s, s->pcg_work, pcg));
-  TRY(ensure(s, s->pcg_iters, (size_t)(s->prm.max_iters * 3 + 16) * 4));
+  TRY(ensure(s, s->pcg_iters, pcg_log_bytes(s->prm.max_iters)));
+  launch_fill_int(1, pcg_log(s).cursor, 0, st);
+  if (s->prm.graph) coarse_pcg_warm();
   HIPCHK(hipGetLastError());
   s->prepared = true;
   s->dt_prepared = dt;
@@ -735,10 +760,8 @@ hot_status vcycle_body(hot_scene* s, const double* q, double* r) {
     launch_restrict(Lm, view(s, m + 1), mx, s->L[m].r.p, bs[m + 1], first ? us[m + 1] : nullptr,
                     st);
   }
-  int slot = std::min(s->vcycles, s->prm.max_iters * 3 + 15);
-  HIPCHK(launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p,
-                    P<int>(s->pcg_iters) + slot, 500, 0.5, st));
-  s->vcycles++;
+  HIPCHK(launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p, pcg_log(s),
+                           500, 0.5, st));
   for (int m = M - 2; m >= 0; --m) {
     LevelView Lm = view(s, m);
     launch_prolong_add(Lm, view(s, m + 1), mx, us[m + 1], us[m], st);
@@ -761,8 +784,53 @@ hot_status vcycle_body(hot_scene* s, const double* q, double* r) {
   return HOT_OK;
 }
 
+// With hot_params.graph set, the solve's cycles (q and r the solver's own
+// vectors) run as one HIP graph per step: the first cycle after prepare is
+// captured on the scene's stream and instantiated, and every cycle of the
+// step launches that graph.  The launches are the same kernels with the same
+// arguments as the eager cycle; the coarse-PCG log advances on the device.
 hot_status vcycle(hot_scene* s, const double* q, double* r) {
-  PROF(s, HOT_PROF_VCYCLE, TRY(vcycle_body(s, q, r)));
+  const bool graph = s->prm.graph && !s->prof && q == P<double>(s->q) && r == P<double>(s->r);
+  if (!graph) {
+    PROF(s, HOT_PROF_VCYCLE, TRY(vcycle_body(s, q, r)));
+  } else {
+    if (s->vc_stale) {
+      HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      hot_status rc = vcycle_body(s, q, r);
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(s->stream, &gr);
+      if (rc < 0) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      if (e != hipSuccess)
+        return fail(HOT_E_DEVICE, "V-cycle capture failed: %s", hipGetErrorString(e));
+      // the cycle of a new step usually has the previous step's launch
+      // sequence with new sizes and buffers: update the executable graph in
+      // place, and instantiate afresh only when that is refused
+      bool updated = false;
+      if (s->vc_exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(s->vc_exec, gr, &err_node, &res) == hipSuccess &&
+                  res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+          (void)hipGetLastError();
+          (void)hipGraphExecDestroy(s->vc_exec);
+          s->vc_exec = nullptr;
+        }
+      }
+      if (!updated) e = hipGraphInstantiate(&s->vc_exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) {
+        s->vc_exec = nullptr;
+        return fail(HOT_E_DEVICE, "V-cycle graph instantiation failed: %s", hipGetErrorString(e));
+      }
+      s->vc_stale = false;
+    }
+    HIPCHK(hipGraphLaunch(s->vc_exec, s->stream));
+  }
+  s->vcycles++;
   return HOT_OK;
 }
 
@@ -1120,6 +1188,7 @@ hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
 void destroy(hot_scene* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  drop_vcycle_graph(s);
   DBuf* all[] = {&s->pbuf[0], &s->pbuf[1], &s->f, &s->key, &s->keys, &s->tmp, &s->Cp, &s->Ag,
                  &s->psi[0], &s->psi[1], &s->S[0], &s->S[1], &s->counts, &s->start,
                  &s->cursor, &s->flags, &s->scan, &s->scan_temp, &s->err, &s->mass,
@@ -1498,7 +1567,7 @@ hot_status hot_step_noalloc(hot_scene* scene, double dt, hot_step_stats* stats) 
   unsigned char* base = nullptr;
   TRY(scratch_address(scene->device, &base));
   // one coarse-PCG count per V-cycle (at most 3 per iteration)
-  const size_t iters = round256(((size_t)scene->prm.max_iters * 3 + 16) * 4);
+  const size_t iters = round256(pcg_log_bytes(scene->prm.max_iters));
   if (BorrowScratch::fixed_bytes() + iters + 4096 > kNoAllocScratchBytes)
     return fail(HOT_E_INVALID,
                 "hot_step_noalloc: max_iters = %d needs %zu bytes of counters; the scratch "
@@ -1685,15 +1754,91 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
 // admitted scene runs all its steps on its own stream from its slot's thread,
 // so the device interleaves the kernels of every resident scene; the batch
 // only does admission (HBM budget, free slot) and completion bookkeeping.
+namespace {
+
+// Device memory pool of a batch.  Scenes that the batch creates (hot_batch_
+// submit) take their buffers from it and return them when destroyed; a
+// returned block is kept in its size class and handed out again, so scenes
+// created and destroyed at the request rate do not call hipMalloc / hipFree
+// (hipFree waits for the device) each time.  Size classes step by 1/8 of a
+// power of two (at most 12.5% rounding).  The blocks go back to the device
+// when the batch is destroyed and every block has been returned.
+struct DevicePool {
+  std::mutex mu;
+  std::map<size_t, std::vector<void*>> free_blocks;
+  std::unordered_map<void*, size_t> live;
+  int device = 0;
+  bool closing = false;
+
+  static size_t size_class(size_t b) {
+    if (b <= 4096) return 4096;
+    int e = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t step = (size_t)1 << (e - 3);
+    return (b + step - 1) / step * step;
+  }
+  // with mu held
+  void release_all() {
+    (void)hipSetDevice(device);
+    for (auto& kv : free_blocks)
+      for (void* p : kv.second) (void)hipFree(p);
+    free_blocks.clear();
+  }
+};
+
+void* pool_alloc(size_t bytes, void* ctx) {
+  DevicePool* pool = (DevicePool*)ctx;
+  const size_t c = DevicePool::size_class(bytes);
+  {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    auto it = pool->free_blocks.find(c);
+    if (it != pool->free_blocks.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      pool->live[p] = c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, c) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(pool->mu);
+  pool->live[p] = c;
+  return p;
+}
+
+void pool_free(void* p, void* ctx) {
+  if (!p) return;
+  DevicePool* pool = (DevicePool*)ctx;
+  bool last = false;
+  {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    auto it = pool->live.find(p);
+    if (it == pool->live.end()) return;
+    pool->free_blocks[it->second].push_back(p);
+    pool->live.erase(it);
+    if (pool->closing && pool->live.empty()) {
+      pool->release_all();
+      last = true;
+    }
+  }
+  if (last) delete pool;
+}
+
+}  // namespace
+
 struct hot_batch {
   using clock = std::chrono::steady_clock;
   struct Job {
     hot_scene* scene = nullptr;
+    bool create = false;    // submitted: the slot thread creates the scene
+    hot_scene_desc desc;
+    hot_params params;
     int steps = 0;
     int64_t tag = 0;
     size_t bytes = 0;
     double t_admit = 0.0;
   };
+  DevicePool* pool = nullptr;
+  int device = 0;
   size_t budget = 0;
   size_t used = 0;
   int resident = 0;
@@ -1714,7 +1859,7 @@ struct hot_batch {
       Job job;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || jobs[k].scene != nullptr; });
+        cv_work.wait(lk, [&] { return stop || jobs[k].scene != nullptr || jobs[k].create; });
         if (stop) return;
         job = jobs[k];
       }
@@ -1722,6 +1867,20 @@ struct hot_batch {
       std::memset(&r, 0, sizeof(r));
       r.tag = job.tag;
       r.t_admit = job.t_admit;
+      if (job.create) {
+        (void)hipSetDevice(device);
+        const hot_scene_desc& d = job.desc;
+        hot_allocator a{pool_alloc, pool_free, pool};
+        hot_status rc = hot_init_scene(&job.params, d.n, d.x, d.v, d.F, d.C, d.vol0, d.mat_id,
+                                       d.mats, d.n_mats, d.bcs, d.n_bcs, &a, nullptr, &job.scene);
+        if (rc < 0) {
+          r.status = rc;
+          std::snprintf(r.message, sizeof(r.message), "%s", g_err.c_str());
+          job.steps = 0;
+        }
+      }
+      r.scene = job.scene;
+      r.t_created = job.create ? now() : job.t_admit;
       for (int i = 0; i < job.steps; ++i) {
         hot_step_stats st;
         hot_status rc = hot_step(job.scene, 0.0, &st);
@@ -1766,6 +1925,12 @@ hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batc
   b->budget = hbm_budget_bytes;
   b->t0 = hot_batch::clock::now();
   b->jobs.resize(max_slots);
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(HOT_E_DEVICE, "no current HIP device");
+  }
+  b->pool = new DevicePool();
+  b->pool->device = b->device;
   try {
     for (int k = 0; k < max_slots; ++k) b->workers.emplace_back([b, k] { b->serve(k); });
   } catch (...) {
@@ -1796,9 +1961,39 @@ hot_status hot_batch_add(hot_batch* b, hot_scene* s, int32_t n_steps, int64_t ta
       return fail(HOT_E_NOMEM, "batch full: %zu + %zu > %zu bytes or no free slot", b->used,
                   need, b->budget);
     int k = 0;
-    while (b->jobs[k].scene) ++k;
+    while (b->jobs[k].scene || b->jobs[k].create) ++k;
     hot_batch::Job& j = b->jobs[k];
     j.scene = s;
+    j.create = false;
+    j.steps = n_steps;
+    j.tag = tag;
+    j.bytes = need;
+    j.t_admit = b->now();
+    b->used += need;
+    b->resident += 1;
+  }
+  b->cv_work.notify_all();
+  return HOT_OK;
+}
+
+hot_status hot_batch_submit(hot_batch* b, const hot_scene_desc* d, int32_t n_steps, int64_t tag) {
+  if (!b || !d || !d->params || !d->x || n_steps < 1) return fail(HOT_E_INVALID, "bad arguments");
+  size_t need = 0;
+  TRY(hot_scene_footprint(d->params, d->n, d->x, &need));
+  need = std::max(need, (size_t)1);
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->resident >= (int)b->jobs.size() || b->used + need > b->budget)
+      return fail(HOT_E_NOMEM, "batch full: %zu + %zu > %zu bytes or no free slot", b->used,
+                  need, b->budget);
+    int k = 0;
+    while (b->jobs[k].scene || b->jobs[k].create) ++k;
+    hot_batch::Job& j = b->jobs[k];
+    j.scene = nullptr;
+    j.create = true;
+    j.desc = *d;
+    j.params = *d->params;
+    j.desc.params = &j.params;
     j.steps = n_steps;
     j.tag = tag;
     j.bytes = need;
@@ -1839,6 +2034,19 @@ void hot_batch_destroy(hot_batch* b) {
   b->cv_work.notify_all();
   for (std::thread& t : b->workers)
     if (t.joinable()) t.join();
+  if (b->pool) {
+    DevicePool* pool = b->pool;
+    bool gone = false;
+    {
+      std::lock_guard<std::mutex> lk(pool->mu);
+      pool->closing = true;
+      if (pool->live.empty()) {
+        pool->release_all();
+        gone = true;
+      }
+    }
+    if (gone) delete pool;
+  }
   delete b;
 }
 

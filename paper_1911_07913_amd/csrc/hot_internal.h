@@ -228,10 +228,27 @@ void launch_restrict(const LevelView& F, const LevelView& Cv, bool mixed, const 
                      void* bc, void* uc, hipStream_t st);
 void launch_prolong_add(const LevelView& F, const LevelView& Cv, bool mixed, const void* uc,
                         void* u, hipStream_t st);
-// Coarsest solve; iters_out receives the iteration count, or -1 if a grid
-// barrier of the multi-work-group form timed out.
+// Per-solve log of coarsest-level iteration counts, indexed on the device:
+// a solve writes its count (-1 if a grid barrier of the multi-work-group form
+// timed out) to base[min(*cursor, cap)] and advances *cursor, so that a
+// captured V-cycle logs each replay in its own entry.
+struct IterLog {
+  int* base;
+  int cap;
+  int* cursor;
+};
+__device__ inline void log_iters(const IterLog& lg, int v) {
+  const int c = *lg.cursor;
+  lg.base[c < lg.cap ? c : lg.cap] = v;
+  *lg.cursor = c + 1;
+}
+// Coarsest solve (relative tolerance rel in the D^-1 norm, at most max_iter
+// iterations), logging its iteration count through lg.
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                             int* iters_out, int max_iter, double rel, hipStream_t st);
+                             IterLog lg, int max_iter, double rel, hipStream_t st);
+// Resolve the coarsest solve's launch shapes for the current device (they
+// are cached; a stream capture must not be the first to ask).
+void coarse_pcg_warm();
 size_t coarse_pcg_work_bytes(int n);
 // coloured symmetric Gauss-Seidel: rows of each colour (coff[0..27], device),
 // diagonal-block inverses, and one colour's in-place pass

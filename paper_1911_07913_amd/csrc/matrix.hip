@@ -914,7 +914,7 @@ constexpr size_t kPcgLdsMax = 60 * 1024;
 template <typename V>
 __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(
     LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
-    int* __restrict__ iters_out, int max_iter, double rel) {
+    IterLog lg, int max_iter, double rel) {
   extern __shared__ __attribute__((aligned(16))) unsigned char pcg_lds[];
   __shared__ V red[kPcgWaves];
   const int n3 = 3 * L.n;
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_coarse_pcg(
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n3; k += kPcgThreads) comp<V>(x4, L.nodes[k / 3], k % 3) = x[k];
-  if (threadIdx.x == 0) *iters_out = it;
+  if (threadIdx.x == 0) log_iters(lg, it);
 }
 
 __global__ __launch_bounds__(256) void k_spmv(LevelView L, const double* __restrict__ x,
@@ -1085,7 +1085,7 @@ template <typename V>
 __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
     LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
     V* __restrict__ work, double* __restrict__ part, GridBar* __restrict__ bar,
-    int* __restrict__ iters_out, int max_iter, double rel) {
+    IterLog lg, int max_iter, double rel) {
   __shared__ double red[kCgWaves];
   __shared__ double s_val;
   __shared__ int s_ok;
@@ -1180,7 +1180,7 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_grid(
   }
   for (int row = gw; row < n; row += nw)
     if (lane < 3) comp<V>(x4, L.nodes[row], lane) = x[3 * row + lane];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) log_iters(lg, ok ? it : -1);
 }
 
 // Register-resident form of the grid solve for coarsest levels of at most R
@@ -1193,7 +1193,7 @@ template <typename V, int R>
 __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_reg(
     LevelView L, const V* __restrict__ b, typename Vec4Of<V>::type* __restrict__ x4,
     V* __restrict__ work, double* __restrict__ part, GridBar* __restrict__ bar,
-    int* __restrict__ iters_out, int max_iter, double rel) {
+    IterLog lg, int max_iter, double rel) {
   __shared__ double red[kCgWaves];
   __shared__ double s_val;
   __shared__ int s_ok;
@@ -1309,7 +1309,7 @@ __global__ __launch_bounds__(kCgWaves * 64) void k_coarse_pcg_reg(
     const int row = gw + k * nw;
     if (row < n && lane < 3) comp<V>(x4, L.nodes[row], lane) = xx[k];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *iters_out = ok ? it : -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) log_iters(lg, ok ? it : -1);
 }
 
 __global__ void k_reset_bar(GridBar* bar) {
@@ -1437,6 +1437,13 @@ void launch_dense_out(const LevelView& L, bool mixed, const void* u, double* out
 }
 
 
+void coarse_pcg_warm() {
+  (void)grid_blocks<float, false>();
+  (void)grid_blocks<double, false>();
+  (void)grid_blocks<float, true>();
+  (void)grid_blocks<double, true>();
+}
+
 size_t coarse_pcg_work_bytes(int n) {
   return (size_t)6 * 3 * n * sizeof(double) + 256 + 2 * kCgMaxBlocks * sizeof(double) +
          sizeof(GridBar);
@@ -1446,7 +1453,7 @@ size_t coarse_pcg_work_bytes(int n) {
 constexpr int kGridMinRows = 128;
 
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                             int* iters_out, int max_iter, double rel, hipStream_t st) {
+                             IterLog lg, int max_iter, double rel, hipStream_t st) {
   const size_t vsz = mixed ? sizeof(float) : sizeof(double);
   const size_t lds = (size_t)5 * 3 * L.n * vsz;
   // One work-group streams the whole level matrix through one compute unit
@@ -1458,11 +1465,11 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   if (!grid || maxb < 2) {
     if (lds > kPcgLdsMax) return hipErrorInvalidConfiguration;
     if (mixed)
-      k_coarse_pcg<float><<<1, kPcgThreads, lds, st>>>(L, (const float*)b, (float4*)x, iters_out,
+      k_coarse_pcg<float><<<1, kPcgThreads, lds, st>>>(L, (const float*)b, (float4*)x, lg,
                                                       max_iter, rel);
     else
       k_coarse_pcg<double><<<1, kPcgThreads, lds, st>>>(L, (const double*)b, (double4*)x,
-                                                       iters_out, max_iter, rel);
+                                                       lg, max_iter, rel);
     return hipGetLastError();
   }
   const size_t vec = (size_t)6 * 3 * L.n * vsz;
@@ -1476,19 +1483,19 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   if (maxr >= 2 && L.n <= kRegRows * nbr * kCgWaves) {
     if (mixed)
       k_coarse_pcg_reg<float, kRegRows><<<nbr, kCgWaves * 64, 0, st>>>(
-          L, (const float*)b, (float4*)x, (float*)work, part, bar, iters_out, max_iter, rel);
+          L, (const float*)b, (float4*)x, (float*)work, part, bar, lg, max_iter, rel);
     else
       k_coarse_pcg_reg<double, kRegRows><<<nbr, kCgWaves * 64, 0, st>>>(
-          L, (const double*)b, (double4*)x, (double*)work, part, bar, iters_out, max_iter, rel);
+          L, (const double*)b, (double4*)x, (double*)work, part, bar, lg, max_iter, rel);
     return hipGetLastError();
   }
   if (mixed)
     k_coarse_pcg_grid<float><<<nb, kCgWaves * 64, 0, st>>>(L, (const float*)b, (float4*)x,
-                                                          (float*)work, part, bar, iters_out,
+                                                          (float*)work, part, bar, lg,
                                                           max_iter, rel);
   else
     k_coarse_pcg_grid<double><<<nb, kCgWaves * 64, 0, st>>>(L, (const double*)b, (double4*)x,
-                                                           (double*)work, part, bar, iters_out,
+                                                           (double*)work, part, bar, lg,
                                                            max_iter, rel);
   return hipGetLastError();
 }

@@ -47,7 +47,7 @@ EXPORTS = ["hot_scene_footprint", "hot_init_scene", "hot_step", "hot_read_partic
            "hot_batch_create", "hot_batch_capacity", "hot_batch_add", "hot_batch_poll",
            "hot_batch_clock", "hot_batch_destroy", "hot_debug_read", "hot_debug_prepare",
            "hot_debug_apply", "hot_debug_set", "hot_profile_enable", "hot_profile_read",
-           "hot_step_noalloc"]
+           "hot_step_noalloc", "hot_batch_submit"]
 
 BATCH_MAX_STEPS = 64
 
@@ -68,7 +68,8 @@ class hot_bc(C.Structure):
 class hot_batch_result(C.Structure):
     _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("steps", C.c_int32),
                 ("iters", C.c_int32), ("reserved", C.c_int32), ("t_admit", C.c_double),
-                ("t_step_end", C.c_double * BATCH_MAX_STEPS), ("message", C.c_char * 160)]
+                ("t_step_end", C.c_double * BATCH_MAX_STEPS), ("message", C.c_char * 160),
+                ("scene", C.c_void_p), ("t_created", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -79,13 +80,20 @@ class hot_allocator(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
+class hot_scene_desc(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("n", C.c_int64), ("x", C.c_void_p), ("v", C.c_void_p),
+                ("F", C.c_void_p), ("C", C.c_void_p), ("vol0", C.c_void_p), ("mat_id", C.c_void_p),
+                ("mats", C.c_void_p), ("n_mats", C.c_int32), ("bcs", C.c_void_p),
+                ("n_bcs", C.c_int32)]
+
+
 class hot_params(C.Structure):
     _fields_ = [("dx", C.c_double), ("grid_cells", C.c_int32 * 3), ("origin", C.c_double * 3),
                 ("gravity", C.c_double * 3), ("cfl", C.c_double), ("max_dt", C.c_double),
                 ("tol", C.c_double), ("lbfgs_history", C.c_int32), ("mg_levels", C.c_int32),
                 ("max_iters", C.c_int32), ("smoother_sweeps", C.c_int32),
                 ("precision", C.c_int32), ("smoother", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("graph", C.c_int32), ("reserved", C.c_int32)]
 
 
 class hot_step_stats(C.Structure):
@@ -134,6 +142,7 @@ def lib():
     L.hot_batch_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(vp)]
     L.hot_batch_capacity.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]
     L.hot_batch_add.argtypes = [vp, vp, C.c_int32, C.c_int64]
+    L.hot_batch_submit.argtypes = [vp, C.POINTER(hot_scene_desc), C.c_int32, C.c_int64]
     L.hot_batch_poll.argtypes = [vp, C.POINTER(hot_batch_result), C.c_int32,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
     L.hot_batch_clock.argtypes = [vp]
@@ -187,7 +196,7 @@ def _dp(a):
 
 def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol=1e-6,
                 lbfgs_history=8, mg_levels=3, max_iters=500, smoother_sweeps=1,
-                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI):
+                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI, graph=0):
     p = hot_params()
     p.dx = dx
     for a in range(3):
@@ -198,6 +207,7 @@ def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol
     p.lbfgs_history, p.mg_levels, p.max_iters = int(lbfgs_history), int(mg_levels), int(max_iters)
     p.smoother_sweeps, p.precision = int(smoother_sweeps), int(precision)
     p.smoother = int(smoother)
+    p.graph = int(graph)
     return p
 
 
@@ -233,44 +243,71 @@ class TorchAllocator:
             self._torch.cuda.caching_allocator_delete(ptr)
 
 
+class SceneArgs:
+    """The host arrays of hot_init_scene in C layout (kept alive by this object)."""
+
+    def __init__(self, params, x, v, F, Cm, vol0, mat_id, materials, bcs):
+        self.params = params
+        self.x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = self.n = self.x.shape[0]
+        self.v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        self.F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(n, 9)
+        self.Cm = None if Cm is None else np.ascontiguousarray(Cm, dtype=np.float64).reshape(n, 9)
+        self.vol0 = np.ascontiguousarray(vol0, dtype=np.float64).reshape(n)
+        self.mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(n)
+        self.mats = (hot_material * len(materials))()
+        for k, m in enumerate(materials):
+            sc2 = m.get("snow_clamp", (0.0, 0.0))
+            self.mats[k] = hot_material(int(m["model"]), m["E"], m["nu"], m["density"],
+                                        m.get("yield_stress", 0.0),
+                                        (C.c_double * 2)(float(sc2[0]), float(sc2[1])))
+        self.n_mats = len(materials)
+        self.nb = len(bcs)
+        self.cb = (hot_bc * max(self.nb, 1))()
+        for k, b in enumerate(bcs):
+            self.cb[k].kind = int(b["kind"])
+            for j, val in enumerate(np.asarray(b["p"], dtype=np.float64)[:16]):
+                self.cb[k].p[j] = float(val)
+
+    def desc(self):
+        def addr(a):
+            return None if a is None else a.ctypes.data
+        return hot_scene_desc(C.addressof(self.params), self.n, addr(self.x), addr(self.v),
+                              addr(self.F), addr(self.Cm), addr(self.vol0), addr(self.mat_id),
+                              C.addressof(self.mats), self.n_mats, C.addressof(self.cb), self.nb)
+
+
 class Scene:
     """Owner of one hot_scene handle."""
 
     def __init__(self, params, x, v, F, Cm, vol0, mat_id, materials, bcs, stream=None,
                  allocator=None):
         L = lib()
-        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
-        n = x.shape[0]
-        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
-        F = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(n, 9)
-        Cm = None if Cm is None else np.ascontiguousarray(Cm, dtype=np.float64).reshape(n, 9)
-        vol0 = np.ascontiguousarray(vol0, dtype=np.float64).reshape(n)
-        mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(n)
-        mats = (hot_material * len(materials))()
-        for k, m in enumerate(materials):
-            sc2 = m.get("snow_clamp", (0.0, 0.0))
-            mats[k] = hot_material(int(m["model"]), m["E"], m["nu"], m["density"],
-                                   m.get("yield_stress", 0.0),
-                                   (C.c_double * 2)(float(sc2[0]), float(sc2[1])))
-        nb = len(bcs)
-        cb = (hot_bc * max(nb, 1))()
-        for k, b in enumerate(bcs):
-            cb[k].kind = int(b["kind"])
-            for j, val in enumerate(np.asarray(b["p"], dtype=np.float64)[:16]):
-                cb[k].p[j] = float(val)
+        a = SceneArgs(params, x, v, F, Cm, vol0, mat_id, materials, bcs)
         if stream or allocator is not None:
             _require_single_runtime()
         self.params = params
-        self.n = n
+        self.n = a.n
         self._allocator = allocator
         h = C.c_void_p()
-        st = _check(L.hot_init_scene(C.byref(params), n, _dp(x), _dp(v), _dp(F), _dp(Cm),
-                                     _dp(vol0), mat_id.ctypes.data_as(C.POINTER(C.c_int32)),
-                                     mats, len(materials), cb, nb,
-                                     C.byref(allocator.struct) if allocator else None,
-                                     C.c_void_p(stream) if stream else None, C.byref(h)))
+        _check(L.hot_init_scene(C.byref(params), a.n, _dp(a.x), _dp(a.v), _dp(a.F), _dp(a.Cm),
+                                _dp(a.vol0), a.mat_id.ctypes.data_as(C.POINTER(C.c_int32)),
+                                a.mats, a.n_mats, a.cb, a.nb,
+                                C.byref(allocator.struct) if allocator else None,
+                                C.c_void_p(stream) if stream else None, C.byref(h)))
         self.handle = h
         self.stats = None
+
+    @classmethod
+    def adopt(cls, handle, n, params):
+        """Wrap a scene handle the library created (a submitted batch request)."""
+        self = cls.__new__(cls)
+        self.params = params
+        self.n = n
+        self._allocator = None
+        self.handle = C.c_void_p(handle)
+        self.stats = None
+        return self
 
     @classmethod
     def from_scene(cls, sc, precision=HOT_FP64, stream=None, allocator=None, **over):
@@ -389,6 +426,17 @@ class Batch:
         _check(st)
         return True
 
+    def submit(self, args: SceneArgs, n_steps: int, tag: int) -> bool:
+        """Admit a request as a scene description (the slot thread creates the
+        scene); False when it does not fit now (HOT_E_NOMEM).  ``args`` must
+        stay alive until the request is collected."""
+        d = args.desc()
+        st = lib().hot_batch_submit(self.handle, C.byref(d), n_steps, tag)
+        if st == HOT_E_NOMEM:
+            return False
+        _check(st)
+        return True
+
     def poll(self, wait_ms=0, cap=64):
         """Finished scenes as dicts (tag, status, steps, iters, t_admit,
         t_step_end list, message) and the number still resident."""
@@ -402,7 +450,8 @@ class Batch:
             m = min(r.steps + (1 if r.status < 0 else 0), BATCH_MAX_STEPS)
             out.append(dict(tag=r.tag, status=r.status, steps=r.steps, iters=r.iters,
                             t_admit=r.t_admit, t_step_end=[r.t_step_end[i] for i in range(m)],
-                            message=r.message.decode(errors="replace")))
+                            message=r.message.decode(errors="replace"), scene=r.scene,
+                            t_created=r.t_created))
         return out, nr.value
 
     def clock(self):

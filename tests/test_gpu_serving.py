@@ -1,11 +1,16 @@
 """Serving: continuous batching of independent scenes through hot_batch_*.
 
-A scene's result must not depend on what else is resident: each request's
-particles after its steps, run inside a stream of overlapping requests, are
-bit-identical to the same scene stepped alone (every kernel of the step is
-deterministic: fixed-order reductions, no floating-point atomics across
-waves).  Admission must respect the HBM budget, and a request larger than
-the budget is refused.
+A scene's result must not depend on what else is resident, nor on how it is
+served: each request's particles after its steps, run inside a stream of
+overlapping requests (scenes created by the batch's slot threads from its
+device pool, V-cycles launched as captured HIP graphs, or scenes created by
+the loop and stepped eagerly), are bit-identical to the same scene stepped
+alone and eagerly (every kernel of the step is deterministic: fixed-order
+reductions, no floating-point atomics across waves).  A captured V-cycle
+graph is replayed at every quasi-Newton iteration of a step, with the
+iteration's eager kernels and host synchronisations between replays, and the
+step must equal the eager step bit for bit.  Admission must respect the HBM
+budget, and a request larger than the budget is refused.
 """
 import numpy as np
 import pytest
@@ -38,9 +43,11 @@ def alone(hot, sc, precision, smoother=0):
         g.close()
 
 
+@pytest.mark.parametrize("submit,graph", [(True, True), (False, False)],
+                         ids=["submitted-graph", "loop-created-eager"])
 @pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (1, 1)],
                          ids=["fp64", "mixed", "mixed-gauss-seidel"])
-def test_results_identical_alone_and_in_the_mix(precision, smoother):
+def test_results_identical_alone_and_in_the_mix(precision, smoother, submit, graph):
     hot, serving = _mods()
     reqs = small_requests()
     ref = [alone(hot, sc, precision, smoother) for sc in reqs]
@@ -52,7 +59,7 @@ def test_results_identical_alone_and_in_the_mix(precision, smoother):
     arrivals = serving.poisson_arrivals(N_REQ, rate=200.0, seed=7)
     records, summary, trace = serving.serve(reqs, arrivals, budget_bytes=8 << 30, max_slots=4,
                                             precision=precision, n_steps=STEPS, collect=collect,
-                                            smoother=smoother)
+                                            smoother=smoother, submit=submit, graph=graph)
     print(summary, trace)
     assert len(records) == N_REQ and summary["failed"] == 0
     assert trace["peak_resident"] > 1, "requests never overlapped"
@@ -93,3 +100,30 @@ def test_oversized_request_is_refused():
     finally:
         b.close()
         g.close()
+
+
+@pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (0, 1), (1, 1)],
+                         ids=["fp64", "mixed", "fp64-gauss-seidel", "mixed-gauss-seidel"])
+def test_graph_vcycle_steps_equal_eager_steps(precision, smoother):
+    """Three steps of a three-level scene with the V-cycle captured as a HIP
+    graph (recaptured at every step, replayed at every iteration) against the
+    same steps run eagerly: identical decisions and bit-identical particles."""
+    hot, _ = _mods()
+    sc = hs.twisting_bars(side=4, length=24, n_steps=3)
+    sc.mg_levels = 3
+    out = []
+    for graph in (0, 1):
+        g = hot.Scene.from_scene(sc, precision=precision, smoother=smoother, graph=graph)
+        try:
+            its = []
+            for _ in range(3):
+                g.step()
+                its.append((g.stats["iters"], g.stats["cg_iters_total"]))
+            out.append((its, g.read()))
+        finally:
+            g.close()
+    (ie, re_), (ig, rg) = out
+    print("eager", ie, "graph", ig)
+    assert ie == ig
+    for f in ("x", "v", "F", "C"):
+        assert np.array_equal(re_[f], rg[f]), f

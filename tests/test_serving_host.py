@@ -20,6 +20,19 @@ def test_step_latencies_chain_from_admission():
     assert serving.step_latencies(rec) == [0.5, 0.25, 1.25]
 
 
+def test_first_step_latency_starts_when_the_scene_is_ready():
+    # a scene the batch created: the first step became eligible at t_created,
+    # and the creation time is reported on its own
+    rec = dict(t_admit=1.0, t_created=1.2, t_step_end=[1.5, 1.75], steps=2, iters=5, status=0,
+               t_arrival=0.5)
+    lat = serving.step_latencies(rec)
+    assert abs(lat[0] - 0.3) < 1e-12 and abs(lat[1] - 0.25) < 1e-12
+    s = serving.summarize([rec], t_begin=0.5)
+    assert abs(s["scene_creation_ms"]["p50"] - 200.0) < 1e-9
+    assert abs(s["admission_wait_ms"]["p50"] - 500.0) < 1e-9
+    assert abs(s["request_latency_ms"]["p50"] - 1250.0) < 1e-9
+
+
 def test_summary_percentiles_and_throughput():
     recs = []
     for k in range(100):
