@@ -226,10 +226,12 @@ hot_status hot_step_noalloc(hot_scene* scene, double dt, hot_step_stats* stats);
 /* ---- serving: continuous batching of independent scenes ------------------
  * Steps of many independent scenes (the paper's per-frame solve applied to
  * a stream of requests) share one GPU.  A batch owns an HBM budget and
- * max_slots slots (1 to 16; HOT_E_INVALID otherwise), each served by one
- * host thread.  At most 16 scenes may step at once on one device, in a batch
- * or on the caller's own streams: each coarsest-level solve that uses grid
- * barriers takes at most 1/16 of the device's resident work-groups.  hot_batch_add admits a
+ * max_slots slots (1 to 64; HOT_E_INVALID otherwise), each served by one
+ * host thread.  Any number of scenes may step at once, in batches or on the
+ * caller's own threads and streams: a coarsest-level solve that uses grid
+ * barriers takes at most 1/16 of the device's resident work-groups, and the
+ * library lets at most 16 of them run at once per device (a step's solve
+ * holds one of 16 tickets and waits for one when all are taken).  hot_batch_add admits a
  * scene with a number of steps to run when a slot is free and the larger of
  * the scene's live bytes and its footprint estimate fits in the budget that
  * resident scenes leave; otherwise it returns HOT_E_NOMEM and the caller

@@ -22,6 +22,7 @@
 
 #include "../../include/hot.h"
 #include "hot_internal.h"
+#include "tickets.h"
 
 using namespace hot;
 
@@ -138,6 +139,7 @@ struct hot_scene {
   int* herr = nullptr;
   int node_cap = 0;
   bool no_alloc = false;  // inside hot_step_noalloc: a buffer that must grow is an error
+  bool grid_ok = false;   // holds a grid-solve ticket for the current solve
   hipGraphExec_t vc_exec = nullptr;  // captured V-cycle (hot_params.graph)
   bool vc_stale = true;              // vc_exec holds an earlier step's cycle
   double cg_per_cycle = 1.0;  // last solve's coarsest-PCG iterations per V-cycle
@@ -761,7 +763,7 @@ hot_status vcycle_body(hot_scene* s, const double* q, double* r) {
                     st);
   }
   HIPCHK(launch_coarse_pcg(view(s, M - 1), mx, bs[M - 1], us[M - 1], s->pcg_work.p, pcg_log(s),
-                           500, 0.5, st));
+                           500, 0.5, s->grid_ok, st));
   for (int m = M - 2; m >= 0; --m) {
     LevelView Lm = view(s, m);
     launch_prolong_add(Lm, view(s, m + 1), mx, us[m + 1], us[m], st);
@@ -833,6 +835,45 @@ hot_status vcycle(hot_scene* s, const double* q, double* r) {
   s->vcycles++;
   return HOT_OK;
 }
+
+// ---------------------------------------------------------------- grid-solve tickets
+TicketPool* grid_tickets(int dev) {
+  static std::mutex mu;
+  static TicketPool* pools[64] = {nullptr};
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!pools[dev]) pools[dev] = new TicketPool(kGridSolves);
+  return pools[dev];
+}
+
+// Holds a grid-solve ticket of the scene's device while the scene's V-cycles
+// run, when its coarsest level uses the multi-work-group solve, waiting for
+// one if all are taken (the single-work-group form sums in another order, so
+// falling back to it would make a scene's result depend on what else runs).
+// Released after the scene's stream has drained.
+class GridTicket {
+ public:
+  explicit GridTicket(hot_scene* s) : s_(s) {
+    const LevelView Lc = view(s, s->levels - 1);
+    TicketPool* pool = grid_tickets(s->device);
+    if (pool && coarse_pcg_uses_grid(Lc, s->mixed)) {
+      pool->acquire();
+      held_ = true;
+    }
+    s->grid_ok = held_;
+  }
+  ~GridTicket() {
+    if (held_) {
+      (void)hipStreamSynchronize(s_->stream);
+      grid_tickets(s_->device)->release();
+    }
+    s_->grid_ok = false;
+  }
+
+ private:
+  hot_scene* s_;
+  bool held_ = false;
+};
 
 // ---------------------------------------------------------------- solve
 hot_status eval_trial(hot_scene* s, const double* dv, const double* p, double alpha, int out) {
@@ -943,6 +984,7 @@ hot_status prof_flush(hot_scene* s) {
 // y^T s > 1e-12 |y||s|, and the node-wise CN stopping test (Sec. 5.2).
 hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
   hipStream_t st = s->stream;
+  GridTicket ticket(s);
   const int n0 = s->L[0].n;
   const long long N = (long long)n0 * 3;
   const double dt = s->dt_prepared;
@@ -1628,6 +1670,7 @@ hot_status hot_debug_apply(hot_scene* scene, int32_t op, const double* in, doubl
   double* vin = P<double>(s->vin);
   double* vout = P<double>(s->vout);
   if (op == 0) {
+    GridTicket ticket(s);
     TRY(vcycle(s, vin, vout));
   } else if (op == 1) {
     TRY(eval_trial(s, vin, nullptr, 0.0, 0));
@@ -1915,12 +1958,10 @@ struct hot_batch {
 extern "C" {
 
 hot_status hot_batch_create(size_t hbm_budget_bytes, int32_t max_slots, hot_batch** out) {
-  // A coarsest-level solve with grid barriers launches at most 1/16 of the
-  // device's resident work-groups, so 16 scenes stepping at once still have
-  // every work-group of every such solve resident; more slots could leave a
-  // solve spinning on work-groups that never start.
-  if (!out || max_slots < 1 || max_slots > 16 || hbm_budget_bytes == 0)
-    return fail(HOT_E_INVALID, "bad arguments (max_slots must be in [1, 16])");
+  // Slots beyond the 16 grid-solve tickets of the device wait for a ticket
+  // before their coarsest solves.
+  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget_bytes == 0)
+    return fail(HOT_E_INVALID, "bad arguments (max_slots must be in [1, 64])");
   hot_batch* b = new hot_batch();
   b->budget = hbm_budget_bytes;
   b->t0 = hot_batch::clock::now();

@@ -244,8 +244,15 @@ __device__ inline void log_iters(const IterLog& lg, int v) {
 }
 // Coarsest solve (relative tolerance rel in the D^-1 norm, at most max_iter
 // iterations), logging its iteration count through lg.
+// grid_ok: the caller holds a grid-solve ticket, so the multi-work-group form
+// may be used where it pays; without one the single-work-group form runs,
+// which needs coarse_pcg_single_fits (hipErrorInvalidConfiguration otherwise).
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                             IterLog lg, int max_iter, double rel, hipStream_t st);
+                             IterLog lg, int max_iter, double rel, bool grid_ok, hipStream_t st);
+// Whether the coarsest solve of this level would use the multi-work-group
+// form, and whether the single-work-group form can hold it.
+bool coarse_pcg_uses_grid(const LevelView& L, bool mixed);
+bool coarse_pcg_single_fits(const LevelView& L, bool mixed);
 // Resolve the coarsest solve's launch shapes for the current device (they
 // are cached; a stream capture must not be the first to ask).
 void coarse_pcg_warm();

@@ -1452,17 +1452,26 @@ size_t coarse_pcg_work_bytes(int n) {
 // Coarsest levels at least this large use the multi-work-group solve.
 constexpr int kGridMinRows = 128;
 
+bool coarse_pcg_uses_grid(const LevelView& L, bool mixed) {
+  const size_t lds = (size_t)5 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double));
+  const int maxb = mixed ? grid_blocks<float, false>() : grid_blocks<double, false>();
+  return (L.n >= kGridMinRows || lds > kPcgLdsMax) && maxb >= 2;
+}
+
+bool coarse_pcg_single_fits(const LevelView& L, bool mixed) {
+  return (size_t)5 * 3 * L.n * (mixed ? sizeof(float) : sizeof(double)) <= kPcgLdsMax;
+}
+
 hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void* x, void* work,
-                             IterLog lg, int max_iter, double rel, hipStream_t st) {
+                             IterLog lg, int max_iter, double rel, bool grid_ok, hipStream_t st) {
   const size_t vsz = mixed ? sizeof(float) : sizeof(double);
   const size_t lds = (size_t)5 * 3 * L.n * vsz;
   // One work-group streams the whole level matrix through one compute unit
   // per CG iteration, which is limited by that unit's outstanding memory
   // requests: it serves small levels only; levels of kGridMinRows rows or
-  // more are read by a grid of work-groups instead.
-  const int maxb = mixed ? grid_blocks<float, false>() : grid_blocks<double, false>();
-  const bool grid = L.n >= kGridMinRows || lds > kPcgLdsMax;
-  if (!grid || maxb < 2) {
+  // more are read by a grid of work-groups instead, when the caller holds a
+  // grid-solve ticket.
+  if (!grid_ok || !coarse_pcg_uses_grid(L, mixed)) {
     if (lds > kPcgLdsMax) return hipErrorInvalidConfiguration;
     if (mixed)
       k_coarse_pcg<float><<<1, kPcgThreads, lds, st>>>(L, (const float*)b, (float4*)x, lg,
@@ -1475,6 +1484,7 @@ hipError_t launch_coarse_pcg(const LevelView& L, bool mixed, const void* b, void
   const size_t vec = (size_t)6 * 3 * L.n * vsz;
   double* part = (double*)((char*)work + ((vec + 255) / 256) * 256);
   GridBar* bar = (GridBar*)(part + 2 * kCgMaxBlocks);
+  const int maxb = mixed ? grid_blocks<float, false>() : grid_blocks<double, false>();
   const int nb = std::max(2, std::min((L.n + kCgWaves - 1) / kCgWaves, maxb));
   k_reset_bar<<<1, 64, 0, st>>>(bar);
   // levels of at most kRegRows rows per wave keep their rows in registers

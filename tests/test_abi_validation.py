@@ -117,14 +117,13 @@ def test_footprint_grows_with_the_scene_and_with_mixed_blocks():
     assert fl > n0 * 1152 * 8
 
 
-@pytest.mark.parametrize("slots", [0, -1, 17, 256])
+@pytest.mark.parametrize("slots", [0, -1, 65, 256])
 def test_batch_slot_count_is_bounded(slots):
-    """A batch holds 1 to 16 slots: each coarsest-level grid-barrier solve
-    takes at most 1/16 of the device's resident work-groups, so 16 scenes
-    stepping at once keep every such solve fully resident."""
+    """A batch holds 1 to 64 slots (the grid-barrier coarsest solves are
+    limited separately, by the device's 16 tickets)."""
     hot = _hot()
     L = hot.lib()
     h = C.c_void_p()
     assert L.hot_batch_create(1 << 20, slots, C.byref(h)) == hot.HOT_E_INVALID
     assert not h.value
-    assert b"16" in L.hot_last_error()
+    assert b"64" in L.hot_last_error()

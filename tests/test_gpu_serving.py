@@ -127,3 +127,27 @@ def test_graph_vcycle_steps_equal_eager_steps(precision, smoother):
     assert ie == ig
     for f in ("x", "v", "F", "C"):
         assert np.array_equal(re_[f], rg[f]), f
+
+
+def test_more_slots_than_grid_tickets():
+    """Twenty slots of scenes whose coarsest levels use the grid-barrier
+    solve: at most 16 such solves run at once (the rest wait for a ticket),
+    and every result is still bit-identical to the scene stepped alone."""
+    hot, serving = _mods()
+    reqs = [hs.serving_scene(i, seed_base=4600, n_min=20000, n_max=40000) for i in range(24)]
+    for sc in reqs:
+        sc.mg_levels = 2  # coarsest levels of several hundred rows: grid solves
+    ref = [alone(hot, sc, 0) for sc in reqs]
+    got = {}
+
+    def collect(k, scene):
+        got[k] = scene.read()
+
+    records, summary, trace = serving.serve(reqs, np.zeros(len(reqs)), budget_bytes=32 << 30,
+                                            max_slots=20, precision=0, n_steps=STEPS,
+                                            collect=collect)
+    print(summary, trace)
+    assert summary["failed"] == 0 and trace["peak_resident"] > 16
+    for k in range(len(reqs)):
+        for f in ("x", "v"):
+            assert np.array_equal(got[k][f], ref[k][f]), f"request {k} field {f}"
