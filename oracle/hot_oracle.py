@@ -854,6 +854,109 @@ def solve(st, hz, tol, history, max_iters=500, sweeps=1, c1=1e-4, max_halvings=3
     return dv, dict(iters=it, converged=bool(converged), log=log, n_nodes=n)
 
 
+def precond_cg(A, apply_M, b, rel, max_iter, log=None):
+    """Preconditioned conjugate gradients from x0 = 0 for A x = b, stopped at
+    the first iterate with sqrt(r^T M r) <= rel * sqrt(b^T M b), where M is
+    the preconditioner's inverse as applied by ``apply_M`` (the inexact linear
+    solve of Sec. 5.3, in the preconditioner's energy norm), or after
+    max_iter iterations.  With apply_M = r / diag(A) this is the arithmetic
+    of ``coarse_pcg``."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = apply_M(r)
+    rz = float(r @ z)
+    stop = rel * math.sqrt(max(rz, 0.0))
+    it = 0
+    if rz > 0.0:
+        p = z.copy()
+        while it < max_iter:
+            q = A @ p
+            alpha = rz / float(p @ q)
+            x += alpha * p
+            r -= alpha * q
+            z = apply_M(r)
+            rz_new = float(r @ z)
+            it += 1
+            if math.sqrt(max(rz_new, 0.0)) <= stop:
+                break
+            beta = rz_new / rz
+            rz = rz_new
+            p = z + beta * p
+    if log is not None:
+        log.append(it)
+    return x
+
+
+def inexact_tolerance(r0Mr0, tau):
+    """Relative tolerance of a Newton step's linear solve (Sec. 5.3, adaptive
+    inexactness): k = min(1/2, sqrt(max(sqrt(r0^T M r0), tau))), with M the
+    preconditioner (its energy norm scales the residual by the local
+    stiffness) and tau the floor; the reading used is tau = the CN
+    tolerance eps."""
+    return min(0.5, math.sqrt(max(math.sqrt(max(r0Mr0, 0.0)), tau)))
+
+
+def solve_pn(st, tol, levels, precond="jacobi", max_iters=500, cg_max_iter=10000, sweeps=1,
+             c1=1e-4, max_halvings=30, smoother="l1jacobi"):
+    """Projected Newton with inexact preconditioned CG (Alg. 1, the inexact
+    Newton-Krylov baseline; PN-PCG with precond="jacobi", PN-MGPCG with
+    precond="mg", Sec. 5.1 and Sec. 7).
+
+    dv^1 = 0; while the CN-scaled gradient norm exceeds eps*sqrt(n): the
+    projected Hessian at dv^i (Teran et al. 2005 projection, Dirichlet
+    projection), its linear system H p = -g solved by CG from 0 to the
+    adaptive relative tolerance k (preconditioner: the scalar diagonal, or
+    one V-cycle of the Galerkin hierarchy rebuilt from this Hessian), then
+    the same backtracking line search as HOT."""
+    n = st.lev0.n
+    dv = np.zeros((n, 3))
+    g = gradient(st, dv)
+    ep, en = energy_terms(st, dv)
+    log = dict(cn=[], alpha_halvings=[], cg=[], k=[], E=[])
+    thresh = tol * math.sqrt(n)
+    cn = cn_norm(st, g)
+    log["cn"].append(cn)
+    log["E"].append(float(np.sum(ep) + np.sum(en)))
+    it = 0
+    converged = cn <= thresh
+    while not converged and it < max_iters:
+        H, nbr = hessian_slots(st, dv=dv)
+        hz = build_hierarchy(st, H, nbr, levels if precond == "mg" else 1, project_pattern=False)
+        b = -g.ravel() * hz.free[0]
+        if precond == "mg":
+            apply_M = lambda r: vcycle(hz, r, sweeps=sweeps, smoother=smoother)
+        else:
+            apply_M = lambda r: r / hz.diag[0]
+        k = inexact_tolerance(float(b @ apply_M(b)), tol)
+        cg_log = []
+        p = precond_cg(hz.A[0], apply_M, b, k, cg_max_iter, log=cg_log).reshape(n, 3)
+        gp = float(np.sum(g * p))
+        alpha = 1.0
+        accepted = False
+        halvings = 0
+        for halvings in range(max_halvings + 1):
+            dv_t = dv + alpha * p
+            ep_t, en_t = energy_terms(st, dv_t)
+            dE = float(np.sum(ep_t - ep) + np.sum(en_t - en))
+            if np.isfinite(dE) and dE <= c1 * alpha * gp:
+                accepted = True
+                break
+            alpha *= 0.5
+        log["alpha_halvings"].append(halvings if accepted else -1)
+        log["cg"].append(cg_log[0])
+        log["k"].append(k)
+        if not accepted:
+            break
+        dv, ep, en = dv_t, ep_t, en_t
+        g = gradient(st, dv)
+        it += 1
+        cn = cn_norm(st, g)
+        log["cn"].append(cn)
+        log["E"].append(float(np.sum(ep) + np.sum(en)))
+        converged = cn <= thresh
+    return dv, dict(iters=it, converged=bool(converged), log=log, n_nodes=n)
+
+
 def von_mises(F, mu, ys):
     """Von Mises return mapping on the Hencky strain, applied once per step
     after the solve (lagged plasticity, Sec. 2 and Sec. 8).  Deviatoric log
@@ -929,8 +1032,10 @@ def g2p(st, dv):
 
 
 def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=None,
-         sweeps=1, return_internals=False, smoother="l1jacobi"):
-    """One implicit MPM step: P2G, HOT solve for dv, G2P (Sec. 3.1, Alg. HOT)."""
+         sweeps=1, return_internals=False, smoother="l1jacobi", solver="hot"):
+    """One implicit MPM step: P2G, the solve for dv, G2P (Sec. 3.1).  solver:
+    "hot" (Alg. HOT), "pn-pcg" or "pn-mgpcg" (Alg. 1 with the diagonal or the
+    multigrid preconditioner)."""
     if dt is None or dt <= 0:
         dt = time_step(scene)
     levels = scene.mg_levels if levels is None else levels
@@ -938,6 +1043,15 @@ def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=N
     tol = scene.tol if tol is None else tol
     max_iters = scene.max_iters if max_iters is None else max_iters
     st = prepare(scene, dt, t)
+    if solver != "hot":
+        assert solver in ("pn-pcg", "pn-mgpcg")
+        dv, info = solve_pn(st, tol, levels, "mg" if solver == "pn-mgpcg" else "jacobi",
+                            max_iters=max_iters, sweeps=sweeps, smoother=smoother)
+        out = g2p(st, dv)
+        info["dt"] = dt
+        if return_internals:
+            return out, info, dict(st=st, dv=dv)
+        return out, info
     H0, nbr0 = hessian_slots(st)
     hz = build_hierarchy(st, H0, nbr0, levels)
     dv, info = solve(st, hz, tol, history, max_iters=max_iters, sweeps=sweeps,
