@@ -231,6 +231,37 @@ def sphere_slab(seed=3000, n=192, slab=(160, 40, 160), y0=24, radius=0.1, speed=
                      tol=1e-6, lbfgs_history=8, mg_levels=levels, n_steps=n_steps)
 
 
+def stiffness_bar(E_mid=1e5, side=8, length=96, seed=5000, E_end=1e5, levels=3,
+                  n_steps=10) -> Scene:
+    """A three-material bar twisted by opposite grips at +-2 rad/s: the two
+    end thirds keep E = E_end and the middle third has E = E_mid (the paper's
+    varying-stiffness experiment raises it from 1e5 to 1e10 Pa).  FCR,
+    nu = 0.3, density 1000; dx = 1/64, grid of (length + 16) x 32 x 32 cells,
+    bar along x from cell 8, centred in y and z, gravity on, sticky walls
+    two cells thick."""
+    dx = 1.0 / 64.0
+    cells = (length + 16, 32, 32)
+    x0, x1 = 8, 8 + length
+    y0 = z0 = (32 - side) // 2
+    t1, t2 = x0 + length // 3, x0 + 2 * length // 3
+    blocks = [((x0, y0, z0), (t1, y0 + side, z0 + side), 0, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+              ((t1, y0, z0), (t2, y0 + side, z0 + side), 1, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+              ((t2, y0, z0), (x1, y0 + side, z0 + side), 2, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))]
+    mats = [material(FCR, E_end, 0.3, 1000.0), material(FCR, E_mid, 0.3, 1000.0),
+            material(FCR, E_end, 0.3, 1000.0)]
+    axis_pt = np.array([0.0, (y0 + side / 2.0) * dx, (z0 + side / 2.0) * dx])
+    ylo, yhi = (y0 - 2) * dx, (y0 + side + 2) * dx
+    zlo, zhi = (z0 - 2) * dx, (z0 + side + 2) * dx
+    bcs = [bc_walls(2),
+           bc_grip(((x0 - 2) * dx, ylo, zlo), ((x0 + 4) * dx, yhi, zhi), axis_pt, (1.0, 0.0, 0.0),
+                   +2.0),
+           bc_grip(((x1 - 4) * dx, ylo, zlo), ((x1 + 2) * dx, yhi, zhi), axis_pt, (1.0, 0.0, 0.0),
+                   -2.0)]
+    return _assemble(f"stiffness_bar_{E_mid:g}", dx, cells, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0),
+                     blocks, mats, bcs, seed, 0.0, tol=1e-6, lbfgs_history=8, mg_levels=levels,
+                     n_steps=n_steps)
+
+
 def serving_scene(index: int, seed_base=4000, n_min=4096, n_max=262144, dx=0.01) -> Scene:
     """One request of the serving stream: a random spinning FCR box.
 
@@ -298,6 +329,7 @@ def small_box(cells=(8, 8, 8), box_lo=(2, 2, 2), box_hi=(5, 6, 5), dx=0.1, seed=
 
 CONFIGS = {
     "rotating_cube": rotating_cube,
+    "stiffness_bar": stiffness_bar,
     "twisting_bars": twisting_bars,
     "sphere_slab": sphere_slab,
 }

@@ -67,6 +67,21 @@ typedef enum { HOT_FP64 = 0, HOT_MIXED = 1 } hot_precision;
  * smoother_sweeps counts sweeps (Jacobi) or forward-backward pairs (SGS). */
 typedef enum { HOT_SMOOTH_L1_JACOBI = 0, HOT_SMOOTH_SGS = 1 } hot_smoother;
 
+/* Solver of the step's minimisation.
+ * HOT_SOLVER_HOT (0, the default): Alg. HOT, L-BFGS whose initial inverse
+ *   Hessian is one V-cycle of the start-of-step Galerkin hierarchy.
+ * HOT_SOLVER_PN_PCG (1): the paper's baseline of Alg. 1, projected Newton
+ *   whose linear systems H(dv) p = -g are solved by CG preconditioned with
+ *   the scalar diagonal, to the adaptive relative tolerance
+ *   k = min(1/2, sqrt(max(sqrt(r0^T M r0), tau))) of Sec. 5.3 (tau = tol;
+ *   at most 10,000 CG iterations); mg_levels is ignored.
+ * HOT_SOLVER_PN_MGPCG (2): the same with one V-cycle (smoother and levels as
+ *   set) as the preconditioner, the hierarchy rebuilt from each Newton
+ *   iteration's Hessian (Sec. 5.1).
+ * For the Newton solvers, hot_step_stats.iters counts Newton iterations and
+ * cg_iters_total the CG iterations of their linear solves. */
+typedef enum { HOT_SOLVER_HOT = 0, HOT_SOLVER_PN_PCG = 1, HOT_SOLVER_PN_MGPCG = 2 } hot_solver;
+
 typedef struct {
   int32_t model;        /* hot_model */
   double E;             /* Young's modulus, Pa, > 0 */
@@ -133,7 +148,7 @@ typedef struct {
                               launched once per cycle; same kernels and
                               results as 0, fewer launches from the host).
                               Ignored while kernel tracing is on. */
-  int32_t reserved;        /* must be zero */
+  int32_t solver;          /* hot_solver */
 } hot_params;
 
 typedef struct {

@@ -335,6 +335,22 @@ __global__ void k_bj_apply(int n, const double* __restrict__ Dinv, const double*
   for (int g = 0; g < 3; ++g) y[3 * i + g] = sign * (D[3 * g] * x0 + D[3 * g + 1] * x1 + D[3 * g + 2] * x2);
 }
 
+// Conjugate-gradient vector updates of the Newton-Krylov solve: y += a x,
+// y = x + b y, and the diagonal preconditioner z = r / d.
+__global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+__global__ void k_xpby(long long n, const double* __restrict__ x, double b, double* __restrict__ y) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] + b * y[i];
+}
+__global__ void k_diag_solve(long long n, const double* __restrict__ d, const double* __restrict__ r,
+                             double* __restrict__ z) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = r[i] / d[i];
+}
+
 __global__ void k_fill_d(long long n, double* p, double v) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
@@ -342,6 +358,16 @@ __global__ void k_fill_d(long long n, double* p, double v) {
 __global__ void k_rho(const double* ys, double* rho) { rho[0] = 1.0 / ys[0]; }
 
 }  // namespace
+
+void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st) {
+  if (n > 0) k_axpy<<<blocks_for(n), kTpb, 0, st>>>(n, a, x, y);
+}
+void launch_xpby(long long n, const double* x, double b, double* y, hipStream_t st) {
+  if (n > 0) k_xpby<<<blocks_for(n), kTpb, 0, st>>>(n, x, b, y);
+}
+void launch_diag_solve(long long n, const double* d, const double* r, double* z, hipStream_t st) {
+  if (n > 0) k_diag_solve<<<blocks_for(n), kTpb, 0, st>>>(n, d, r, z);
+}
 
 void launch_fill_double(long long n, double* p, double v, hipStream_t st) {
   if (n > 0) k_fill_d<<<blocks_for(n), kTpb, 0, st>>>(n, p, v);

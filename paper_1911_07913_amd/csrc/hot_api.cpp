@@ -332,7 +332,9 @@ hot_status validate_params(const hot_params* p) {
   if (p->smoother != HOT_SMOOTH_L1_JACOBI && p->smoother != HOT_SMOOTH_SGS)
     return fail(HOT_E_INVALID, "unknown smoother");
   if (p->graph != 0 && p->graph != 1) return fail(HOT_E_INVALID, "graph must be 0 or 1");
-  if (p->reserved) return fail(HOT_E_INVALID, "reserved field must be zero");
+  if (p->solver != HOT_SOLVER_HOT && p->solver != HOT_SOLVER_PN_PCG &&
+      p->solver != HOT_SOLVER_PN_MGPCG)
+    return fail(HOT_E_INVALID, "unknown solver");
   return HOT_OK;
 }
 
@@ -584,6 +586,8 @@ hot_status alloc_nodes0(hot_scene* s, int n) {
   return HOT_OK;
 }
 
+hot_status build_hessian(hot_scene* s, const double* dv);
+
 // Binning, active grid and hierarchy index sets, P2G, level-0 Hessian and the
 // Galerkin hierarchy: everything of a step that precedes the solve.
 hot_status prepare(hot_scene* s, double dt) {
@@ -656,10 +660,27 @@ hot_status prepare(hot_scene* s, double dt) {
              P<int>(s->counts), P<double>(s->bpartial), dt, s->t + dt, P<double>(s->mass),
              P<double>(s->vstar), P<double>(s->xi), P<int>(s->fixed), st);
   HIPCHK(hipEventRecord(s->ev[1], st));
-  // -- level-0 Hessian at dv = 0 and the Galerkin hierarchy
+  s->dt_prepared = dt;
+  TRY(build_hessian(s, nullptr));
+  launch_fill_int(1, pcg_log(s).cursor, 0, st);
+  s->prepared = true;
+  s->vcycles = 0;
+  return HOT_OK;
+}
+
+// Level-0 projected Hessian at dv (NULL: dv = 0, Alg. HOT's start-of-step
+// Hessian) and, for levels > 1, its Galerkin hierarchy with the smoother
+// data and the coarsest solve's work space.
+hot_status build_hessian(hot_scene* s, const double* dv) {
+  hipStream_t st = s->stream;
+  const int n = s->n;
+  Particles& pt = s->P[s->cur];
+  LevelView L0 = view(s, 0);
+  const double dt = s->dt_prepared;
+  s->vc_stale = true;  // the matrices change
   PROF(s, HOT_PROF_PHESS,
        launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
-                               pt.mat, P<double>(s->vstar), dt, P<double>(s->wnode),
+                               pt.mat, P<double>(s->vstar), dv, dt, P<double>(s->wnode),
                                P<double>(s->Cp), st));
   PROF(s, HOT_PROF_ASSEMBLE,
        launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, n, P<double>(s->f), pt.F,
@@ -702,12 +723,8 @@ hot_status prepare(hot_scene* s, double dt) {
   size_t pcg = coarse_pcg_work_bytes(s->L[s->levels - 1].n);
   TRY(ensure(s, s->pcg_work, pcg));
   TRY(ensure(s, s->pcg_iters, pcg_log_bytes(s->prm.max_iters)));
-  launch_fill_int(1, pcg_log(s).cursor, 0, st);
   if (s->prm.graph) coarse_pcg_warm();
   HIPCHK(hipGetLastError());
-  s->prepared = true;
-  s->dt_prepared = dt;
-  s->vcycles = 0;
   return HOT_OK;
 }
 
@@ -1180,6 +1197,163 @@ hot_status solve(hot_scene* s, hot_step_stats* stats, bool* converged) {
   return HOT_OK;
 }
 
+// Projected Newton with inexact preconditioned CG (Alg. 1): PN-PCG with the
+// scalar diagonal as preconditioner, PN-MGPCG with one V-cycle of the
+// Galerkin hierarchy rebuilt from each Newton iteration's Hessian (Sec. 5.1).
+// Each iteration solves H(dv) p = -g by CG from 0 to the relative tolerance
+// k = min(1/2, sqrt(max(sqrt(r0^T M r0), eps))) in the preconditioner's
+// energy norm (Sec. 5.3, tau read as the CN tolerance eps; at most 10,000 CG
+// iterations), then runs HOT's backtracking line search.  Logged per
+// iteration: step-length halvings and CG iterations.
+constexpr int kPnCgMax = 10000;
+
+hot_status solve_pn(hot_scene* s, hot_step_stats* stats, bool* converged) {
+  hipStream_t st = s->stream;
+  const int n0 = s->L[0].n;
+  const long long N = (long long)n0 * 3;
+  const double dt = s->dt_prepared;
+  const double cn_scale = 24.0 * s->prm.dx * s->prm.dx * dt;
+  const double thresh = s->prm.tol * std::sqrt((double)n0);
+  const bool mg = s->prm.solver == HOT_SOLVER_PN_MGPCG;
+  double* dscal = P<double>(s->dscal);
+  double* partial = P<double>(s->partial);
+  double* dv = P<double>(s->dv);
+  double* g = P<double>(s->g);
+  // CG vectors: direction x, residual r, preconditioned residual z, search
+  // direction p, product q
+  double* x = P<double>(s->r);
+  double* r = P<double>(s->q);
+  double* z = P<double>(s->vin);
+  double* p = P<double>(s->vout);
+  double* q = P<double>(s->gnew);
+  LevelView L0 = view(s, 0);
+  const double* d0 = P<double>(s->L[0].diag);
+  s->log_int.clear();
+  s->log_cn.clear();
+  launch_fill_double(N, dv, 0.0, st);
+  s->pc = 0;
+  TRY(eval_trial(s, dv, nullptr, 0.0, s->pc));
+  launch_sum(s->n, P<double>(s->psi[s->pc]), partial, dscal + S_E0, st);
+  TRY(gradient(s, dv, s->pc, g));
+  launch_cn_sq(n0, g, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
+  TRY(readback(s));
+  double E = s->hscal[S_E0];
+  double cn = std::sqrt(s->hscal[S_CN]);
+  if (!std::isfinite(E) || !std::isfinite(cn))
+    return fail(HOT_E_NONFINITE, "non-finite energy or gradient at dv = 0");
+  if (stats) {
+    stats->E0 = E;
+    stats->cn0 = cn;
+    stats->cn_tol = thresh;
+  }
+  s->log_cn.push_back(cn);
+  auto precondition = [&](const double* rr, double* zz) -> hot_status {
+    if (mg) return vcycle(s, rr, zz);
+    launch_diag_solve(N, d0, rr, zz, st);
+    return HOT_OK;
+  };
+  auto dot = [&](const double* a, const double* b, double* out) -> hot_status {
+    launch_dot(N, a, b, partial, dscal + S_GP, st);
+    TRY(readback(s));
+    *out = s->hscal[S_GP];
+    return HOT_OK;
+  };
+  int it = 0, backtracks = 0, cg_total = 0;
+  bool conv = cn <= thresh;
+  while (!conv && it < s->prm.max_iters) {
+    if (it > 0) {
+      TRY(build_hessian(s, dv));
+      L0 = view(s, 0);
+    }
+    // CG from 0 for H p = -g (g is zero on constrained DOFs)
+    launch_fill_double(N, x, 0.0, st);
+    launch_scale_copy(N, -1.0, g, r, st);
+    TRY(precondition(r, z));
+    double rz = 0.0;
+    TRY(dot(r, z, &rz));
+    const double k = std::min(0.5, std::sqrt(std::max(std::sqrt(std::max(rz, 0.0)), s->prm.tol)));
+    const double stop = k * std::sqrt(std::max(rz, 0.0));
+    int cgi = 0;
+    if (rz > 0.0) {
+      launch_scale_copy(N, 1.0, z, p, st);
+      while (cgi < kPnCgMax) {
+        launch_spmv(L0, p, q, st);
+        double pq = 0.0;
+        TRY(dot(p, q, &pq));
+        const double alpha = rz / pq;
+        launch_axpy(N, alpha, p, x, st);
+        launch_axpy(N, -alpha, q, r, st);
+        TRY(precondition(r, z));
+        double rzn = 0.0;
+        TRY(dot(r, z, &rzn));
+        ++cgi;
+        if (std::sqrt(std::max(rzn, 0.0)) <= stop) break;
+        const double beta = rzn / rz;
+        rz = rzn;
+        launch_xpby(N, z, beta, p, st);
+      }
+    }
+    cg_total += cgi;
+    // line search along x, as in HOT
+    double gp = 0.0;
+    TRY(dot(g, x, &gp));
+    int trial = 1 - s->pc;
+    double alpha = 1.0;
+    bool accepted = false;
+    int halvings = 0;
+    double dE = 0.0;
+    for (halvings = 0; halvings <= 30; ++halvings) {
+      TRY(eval_trial(s, dv, x, alpha, trial));
+      launch_energy_delta(s->n, P<double>(s->psi[trial]), P<double>(s->psi[s->pc]), n0,
+                          P<double>(s->mass), dv, x, alpha, partial, dscal + S_DEP, st);
+      TRY(readback(s));
+      dE = s->hscal[S_DEP] + s->hscal[S_DEK];
+      if (std::isfinite(dE) && dE <= 1e-4 * alpha * gp) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) {
+      s->log_int.insert(s->log_int.end(), {-1, 0, 0, cgi});
+      break;
+    }
+    backtracks += halvings;
+    launch_axpy(N, alpha, x, dv, st);
+    s->pc = trial;
+    TRY(gradient(s, dv, s->pc, g));
+    launch_cn_sq(n0, g, P<double>(s->xi), cn_scale, partial, dscal + S_CN, st);
+    TRY(readback(s));
+    E += dE;
+    cn = std::sqrt(s->hscal[S_CN]);
+    if (!std::isfinite(cn)) return fail(HOT_E_NONFINITE, "non-finite gradient");
+    s->log_cn.push_back(cn);
+    s->log_int.insert(s->log_int.end(), {halvings, 0, 0, cgi});
+    ++it;
+    conv = cn <= thresh;
+  }
+  if (mg) {  // the V-cycles' coarsest solves all completed
+    const int nv = std::min(s->vcycles, pcg_log_cap(s) + 1);
+    std::vector<int> pcg(std::max(nv, 1), 0);
+    if (nv > 0) {
+      HIPCHK(hipMemcpyAsync(pcg.data(), s->pcg_iters.p, nv * 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    for (int v = 0; v < nv; ++v)
+      if (pcg[v] < 0) return fail(HOT_E_DEVICE, "coarsest solve: grid barrier timed out");
+  }
+  *converged = conv;
+  if (stats) {
+    stats->E = E;
+    stats->cn = cn;
+    stats->iters = it;
+    stats->backtracks = backtracks;
+    stats->cg_iters_total = cg_total;
+    stats->converged = conv ? 1 : 0;
+  }
+  return HOT_OK;
+}
+
 hot_status choose_dt(hot_scene* s, double dt_in, double* dt_out) {
   if (dt_in > 0.0) {
     *dt_out = dt_in;
@@ -1203,7 +1377,14 @@ hot_status do_step(hot_scene* s, double dt_in, hot_step_stats* stats) {
   TRY(prepare(s, dt));
   HIPCHK(hipEventRecord(s->ev[2], st));
   bool conv = false;
-  TRY(solve(s, stats, &conv));
+  if (s->prm.solver == HOT_SOLVER_HOT) {
+    TRY(solve(s, stats, &conv));
+  } else if (s->prm.solver == HOT_SOLVER_PN_MGPCG) {
+    GridTicket ticket(s);
+    TRY(solve_pn(s, stats, &conv));
+  } else {
+    TRY(solve_pn(s, stats, &conv));
+  }
   HIPCHK(hipEventRecord(s->ev[3], st));
   Particles& pt = s->P[s->cur];
   launch_g2p(s->sd, view(s, 0), s->n, P<double>(s->f), P<int>(s->key), pt.x, pt.v, pt.C, pt.F,
@@ -1362,7 +1543,8 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     return bail(fail(HOT_E_DEVICE, "pinned host allocation failed"));
   s->n = (int)n;
   s->mixed = params->precision == HOT_MIXED;
-  s->levels = params->mg_levels;
+  // PN-PCG's diagonal preconditioner needs no coarse levels
+  s->levels = params->solver == HOT_SOLVER_PN_PCG ? 1 : params->mg_levels;
   s->mats.assign(mats, mats + n_mats);
   s->bcs.assign(bcs, bcs + n_bcs);
   s->bc_speed = bc_max_speed(s->bcs);

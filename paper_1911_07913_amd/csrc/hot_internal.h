@@ -177,10 +177,11 @@ void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const d
 // (v* + dv + alpha p) into `wnode`, a double4 array over the padded level-0
 // grid, so each particle gathers 27 nodes with two loads per node and no map
 // lookup.
+// projected stress derivative of each particle at F(dv) (dv = NULL: dv = 0)
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
-                             const double* vstar, double dt, double* wnode, double* Cp,
-                             hipStream_t st);
+                             const double* vstar, const double* dv, double dt, double* wnode,
+                             double* Cp, hipStream_t st);
 // energy/stress at dv + alpha*p: psi_out[n] = V_p psi, S_out[9n] = V_p P F^n^T
 void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
                           const int* key, const double* F, const double* vol, const int* mat,
@@ -309,6 +310,10 @@ void launch_to_f32(long long n, const double* x, float* y, hipStream_t st);
 void launch_block_jacobi_apply(int n, const double* Dinv, const double* x, double* y, double sign,
                                hipStream_t st);
 void launch_fill_double(long long n, double* p, double v, hipStream_t st);
+// y += a x;  y = x + b y;  z = r / d (elementwise)
+void launch_axpy(long long n, double a, const double* x, double* y, hipStream_t st);
+void launch_xpby(long long n, const double* x, double b, double* y, hipStream_t st);
+void launch_diag_solve(long long n, const double* d, const double* r, double* z, hipStream_t st);
 void launch_rho(const double* ys, double* rho, hipStream_t st);
 
 }  // namespace hot

@@ -841,9 +841,9 @@ static void node_vel(const LevelView& L0, const double* vstar, const double* dv,
 
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
-                             const double* vstar, double dt, double* wnode, double* Cp,
-                             hipStream_t st) {
-  node_vel(L0, vstar, nullptr, nullptr, 0.0, wnode, st);
+                             const double* vstar, const double* dv, double dt, double* wnode,
+                             double* Cp, hipStream_t st) {
+  node_vel(L0, vstar, dv, nullptr, 0.0, wnode, st);
   if (n > 0)
     k_particle_hessian<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat,
                                                        (const double4*)wnode, dt, Cp);

@@ -24,6 +24,9 @@ HOT_FP64 = 0
 HOT_MIXED = 1
 HOT_SMOOTH_L1_JACOBI = 0
 HOT_SMOOTH_SGS = 1
+HOT_SOLVER_HOT = 0
+HOT_SOLVER_PN_PCG = 1
+HOT_SOLVER_PN_MGPCG = 2
 
 DBG_PERM = 1
 DBG_LEVEL_NODES = 10
@@ -93,7 +96,7 @@ class hot_params(C.Structure):
                 ("tol", C.c_double), ("lbfgs_history", C.c_int32), ("mg_levels", C.c_int32),
                 ("max_iters", C.c_int32), ("smoother_sweeps", C.c_int32),
                 ("precision", C.c_int32), ("smoother", C.c_int32),
-                ("graph", C.c_int32), ("reserved", C.c_int32)]
+                ("graph", C.c_int32), ("solver", C.c_int32)]
 
 
 class hot_step_stats(C.Structure):
@@ -196,7 +199,7 @@ def _dp(a):
 
 def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol=1e-6,
                 lbfgs_history=8, mg_levels=3, max_iters=500, smoother_sweeps=1,
-                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI, graph=0):
+                precision=HOT_FP64, smoother=HOT_SMOOTH_L1_JACOBI, graph=0, solver=0):
     p = hot_params()
     p.dx = dx
     for a in range(3):
@@ -208,6 +211,7 @@ def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol
     p.smoother_sweeps, p.precision = int(smoother_sweeps), int(precision)
     p.smoother = int(smoother)
     p.graph = int(graph)
+    p.solver = int(solver)
     return p
 
 
