@@ -366,6 +366,43 @@ def smoother_summary(r, steps, precision):
             "vcycle_roofline": vcycle_roofline(r["prof"], precision)}
 
 
+def stiffness_sweep(steps=3):
+    """The varying-stiffness experiment (Sec. 7): a three-material bar (ends
+    E = 1e5 Pa, middle E = 1e5 .. 1e10 Pa, 49,152 particles) twisted by its
+    grips, stepped with HOT, LBFGS-H (HOT with one level: the level-0
+    Jacobi-PCG as initial inverse Hessian), PN-PCG and PN-MGPCG; FP64, ms per
+    step and iterations (quasi-Newton or Newton; CG iterations of the Newton
+    solves, coarsest-PCG iterations of the quasi-Newton ones)."""
+    import torch
+
+    import hot_scenes as hs
+    from paper_1911_07913_amd import hot
+    out = []
+    for E in (1e5, 1e6, 1e7, 1e8, 1e9, 1e10):
+        row = {"E_mid": E}
+        for name, kw in (("hot", {}), ("lbfgs_h", dict(mg_levels=1)),
+                         ("pn_pcg", dict(solver=hot.HOT_SOLVER_PN_PCG)),
+                         ("pn_mgpcg", dict(solver=hot.HOT_SOLVER_PN_MGPCG))):
+            sc = hs.stiffness_bar(E_mid=E)
+            g = hot.Scene.from_scene(sc, **kw)
+            its, cgs = [], []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.step()
+                its.append(g.stats["iters"])
+                cgs.append(g.stats["cg_iters_total"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g.close()
+            row[name] = {"ms_per_step": 1000.0 * (t1 - t0) / steps, "iters": its, "cg_iters": cgs}
+        row["particles"] = sc.n
+        out.append(row)
+    return {"workload": "stiffness_bar: 3-material FCR bar 96x8x8 cells (ends 1e5 Pa), grips at "
+                        "+-2 rad/s, 112x32x32 grid dx=1/64, 3 levels, eps=1e-6, "
+                        f"{steps} steps per solver and stiffness", "rows": out}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """One plain device-to-device copy of a known size (for scaling HBM
     counters read under the profiler)."""
@@ -400,6 +437,8 @@ def main():
                     help="skip the same job with the coloured Gauss-Seidel smoother")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the 8.2M-particle sphere-slab job")
+    ap.add_argument("--no-stiffness", action="store_true",
+                    help="skip the varying-stiffness bar with the four solvers")
     ap.add_argument("--no-mixed-error", action="store_true",
                     help="skip the per-step mixed-vs-FP64 error pass (untimed)")
     ap.add_argument("--cpu-worker", action="store_true")
@@ -498,6 +537,8 @@ def main():
         line["sphere_slab_8M"] = {"workload": "sphere_slab: FCR von Mises slab 160x40x160 cells, "
                                   "8192000 particles, 192^3 grid dx=1/192, 4-level Galerkin MG, "
                                   "rigid sphere at 3 m/s, 30 steps", **slab}
+    if not a.no_stiffness:
+        line["stiffness_sweep"] = stiffness_sweep()
     if a.serving_requests > 0:
         sp = {"fp64": [hot.HOT_FP64], "mixed": [hot.HOT_MIXED],
               "both": [hot.HOT_MIXED, hot.HOT_FP64]}[a.serving_precision]
