@@ -68,6 +68,19 @@ def workload_name(side, smoother="l1 block-Jacobi"):
             f"L-BFGS w=8, CN eps=1e-6")
 
 
+def hs_sweeps(side):
+    """Smoothing sweeps the twisting-bars scene is stepped with."""
+    import inspect
+
+    import hot_scenes as hs
+    return inspect.signature(hs.twisting_bars).parameters["sweeps"].default
+
+
+def smoother_label(sgs, sweeps):
+    return ("coloured symmetric Gauss-Seidel (1 forward-backward pair)" if sgs else
+            f"l1 block-Jacobi ({sweeps} sweeps per level and direction)")
+
+
 def cpu_worker(side):
     """Oracle timing on the bounded sample (run in a single-threaded child):
     the per-step set-up (binning, P2G, level-0 Hessian, Galerkin hierarchy)
@@ -90,9 +103,10 @@ def cpu_worker(side):
     t1 = time.perf_counter()
     # the solve's own set-up (smoother inverses, first energy and gradient),
     # then exactly SAMPLE_ITERS iterations (tolerance 0)
-    O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=0)
+    O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=0, sweeps=sc.smoother_sweeps)
     t2 = time.perf_counter()
-    dv, info = O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=SAMPLE_ITERS)
+    dv, info = O.solve(st, hz, 0.0, sc.lbfgs_history, max_iters=SAMPLE_ITERS,
+                       sweeps=sc.smoother_sweeps)
     t3 = time.perf_counter()
     O.g2p(st, dv)
     t4 = time.perf_counter()
@@ -183,17 +197,19 @@ def run(precision, steps, warmup, side, profile=True, smoother=0, scene=None):
     from paper_1911_07913_amd import hot
 
     sc = hs.twisting_bars(side=side) if scene is None else scene
+    # the paper's smoothing is one symmetric Gauss-Seidel sweep pair per level
+    over = {"smoother_sweeps": 1} if smoother == hot.HOT_SMOOTH_SGS else {}
     stream = torch.cuda.Stream()
     alloc = hot.TorchAllocator(0)
     if warmup > 0:
         w = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream,
-                                 allocator=alloc, smoother=smoother)
+                                 allocator=alloc, smoother=smoother, **over)
         for _ in range(warmup):
             w.step()
         torch.cuda.synchronize()
         w.close()
     g = hot.Scene.from_scene(sc, precision=precision, stream=stream.cuda_stream, allocator=alloc,
-                             smoother=smoother)
+                             smoother=smoother, **over)
     if profile:
         g.profile(True)
     stats = []
@@ -487,8 +503,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_p == hot.HOT_FP64 else "f64+f32/bf16",
         "data": "synthetic",
-        "config": {"workload": workload_name(a.side, "l1 block-Jacobi" if a.smoother == "l1jacobi"
-                                             else "coloured symmetric Gauss-Seidel"),
+        "config": {"workload": workload_name(a.side, smoother_label(
+                       a.smoother == "sgs", hs_sweeps(a.side))),
                    "particles": r["n"],
                    "precision": prec_name(main_p),
                    "smoother": a.smoother},

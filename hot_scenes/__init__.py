@@ -65,6 +65,7 @@ class Scene:
     mg_levels: int = 3
     max_iters: int = 500
     n_steps: int = 1
+    smoother_sweeps: int = 1  # smoothing sweeps per level and direction
 
     @property
     def n(self) -> int:
@@ -179,12 +180,14 @@ def rotating_cube(cells=32, cube=16, seed=0) -> Scene:
         tol=1e-6, lbfgs_history=5, mg_levels=3, n_steps=1)
 
 
-def twisting_bars(side=16, seed=1000, length=192, n_steps=20) -> Scene:
+def twisting_bars(side=16, seed=1000, length=192, n_steps=20, sweeps=4) -> Scene:
     """Four parallel Neo-Hookean bars twisted by opposite grips at +-2 rad/s.
 
     Grid 256x64x64 with dx = 1/64; bars run along x over cells [32, 32+length)
     with a side x side cross-section, laid out 2x2 in y-z.  side=12 gives
     884736 particles and side=16 gives 1572864.  E per bar in {1e5..1e8} Pa.
+    Solver settings: 5 levels, L-BFGS window 8, CN tolerance 1e-6, and
+    ``sweeps`` l1 block-Jacobi sweeps per level and direction.
     """
     dx = 1.0 / 64.0
     cells = (256, 64, 64)
@@ -209,7 +212,7 @@ def twisting_bars(side=16, seed=1000, length=192, n_steps=20) -> Scene:
             k += 1
     return _assemble(f"twisting_bars_{side}", dx, cells, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0),
                      blocks, mats, bcs, seed, 0.0, tol=1e-6, lbfgs_history=8, mg_levels=5,
-                     n_steps=n_steps)
+                     n_steps=n_steps, smoother_sweeps=sweeps)
 
 
 def sphere_slab(seed=3000, n=192, slab=(160, 40, 160), y0=24, radius=0.1, speed=3.0,

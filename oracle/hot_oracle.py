@@ -1032,7 +1032,7 @@ def g2p(st, dv):
 
 
 def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=None,
-         sweeps=1, return_internals=False, smoother="l1jacobi", solver="hot"):
+         sweeps=None, return_internals=False, smoother="l1jacobi", solver="hot"):
     """One implicit MPM step: P2G, the solve for dv, G2P (Sec. 3.1).  solver:
     "hot" (Alg. HOT), "pn-pcg" or "pn-mgpcg" (Alg. 1 with the diagonal or the
     multigrid preconditioner)."""
@@ -1042,6 +1042,7 @@ def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=N
     history = scene.lbfgs_history if history is None else history
     tol = scene.tol if tol is None else tol
     max_iters = scene.max_iters if max_iters is None else max_iters
+    sweeps = getattr(scene, "smoother_sweeps", 1) if sweeps is None else sweeps
     st = prepare(scene, dt, t)
     if solver != "hot":
         assert solver in ("pn-pcg", "pn-mgpcg")

@@ -217,10 +217,12 @@ def make_params(dx, grid_cells, origin, gravity, cfl=0.6, max_dt=1.0 / 24.0, tol
 
 def params_of(scene, precision=HOT_FP64, **over):
     """hot_params from any object with the scene attributes (dx, grid_cells,
-    origin, gravity, cfl, max_dt, tol, lbfgs_history, mg_levels, max_iters)."""
+    origin, gravity, cfl, max_dt, tol, lbfgs_history, mg_levels, max_iters,
+    and optionally smoother_sweeps)."""
     kw = dict(cfl=scene.cfl, max_dt=scene.max_dt, tol=scene.tol,
               lbfgs_history=scene.lbfgs_history, mg_levels=scene.mg_levels,
-              max_iters=scene.max_iters, precision=precision)
+              max_iters=scene.max_iters, precision=precision,
+              smoother_sweeps=getattr(scene, "smoother_sweeps", 1))
     kw.update(over)
     return make_params(scene.dx, scene.grid_cells, scene.origin, scene.gravity, **kw)
 

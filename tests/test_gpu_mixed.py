@@ -63,7 +63,7 @@ def test_mixed_vcycle_close_to_fp64(prepared_mixed):
     n = st.lev0.n
     rng = np.random.Generator(np.random.PCG64(6))
     b = rng.normal(size=3 * n) * hz.free[0]
-    uo = O.vcycle(hz, b)
+    uo = O.vcycle(hz, b, sweeps=sc.smoother_sweeps)
     ug = g.debug_apply(0, b)
     err = rel(ug, uo)
     print(f"{name}: mixed V-cycle relative error {err:.2e}")

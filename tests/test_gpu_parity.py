@@ -124,7 +124,7 @@ def test_gradient_energy_and_vcycle(prepared):
     assert rel(Hx, hz.A[0] @ dv.ravel()) < 1e-12
     b = (rng.normal(size=3 * n) * hz.free[0])
     log = []
-    uo = O.vcycle(hz, b, log=log)
+    uo = O.vcycle(hz, b, sweeps=sc.smoother_sweeps, log=log)
     ug = g.debug_apply(0, b)
     assert rel(ug, uo) < 1e-11
 
@@ -178,7 +178,7 @@ def test_vcycle_two_rows_per_wave(prepared):
     finally:
         hot.debug_set(hot.SET_MULTIROW_MIN, -1)
     assert np.array_equal(u1, u2)
-    assert rel(u2, O.vcycle(hz, b)) < 1e-11
+    assert rel(u2, O.vcycle(hz, b, sweeps=sc.smoother_sweeps)) < 1e-11
 
 
 @pytest.mark.parametrize("name", list(SCENES))

@@ -56,7 +56,7 @@ def test_vcycle_sgs(prepared_sgs):
     rng = np.random.Generator(np.random.PCG64(15))
     for k in range(2):
         b = rng.normal(size=3 * n) * hz.free[0]
-        uo = O.vcycle(hz, b, smoother="sgs")
+        uo = O.vcycle(hz, b, sweeps=sc.smoother_sweeps, smoother="sgs")
         ug = g.debug_apply(0, b)
         assert rel(ug, uo) < 1e-11, f"cycle {k}"
         assert np.all(ug[hz.free[0] == 0] == 0.0)
@@ -99,7 +99,7 @@ def test_mixed_vcycle_and_tight_step(smoother):
         g.debug_prepare(dt)
         rng = np.random.Generator(np.random.PCG64(16))
         b = rng.normal(size=3 * st.lev0.n) * hz.free[0]
-        err = rel(g.debug_apply(0, b), O.vcycle(hz, b, smoother=smoother))
+        err = rel(g.debug_apply(0, b), O.vcycle(hz, b, sweeps=sc.smoother_sweeps, smoother=smoother))
         print(f"mixed {smoother} V-cycle relative error {err:.2e}")
         assert err < 2e-2
     finally:
