@@ -150,38 +150,53 @@ def mixed_step_errors(side, steps):
     compared with the FP64 ones: max |dx| / max |x|, max |dv| / max |v|, and
     max |dx| over the largest FP64 displacement.  The FP64 GPU step stands in
     for the FP64 oracle at this size (it matches the oracle within 1e-10 at
-    every size the tests compare)."""
+    every size the tests compare).  A third step from the same state, FP64 at
+    eps = 1e-9, gives each one's distance to a much tighter solve
+    (tight_v_fp64, tight_v_mixed): at the config tolerance both stop inside
+    the same tolerance ball."""
     import numpy as np
 
     import hot_scenes as hs
     from paper_1911_07913_amd import hot
     sc = hs.twisting_bars(side=side)
     g = hot.Scene.from_scene(sc)
-    out = {"x": [], "v": [], "x_displacement": [], "iters_mixed": [], "iters_fp64": []}
+    out = {"x": [], "v": [], "x_displacement": [], "iters_mixed": [], "iters_fp64": [],
+           "tight_v_fp64": [], "tight_v_mixed": [], "iters_tight": []}
+
+    def one_step(state, **kw):
+        cur = sc.copy()
+        cur.x, cur.v, cur.F, cur.C = state["x"], state["v"], state["F"], state["C"]
+        h = hot.Scene.from_scene(cur, **kw)
+        try:
+            h.step()
+            return h.read(F=False, Cm=False), h.stats["iters"]
+        finally:
+            h.close()
+
+    def relv(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
     try:
         for _ in range(steps):
             st = g.read()
-            cur = sc.copy()
-            cur.x, cur.v, cur.F, cur.C = st["x"], st["v"], st["F"], st["C"]
-            gm = hot.Scene.from_scene(cur, precision=hot.HOT_MIXED)
-            try:
-                gm.step()
-                im = gm.stats["iters"]
-                rm = gm.read(F=False, Cm=False)
-            finally:
-                gm.close()
+            rm, im = one_step(st, precision=hot.HOT_MIXED)
+            # a much tighter FP64 solve from the same state (Gauss-Seidel, one
+            # pair, eps = 1e-9): how far each config-tolerance step lies from it
+            rt, it_t = one_step(st, tol=1e-9, smoother=hot.HOT_SMOOTH_SGS, smoother_sweeps=1)
             g.step()
             r64 = g.read(F=False, Cm=False)
-            out["x"].append(float(np.abs(rm["x"] - r64["x"]).max() / np.abs(r64["x"]).max()))
-            out["v"].append(float(np.abs(rm["v"] - r64["v"]).max() / np.abs(r64["v"]).max()))
+            out["x"].append(relv(rm["x"], r64["x"]))
+            out["v"].append(relv(rm["v"], r64["v"]))
             out["x_displacement"].append(float(np.abs(rm["x"] - r64["x"]).max() /
                                                max(np.abs(r64["x"] - st["x"]).max(), 1e-300)))
             out["iters_mixed"].append(im)
             out["iters_fp64"].append(g.stats["iters"])
+            out["tight_v_fp64"].append(relv(r64["v"], rt["v"]))
+            out["tight_v_mixed"].append(relv(rm["v"], rt["v"]))
+            out["iters_tight"].append(it_t)
     finally:
         g.close()
-    out["max"] = {"x": max(out["x"]), "v": max(out["v"]),
-                  "x_displacement": max(out["x_displacement"])}
+    out["max"] = {k: max(out[k]) for k in ("x", "v", "x_displacement", "tight_v_fp64",
+                                            "tight_v_mixed")}
     return out
 
 

@@ -911,21 +911,24 @@ hot_status gradient(hot_scene* s, const double* dv, int sbuf, double* g) {
   return HOT_OK;
 }
 
-// Algorithmic bytes of one whole V-cycle.  Every non-coarsest level m runs
-// (l1 block-Jacobi) a residual pass and a post-smoothing pass over its
-// structural blocks, with the vectors each reads and writes once (the same
-// counts as the traced level-0 kernels), the first smoothing from zero on
-// level 0 (b and D~^-1 in, u out; coarser levels get it from the
-// restriction), the restriction (r in; b and, unless the next level is the
-// coarsest, D~^-1 and u of the next level) and the prolongation (coarse u in,
-// u in and out); with Gauss-Seidel, two smoothings of the traced level-0
-// form and a clearing of u instead of the first smoothing.  The coarsest
-// Jacobi-PCG reads its matrix and five vectors once per iteration (the
-// step's average iteration count per cycle).  Mixed precision adds the FP32
-// conversion of the input; the FP64 output is written once.
+// Algorithmic bytes of one whole V-cycle with nu smoothing sweeps.  Every
+// non-coarsest level m runs (l1 block-Jacobi) nu - 1 further pre-smoothing
+// sweeps after the first one from zero, a residual pass and nu
+// post-smoothing sweeps over its structural blocks (2 nu matrix reads), with
+// the vectors each reads and writes once (the same counts as the traced
+// level-0 kernels); the first smoothing from zero on level 0 (b and D~^-1
+// in, u out; coarser levels get it from the restriction); the restriction (r
+// in; b and, unless the next level is the coarsest, D~^-1 and u of the next
+// level) and the prolongation (coarse u in, u in and out).  With
+// Gauss-Seidel: a clearing of u, nu forward-backward pairs before and after,
+// each of the traced level-0 form, and the residual.  The coarsest Jacobi-PCG
+// reads its matrix and five vectors once per iteration (the step's average
+// iteration count per cycle).  Mixed precision adds the FP32 conversion of
+// the input; the FP64 output is written once.
 double vcycle_bytes(hot_scene* s) {
   const bool mx = s->mixed, gs = s->prm.smoother == HOT_SMOOTH_SGS;
   const double vs = mx ? 4.0 : 8.0, ms = mx ? 18.0 : 72.0;
+  const double nu = s->prm.smoother_sweeps;
   const int M = s->levels;
   const double n0 = s->L[0].n;
   double b = mx ? 36.0 * n0 : 0.0;
@@ -934,12 +937,12 @@ double vcycle_bytes(hot_scene* s) {
     const double n = L.n, nnz = s->hscal[S_NNZ + m], nc = s->L[m + 1].n;
     if (gs) {
       const double f = 2.0 - (double)(L.coff[kColors] - L.coff[kColors - 1]) / std::max(n, 1.0);
-      b += 4.0 * vs * n + 2.0 * f * (ms * nnz + (mx ? 85.0 : 107.0) * n);
+      b += 4.0 * vs * n + 2.0 * nu * f * (ms * nnz + (mx ? 85.0 : 107.0) * n);
     } else {
       if (m == 0) b += 16.0 * vs * n;
-      b += ms * nnz + (mx ? 40.0 : 76.0) * n;   // residual
-      b += ms * nnz + (mx ? 79.0 : 151.0) * n;  // post-smoothing
+      b += (2.0 * nu - 1.0) * (ms * nnz + (mx ? 79.0 : 151.0) * n);  // smoothing sweeps
     }
+    b += ms * nnz + (mx ? 40.0 : 76.0) * n;  // residual
     const bool first = !gs && m + 2 < M;
     b += 3.0 * vs * n + 3.0 * vs * nc + (first ? 13.0 * vs * nc : 0.0);  // restriction
     b += 4.0 * vs * nc + 8.0 * vs * n;                                    // prolongation
@@ -964,10 +967,11 @@ double prof_launch_bytes(hot_scene* s, int kind) {
     // b, the gathered iterate, row list entry, node index, pattern and free
     // flags once and writing its iterate entries once (blocks counted in
     // proportion to rows)
-    case HOT_PROF_SGS0: {
+    case HOT_PROF_SGS0: {  // smoother_sweeps forward-backward pairs
       const LevelH& L0 = s->L[0];
       const double f = 2.0 - (double)(L0.coff[kColors] - L0.coff[kColors - 1]) / std::max(n0, 1.0);
-      return mx ? f * (18.0 * nnz0 + 85.0 * n0) : f * (72.0 * nnz0 + 107.0 * n0);
+      return s->prm.smoother_sweeps *
+             (mx ? f * (18.0 * nnz0 + 85.0 * n0) : f * (72.0 * nnz0 + 107.0 * n0));
     }
     case HOT_PROF_RESIDUAL0: return mx ? 18.0 * nnz0 + 40.0 * n0 : 72.0 * nnz0 + 76.0 * n0;
     case HOT_PROF_ASSEMBLE: return 72.0 * nnz0 + 456.0 * np + 111.0 * n0;
