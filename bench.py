@@ -596,6 +596,10 @@ def main():
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["n"], a.side, [s["iters"] for s in stats])
     print(json.dumps(line), flush=True)
+    # hand the device memory back before the interpreter exits, so that the
+    # process ends promptly
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return 0
 
 

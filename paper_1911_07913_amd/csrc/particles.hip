@@ -636,6 +636,7 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
   __shared__ double pc[kAsmChunk][kPC];      // their C
   __shared__ double red[12];
   __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
+  __shared__ int nextv[kMaxCx * 9 + 1];  // first non-empty column at or after v (-1: none)
   __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
   __shared__ double rmass[kSegRows];
   __shared__ int rx[kSegRows];
@@ -667,6 +668,15 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
     rmass[v] = mass[rb + v];
   }
   for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    int nx = -1;
+    nextv[ncx * 9] = -1;
+    for (int w = ncx * 9 - 1; w >= 0; --w) {
+      if (mcnt[w] > 0) nx = w;
+      nextv[w] = nx;
+    }
+  }
   // matrix-core roles: wave w owns output tile (rows 16 tile_m.., columns
   // 16 tile_n..) of the 27 x 27 product; lane l feeds A[l % 16][l / 16] and
   // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3
@@ -707,13 +717,7 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
       nt = t0 + kAsmChunk;
       return;
     }
-    for (int w = v + 1; w < ncx * 9; ++w)
-      if (mcnt[w] > 0) {
-        nv = w;
-        nt = 0;
-        return;
-      }
-    nv = -1;
+    nv = nextv[v + 1];
     nt = 0;
   };
   // staging: a chunk's particles are consecutive, so its a_l and C values are
@@ -790,15 +794,21 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
           }
         }
       }
-      // the column's blocks into the sliding window (disjoint per lane/wave)
+      // the column's blocks into the sliding window (disjoint per lane/wave):
+      // the four reads first, then the adds and stores
       if (dn < 27) {
+        double* wp[4];
+        double wv[4];
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int r = dm_r[vv] < 3 ? dm_r[vv] : 0;
+          wp[vv] = &win[(c + r + 3) % 3][dm_e[vv] * kSlotPad + dsl0 - r - 5 * ky - 25 * kz];
+          wv[vv] = *wp[vv];
+        }
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
           const int r = dm_r[vv];
-          if (r >= rlo && r <= rhi) {
-            const int sl = dsl0 - r - 5 * ky - 25 * kz;
-            win[(c + r + 3) % 3][dm_e[vv] * kSlotPad + sl] += acc[vv];
-          }
+          if (r >= rlo && r <= rhi) *wp[vv] = wv[vv] + acc[vv];
         }
       }
     }
