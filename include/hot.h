@@ -235,7 +235,9 @@ hot_status hot_scene_memory(const hot_scene* scene, size_t* live_bytes, size_t* 
  *     Calls that overlap in time on one GPU (several host threads, or
  *     several streams) race on the array and must be serialised by the
  *     caller;
- *   - kernel tracing (hot_profile_enable) must be off: HOT_E_INVALID. */
+ *   - kernel tracing (hot_profile_enable) must be off: HOT_E_INVALID;
+ *   - with hot_params.graph set, the V-cycles run eagerly in this call
+ *     (same kernels and results; instantiating a graph may allocate). */
 hot_status hot_step_noalloc(hot_scene* scene, double dt, hot_step_stats* stats);
 
 /* ---- serving: continuous batching of independent scenes ------------------

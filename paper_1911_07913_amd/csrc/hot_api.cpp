@@ -809,7 +809,9 @@ hot_status vcycle_body(hot_scene* s, const double* q, double* r) {
 // step launches that graph.  The launches are the same kernels with the same
 // arguments as the eager cycle; the coarse-PCG log advances on the device.
 hot_status vcycle(hot_scene* s, const double* q, double* r) {
-  const bool graph = s->prm.graph && !s->prof && q == P<double>(s->q) && r == P<double>(s->r);
+  // (not inside hot_step_noalloc: instantiating a graph may allocate)
+  const bool graph = s->prm.graph && !s->prof && !s->no_alloc && q == P<double>(s->q) &&
+                     r == P<double>(s->r);
   if (!graph) {
     PROF(s, HOT_PROF_VCYCLE, TRY(vcycle_body(s, q, r)));
   } else {

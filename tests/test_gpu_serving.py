@@ -151,3 +151,32 @@ def test_more_slots_than_grid_tickets():
     for k in range(len(reqs)):
         for f in ("x", "v"):
             assert np.array_equal(got[k][f], ref[k][f]), f"request {k} field {f}"
+
+
+def test_submitted_request_with_invalid_scene_comes_back_with_its_error():
+    """A scene description that fails validation is refused on the slot
+    thread: its result carries the status and message and no scene, and the
+    batch serves the next request normally."""
+    hot, serving = _mods()
+    good = small_requests()[0]
+    bad = small_requests()[1]
+    bad.v = bad.v.copy()
+    bad.v[3, 1] = np.nan
+    b = hot.Batch(8 << 30, 2)
+    try:
+        args = [hot.SceneArgs(hot.params_of(sc), sc.x, sc.v, sc.F, sc.C, sc.vol0, sc.mat_id,
+                              sc.materials, sc.bcs) for sc in (bad, good)]
+        assert b.submit(args[0], 1, 0) and b.submit(args[1], 1, 1)
+        got = {}
+        for _ in range(200):
+            done, resident = b.poll(wait_ms=50)
+            for r in done:
+                got[r["tag"]] = r
+            if len(got) == 2:
+                break
+        assert got[0]["status"] == hot.HOT_E_INVALID and not got[0]["scene"]
+        assert "finite" in got[0]["message"]
+        assert got[1]["status"] == 0 and got[1]["steps"] == 1 and got[1]["scene"]
+        hot.Scene.adopt(got[1]["scene"], args[1].n, args[1].params).close()
+    finally:
+        b.close()

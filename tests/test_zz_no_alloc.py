@@ -24,10 +24,10 @@ def _read_all(g):
     return np.concatenate([r["x"].ravel(), r["v"].ravel(), r["F"].ravel(), r["C"].ravel()])
 
 
-def _same_step(make, precision):
+def _same_step(make, precision, graph=0):
     hot = _hot()
-    a = hot.Scene.from_scene(make(), precision=precision)
-    b = hot.Scene.from_scene(make(), precision=precision)
+    a = hot.Scene.from_scene(make(), precision=precision, graph=graph)
+    b = hot.Scene.from_scene(make(), precision=precision, graph=graph)
     try:
         a.step(0.0)  # sizes both scenes' buffers
         b.step(0.0)
@@ -54,6 +54,8 @@ def test_noalloc_step_equals_hot_step_twice_second_smaller():
     _same_step(big, hot.HOT_FP64)
     _same_step(small, hot.HOT_FP64)
     _same_step(small, hot.HOT_MIXED)
+    # a scene set to capture its V-cycles runs them eagerly here
+    _same_step(small, hot.HOT_FP64, graph=1)
 
 
 def test_noalloc_first_step_refused_then_usable():
