@@ -116,7 +116,7 @@ struct hot_scene {
   Particles P[2];
   int cur = 0;
   DBuf pbuf[2];
-  DBuf f, key, keys, tmp, Cp, Ag, psi[2], S[2];
+  DBuf f, key, keys, tmp, arec, psi[2], S[2];
   DBuf wnode;  // double4 node velocities over the padded level-0 grid
   // half-coarsened grid of the Galerkin product (reused for every level)
   DBuf tnodes, tmap, tpat, tH;
@@ -443,7 +443,7 @@ size_t estimate_bytes(const hot_params* p, int64_t n, const SetCounts& c) {
   const double N = (double)n;
   // particle state (two sets), per-particle work arrays, keys
   A(N * 208); A(N * 208);
-  A(N * 24); A(N * 360); A(N * 648); A(N * 8); A(N * 8); A(N * 72); A(N * 72);
+  A(N * 24); A(N * kAsmRec * 8); A(N * 8); A(N * 8); A(N * 72); A(N * 72);
   A(N * 4); A(N * 4); A(N * 4);
   // dense maps over the padded level grids, bricks, reductions
   int dims[3] = {p->grid_cells[0] + 1, p->grid_cells[1] + 1, p->grid_cells[2] + 1};
@@ -681,10 +681,10 @@ hot_status build_hessian(hot_scene* s, const double* dv) {
   PROF(s, HOT_PROF_PHESS,
        launch_particle_hessian(s->sd, L0, n, P<double>(s->f), P<int>(s->key), pt.F, pt.vol,
                                pt.mat, P<double>(s->vstar), dv, dt, P<double>(s->wnode),
-                               P<double>(s->Cp), st));
+                               P<double>(s->arec), st));
   PROF(s, HOT_PROF_ASSEMBLE,
        launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, n, P<double>(s->f), pt.F,
-                          P<double>(s->Cp), P<double>(s->Ag), P<int>(s->start),
+                          P<double>(s->arec), P<int>(s->start),
                           P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), st));
   for (int m = 0; m + 1 < s->levels; ++m) {
     // rows of the half-coarsened grid: x-y parents of level m's nodes
@@ -1418,7 +1418,7 @@ void destroy(hot_scene* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   drop_vcycle_graph(s);
-  DBuf* all[] = {&s->pbuf[0], &s->pbuf[1], &s->f, &s->key, &s->keys, &s->tmp, &s->Cp, &s->Ag,
+  DBuf* all[] = {&s->pbuf[0], &s->pbuf[1], &s->f, &s->key, &s->keys, &s->tmp, &s->arec,
                  &s->psi[0], &s->psi[1], &s->S[0], &s->S[1], &s->counts, &s->start,
                  &s->cursor, &s->flags, &s->scan, &s->scan_temp, &s->err, &s->mass,
                  &s->vstar, &s->xi, &s->fixed, &s->dv, &s->dvt, &s->g, &s->gnew, &s->q, &s->r,
@@ -1617,10 +1617,10 @@ hot_status hot_init_scene(const hot_params* params, int64_t n, const double* x, 
     Pp.mat = (int*)(Pp.vol + n);
     Pp.id = Pp.mat + n;
   }
-  DBuf* pb[] = {&s->f, &s->Cp, &s->Ag, &s->psi[0], &s->psi[1], &s->S[0], &s->S[1]};
-  size_t pbs[] = {(size_t)n * 24, (size_t)n * 45 * 8, (size_t)n * 81 * 8, (size_t)n * 8,
-                  (size_t)n * 8, (size_t)n * 72, (size_t)n * 72};
-  for (int k = 0; k < 7; ++k)
+  DBuf* pb[] = {&s->f, &s->arec, &s->psi[0], &s->psi[1], &s->S[0], &s->S[1]};
+  size_t pbs[] = {(size_t)n * 24, (size_t)n * kAsmRec * 8, (size_t)n * 8, (size_t)n * 8,
+                  (size_t)n * 72, (size_t)n * 72};
+  for (int k = 0; k < 6; ++k)
     if ((rc = ensure(s, *pb[k], pbs[k])) < 0) return bail(rc);
   DBuf* ib[] = {&s->key, &s->keys, &s->tmp};
   for (DBuf* b : ib)

@@ -62,6 +62,11 @@ constexpr int kBrick = 4;
 constexpr int kBrickNodes = kBrick + 2;  // node window per axis
 constexpr int kBrickWin = kBrickNodes * kBrickNodes * kBrickNodes;  // 216
 constexpr int kSegRows = 16;
+// Level-0 assembly record of one particle: C_p (45 doubles, packed upper
+// triangle), then a_lp = F_p^n^T grad w_lp for its 27 stencil nodes (27 x 3);
+// 1008 bytes, a multiple of 16.
+constexpr int kAsmRec = 126;
+constexpr int kAsmRecA = 45;
 struct BrickGeom {
   int bd[3];  // bricks per axis
   long long total;
@@ -181,7 +186,7 @@ void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const d
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
                              const double* vstar, const double* dv, double dt, double* wnode,
-                             double* Cp, hipStream_t st);
+                             double* rec, hipStream_t st);
 // energy/stress at dv + alpha*p: psi_out[n] = V_p psi, S_out[9n] = V_p P F^n^T
 void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
                           const int* key, const double* F, const double* vol, const int* mat,
@@ -195,12 +200,12 @@ void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, co
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
                 const double* dv, double dt, double* wnode, hipStream_t st);
-// level-0 Hessian: the particles' a_l operands into Ag ([n][27][3], scratch),
-// then the row segments' blocks
+// level-0 Hessian: the particles' a_l operands into their assembly records
+// (after C_p, written by launch_particle_hessian), then the row segments'
+// blocks
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        int n, const double* f, const double* F, const double* Cp, double* Ag,
-                        const int* cstart, const int* ccount, const double* mass, const int* fixed,
-                        hipStream_t st);
+                        int n, const double* f, const double* F, double* rec, const int* cstart,
+                        const int* ccount, const double* mass, const int* fixed, hipStream_t st);
 
 // matrix.hip
 void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);

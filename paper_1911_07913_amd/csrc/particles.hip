@@ -4,6 +4,8 @@
 // Particle-to-node sums are computed without global floating-point atomics
 // and in a fixed order (see the brick and row-segment kernels below), so the
 // results are reproducible run to run.
+#include <climits>
+
 #include "mpm_math.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -264,12 +266,13 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
 
 // Per-particle projected stress derivative at dv = 0, scaled by dt^2 V_p
 // (the particle's contribution to the level-0 Hessian, Alg. HOT
-// projectHessian).  45 upper-triangle entries per particle.
+// projectHessian): 45 upper-triangle entries at the head of the particle's
+// assembly record.
 __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                    const int* __restrict__ key, const double* __restrict__ Fn,
                                    const double* __restrict__ vol, const int* __restrict__ mat,
                                    const double4* __restrict__ wn, double dt,
-                                   double* __restrict__ Cp) {
+                                   double* __restrict__ rec) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double F[9], fn[9];
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView 
   particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
   double C45[45];
   projected_dPdF(s.mats[mat[p]], F, dt * dt * vol[p], C45);
-  for (int i = 0; i < 45; ++i) Cp[45 * (long long)p + i] = C45[i];
+  for (int i = 0; i < 45; ++i) rec[kAsmRec * (long long)p + i] = C45[i];
 }
 
 // Energy density and stress at the trial point: psi_out[p] = V_p psi(F_p),
@@ -477,32 +480,37 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // Level-0 Hessian (Sec. 4.1 / Alg. HOT initialisation):
 //   H_ij = m_i delta_ij I + sum_p a_ip^T C_p a_jp,  a_ip = F_p^n^T grad w_ip,
 // with C_p the particle's projected stress derivative already scaled by
-// dt^2 V_p (45 upper-triangle entries).
+// dt^2 V_p (45 upper-triangle entries).  Each particle's operands sit in one
+// record of kAsmRec doubles: C_p, then a_lp for its 27 stencil nodes l.
 //
-// One work-group per row segment: up to 16 consecutive rows (x, y, z) of one
-// x-line.  The group sweeps the base cells c = x_first - 2 .. x_last of the 9
-// cell columns (c, y - ky, z - kz), ky, kz in {0,1,2}; a particle of column
-// (ky, kz) in cell c touches rows c + r, r in {0,1,2}, of this segment, with
-// stencil offset k = (r, ky, kz).  For one cell column the blocks are a dense
-// contraction over the column's particles p and the component eps:
+// One work-group of two waves per row segment: up to 16 consecutive rows
+// (x, y, z) of one x-line.  The group sweeps the base cells c = x_first - 2
+// .. x_last of the 9 cell columns (c, y - ky, z - kz), ky, kz in {0,1,2}; a
+// particle of column (ky, kz) in cell c touches rows c + r, r in {0,1,2}, of
+// this segment, with stencil offset k = (r, ky, kz).  For one cell column the
+// blocks are a dense contraction over the column's particles p and the
+// component eps:
 //   B[(r, g, d)][l] = sum_(p, eps) Z_p[(r, g, d)][eps] a_p[l][eps],
-// Z_p[(r, g, d)][eps] = sum_b a_p[k][b] C_p[3g + b][3d + eps] (k = (r, ky, kz)),
-// a 27 x 27 x 3P product that the four waves compute as 2 x 2 tiles of FP64
-// 16x16x4 matrix-core instructions, accumulating in registers over the
-// column's particles; each lane forms its own Z operands from a_k and C_p in
-// registers right before the matrix-core steps.  The a_l come precomputed
-// (k_particle_agrad) and are staged with C_p as two contiguous ranges.  Per cell column the sums go
-// to a 3-row sliding window in LDS.  After cell c, row c receives nothing
+//   Z_p[(r, g, d)][eps] = sum_b a_p[k][b] C_p[3g + b][3d + eps],
+// a 27 x 27 x 3P product computed with FP64 16x16x4 matrix-core steps.  Wave
+// w owns product rows 16w .. 16w + 15 and both 16-column tiles: each lane
+// forms its A operands (Z values) once, in registers, for two steps, and the
+// two waves' rows are disjoint entries of the 3-row sliding window in LDS,
+// so a column's sums are added to the window by the wave that computed them
+// with no barrier.  Particles are staged kAsmChunk at a time as one
+// contiguous range of records, 16 bytes per load; record slots past the
+// column's last particle are zero-filled, so every operand read and
+// matrix-core step is unconditional.  After cell c, row c receives nothing
 // more: it is finalised (mass, Dirichlet projection, smoother inverse) and
 // written once.  Every block of every particle is computed exactly once; no
-// atomics.  The kernel is bound by latency, not by a unit: LDS (under 40 KB)
-// and registers (at most 128) are sized so that four work-groups share a
-// compute unit.
-constexpr int kAsmChunk = 8;   // particles staged per pass
-constexpr int kPA = 81;        // a_l (27 x 3) per particle
-constexpr int kPC = 45;        // C per particle
-constexpr int kARegs = (kAsmChunk * kPA + 255) / 256;
-constexpr int kCRegs = (kAsmChunk * kPC + 255) / 256;
+// atomics.
+constexpr int kAsmChunk = 8;                       // particles staged per pass
+constexpr int kAsmThreads = 128;                   // two waves
+constexpr int kStage = 1024;                       // staged doubles per pass
+constexpr int kStageLd = kStage / (2 * kAsmThreads);  // 16-byte loads per thread
+constexpr int kBufferWord3 = 0x00020000;          // buffer resource word 3 (raw, 32-bit)
+static_assert(kAsmChunk * kAsmRec <= kStage, "staging area too small");
+static_assert((kAsmRec % 2) == 0, "records must keep 16-byte alignment");
 
 __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
   double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
@@ -513,10 +521,11 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
 }
 
 // The assembly's right-hand operands a_lp = F_p^n^T grad w_lp for the 27
-// stencil nodes l of every particle, [n][27][3], once per step (the assembly
-// visits each particle from up to 9 x-lines).  One thread per (particle, node).
+// stencil nodes l of every particle, into the particle's record after C_p,
+// once per step (the assembly visits each particle from up to 9 x-lines).
+// One thread per (particle, node).
 __global__ void k_particle_agrad(SceneDev s, long long n27, const double* __restrict__ f,
-                                 const double* __restrict__ Fn, double* __restrict__ A) {
+                                 const double* __restrict__ Fn, double* __restrict__ rec) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n27) return;
   const long long p = e / 27;
@@ -527,114 +536,77 @@ __global__ void k_particle_agrad(SceneDev s, long long n27, const double* __rest
   wdw(l / 9, f[3 * p + 2], s.inv_dx, w2, d2);
   double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
   const double* F = Fn + 9 * p;
-  double* o = A + 3 * e;
+  double* o = rec + kAsmRec * p + kAsmRecA + 3 * l;
   o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
   o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
   o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
 }
 
-// Entries (c, s) of a block row owned by one of 256 threads, decomposed once:
-// LDS index, offset of the slot's neighbour in the segment's constrained-flag
-// window (kNoNb for the diagonal slot), and block row g of off-diagonal slots
-// (-1 for the diagonal slot and for unused items).
-constexpr int kFinItems = (kBlock * kSlots + 255) / 256;
-constexpr int kNoNb = -(1 << 30);
-struct FinRoles {
-  int idx[kFinItems];
-  int nb[kFinItems];
-  int g[kFinItems];
-};
-
-__device__ inline void fin_roles(int tid, int nxw, FinRoles& fr) {
-#pragma unroll
-  for (int k = 0; k < kFinItems; ++k) {
-    const int e = tid + 256 * k;
-    const int c = e / kSlots, sl = e - c * kSlots;
-    const bool valid = e < kBlock * kSlots;
-    fr.idx[k] = valid ? c * kSlotPad + sl : -1;
-    const bool center = sl == kCenter;
-    fr.nb[k] = (!valid || center) ? kNoNb
-                                  : (sl % 5 - 2) + nxw * ((sl / 5) % 5 + 5 * (sl / 25));
-    fr.g[k] = (!valid || center) ? -1 : c / 3;
-  }
-}
-
-// Block-level finalisation of level-0 row i held in LDS (256 threads): mass
-// on the diagonal, Dirichlet projection (constrained row -> m_i I, blocks to
-// constrained neighbours -> 0), exact-zero diagonal rule, write-out, scalar
-// diagonal and the l1 block-Jacobi inverse.  In mixed precision (L.Hb set)
-// the BF16 blocks and FP32 copies of the diagonal and inverse are written
-// here too, as the level conversion would.  nbf holds the constrained flags
-// of the 5x5 y-z neighbourhood of the segment's x-line, x-major from xw0.
-__device__ inline void finalize_row_block(double* acc, int i, int xi, int xw0,
-                                          const LevelView& L, const uint8_t* nbf,
-                                          const FinRoles& fr, bool row_fixed, double mass_i,
-                                          double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint8_t* nbx = nbf + (xi - xw0);
-#pragma unroll
-  for (int k = 0; k < kFinItems; ++k) {
-    if (fr.idx[k] >= 0) {
-      bool z = row_fixed || (fr.nb[k] != kNoNb && nbx[fr.nb[k]] != 0);
-      if (z) acc[fr.idx[k]] = 0.0;
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int g = 0; g < 3; ++g) {
-      double d = acc[(4 * g) * kSlotPad + kCenter] + mass_i;
-      bool zero = (d == 0.0);
-      acc[(4 * g) * kSlotPad + kCenter] = zero ? 1.0 : d;
-      L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
-      L.diag[3 * i + g] = zero ? 1.0 : d;
-      if (L.Hb) L.diag32[3 * i + g] = (float)(zero ? 1.0 : d);
-    }
-  }
-  __syncthreads();
+// Finalisation of level-0 row i held in the LDS window (the group's
+// kAsmThreads threads, no barrier): mass on the diagonal, Dirichlet
+// projection (constrained row -> m_i I, blocks to constrained neighbours ->
+// 0), exact-zero diagonal rule, write-out (and in mixed precision, L.Hb set,
+// the BF16 blocks and FP32 diagonal, as the level conversion would), the
+// scalar diagonal and free-dof flags.  Thread t < 125 owns slot t of the
+// nine entry planes; nb_fixed is the constrained flag of that slot's
+// neighbour.  The window row is cleared as it is read.  The final diagonal
+// block goes to cb[9] and this wave's share of the off-diagonal l1 row sums
+// to l1w[3]; the l1 block-Jacobi inverse is formed from them once the whole
+// segment is done.
+constexpr int kWinPad = kSlots;  // window plane stride (the row's padding slots are not held)
+__device__ inline void finalize_row(double* acc, int i, const LevelView& L, bool row_fixed,
+                                    bool nb_fixed, double mass_i, double* cb, double* l1w) {
+  const int tid = threadIdx.x, lane = tid & 63;
   double l1[3] = {0.0, 0.0, 0.0};
-  double* Hrow = L.H + (long long)i * kRowStride;
-  uint16_t* Hbrow = L.Hb ? L.Hb + (long long)i * kRowStride : nullptr;
+  if (tid < kSlots) {
+    const bool center = tid == kCenter;
+    const bool proj = row_fixed || (!center && nb_fixed);
+    double* Hrow = L.H + (long long)i * kRowStride + tid;
+    uint16_t* Hbrow = L.Hb ? L.Hb + (long long)i * kRowStride + tid : nullptr;
 #pragma unroll
-  for (int k = 0; k < kFinItems; ++k) {
-    if (fr.idx[k] >= 0) {
-      double v = acc[fr.idx[k]];
-      Hrow[fr.idx[k]] = v;
-      if (Hbrow) Hbrow[fr.idx[k]] = f32_to_bf16((float)v);
-      const double av = fabs(v);
-      l1[0] += (fr.g[k] == 0) ? av : 0.0;
-      l1[1] += (fr.g[k] == 1) ? av : 0.0;
-      l1[2] += (fr.g[k] == 2) ? av : 0.0;
+    for (int c = 0; c < kBlock; ++c) {
+      double v = acc[c * kWinPad + tid];
+      acc[c * kWinPad + tid] = 0.0;
+      if (proj) v = 0.0;
+      if (center) {
+        if (c % 4 == 0) {
+          const int g = c / 4;
+          const double d = v + mass_i;
+          const bool zero = (d == 0.0);
+          v = zero ? 1.0 : d;
+          L.free_dof[3 * i + g] = (!row_fixed && !zero) ? 1 : 0;
+          L.diag[3 * i + g] = v;
+          if (L.Hb) L.diag32[3 * i + g] = (float)v;
+        }
+        cb[c] = v;
+      }
+      Hrow[c * kSlotPad] = v;
+      if (Hbrow) Hbrow[c * kSlotPad] = f32_to_bf16((float)v);
+      l1[c / 3] += center ? 0.0 : fabs(v);
     }
   }
   for (int g = 0; g < 3; ++g) {
-    double t = wave_sum(l1[g]);
-    if (lane == 0) red[wave * 3 + g] = t;
+    const double t = wave_sum(l1[g]);
+    if (lane == 0) l1w[g] = t;
   }
-  __syncthreads();
-  if (tid == 0) {
-    double Dt[9];
-    for (int k = 0; k < 9; ++k) Dt[k] = acc[k * kSlotPad + kCenter];
-    for (int g = 0; g < 3; ++g) Dt[4 * g] += red[g] + red[3 + g] + red[6 + g] + red[9 + g];
-    double Di[9];
-    inv3(Dt, Di);
-    for (int k = 0; k < 9; ++k) L.Dinv[(long long)i * 9 + k] = Di[k];
-    if (L.Hb)
-      for (int k = 0; k < 9; ++k) L.Dinv32[(long long)i * 9 + k] = (float)Di[k];
-  }
-  __syncthreads();
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+// Zeroes a window row that holds no node of the segment.
+__device__ inline void clear_row(double* acc) {
+  for (int e = threadIdx.x; e < kBlock * kWinPad; e += kAsmThreads) acc[e] = 0.0;
+}
+
+__global__ __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin,
-                      const double* __restrict__ Ag, const double* __restrict__ Cp,
-                      const int* __restrict__ cstart,
-                      const int* __restrict__ ccount, const double* __restrict__ mass,
-                      const int* __restrict__ fixed) {
+                      const double* __restrict__ rec,
+                      const int* __restrict__ cstart, const int* __restrict__ ccount,
+                      const double* __restrict__ mass, const int* __restrict__ fixed) {
   constexpr int kMaxCx = kSegRows + 2;
-  __shared__ double win[3][kRowStride];
-  __shared__ double av[kAsmChunk][27][3];    // a_l of the staged particles
-  __shared__ double pc[kAsmChunk][kPC];      // their C
-  __shared__ double red[12];
+  constexpr int kWinRow = kBlock * kWinPad;
+  __shared__ __attribute__((aligned(16))) double win[3][kWinRow];
+  __shared__ __attribute__((aligned(16))) double stg[kStage];  // kAsmChunk records
+  __shared__ double cb[kSegRows][9];       // final diagonal blocks of the rows
+  __shared__ double l1w[2][kSegRows][3];   // per-wave l1 sums of the rows
   __shared__ int mcnt[kMaxCx * 9], mst[kMaxCx * 9];
   __shared__ int nextv[kMaxCx * 9 + 1];  // first non-empty column at or after v (-1: none)
   __shared__ uint8_t nbf[(kMaxCx + 2) * 25];
@@ -648,7 +620,7 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
   unpidx(L.g, L.nodes[re - 1], xb, yy, zz);
   const int ncx = xb - xa + 3;
   // particle ranges of the 9 cell columns over the whole sweep, in one trip
-  for (int v = tid; v < ncx * 9; v += 256) {
+  for (int v = tid; v < ncx * 9; v += kAsmThreads) {
     int ci = v / 9, col = v - 9 * ci;
     long long cell = pidx(L.g, xa - 2 + ci, ys - col % 3, zs - col / 3);
     mcnt[v] = ccount[cell];
@@ -656,172 +628,231 @@ void k_assemble_strip(SceneDev s, LevelView L, const int* __restrict__ seg_begin
   }
   // constrained flags of the rows' neighbourhood, the rows' masses and x
   const int xw0 = xa - 2, nxw = ncx + 2;
-  for (int v = tid; v < nxw * 25; v += 256) {
-    int xo = v % nxw, r = v / nxw;
-    int j = L.map[pidx(L.g, xw0 + xo, ys + r % 5 - 2, zs + r / 5 - 2)];
-    nbf[v] = (j >= 0 && fixed[j]) ? 1 : 0;
+  {
+    constexpr int kNbIt = ((kMaxCx + 2) * 25 + kAsmThreads - 1) / kAsmThreads;
+    int jn[kNbIt];
+#pragma unroll
+    for (int k = 0; k < kNbIt; ++k) {
+      const int v = tid + kAsmThreads * k;
+      const int xo = v % nxw, r = v / nxw;
+      jn[k] = (v < nxw * 25) ? L.map[pidx(L.g, xw0 + xo, ys + r % 5 - 2, zs + r / 5 - 2)] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kNbIt; ++k) {
+      const int v = tid + kAsmThreads * k;
+      if (v < nxw * 25) nbf[v] = (jn[k] >= 0 && fixed[jn[k]]) ? 1 : 0;
+    }
   }
-  for (int v = tid; v < re - rb; v += 256) {
+  for (int v = tid; v < re - rb; v += kAsmThreads) {
     int x0, y0, z0;
     unpidx(L.g, L.nodes[rb + v], x0, y0, z0);
     rx[v] = x0;
     rmass[v] = mass[rb + v];
   }
-  for (int e = tid; e < 3 * kRowStride; e += 256) (&win[0][0])[e] = 0.0;
+  for (int e = tid; e < 3 * kWinRow; e += kAsmThreads) (&win[0][0])[e] = 0.0;
   __syncthreads();
-  if (tid == 0) {
-    int nx = -1;
-    nextv[ncx * 9] = -1;
-    for (int w = ncx * 9 - 1; w >= 0; --w) {
-      if (mcnt[w] > 0) nx = w;
-      nextv[w] = nx;
-    }
-  }
-  // matrix-core roles: wave w owns output tile (rows 16 tile_m.., columns
-  // 16 tile_n..) of the 27 x 27 product; lane l feeds A[l % 16][l / 16] and
-  // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3
-  const int wave = tid >> 6, lane = tid & 63;
-  const int tile_m = wave >> 1, tile_n = wave & 1;
-  const int am = tile_m * 16 + (lane & 15);      // A row: (r, g, d)
-  const bool am_ok = am < 27;
-  const int amc = am_ok ? am : 0;                // clamped for addressing
-  const int am_r = amc / 9, am_g = (amc % 9) / 3, am_d = amc % 3;
-  const int bn = tile_n * 16 + (lane & 15);      // B column: stencil node l
-  const bool bn_ok = bn < 27;
-  const int bnc = bn_ok ? bn : 0;
-  const int kq = lane >> 4;                      // lane group: k offset within a step
-  int dm_r[4], dm_e[4];                          // D rows held by this lane
+  if (tid < 64) {  // nextv: suffix minimum of the non-empty columns, three per lane
+    const int nv9 = ncx * 9;
+    int m[3];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int m = tile_m * 16 + kq + 4 * v;
-    dm_r[v] = (m < 27) ? m / 9 : 3;
-    dm_e[v] = (m < 27) ? 3 * ((m % 9) / 3) + m % 3 : 0;
+    for (int k = 0; k < 3; ++k) {
+      const int e = 3 * tid + k;
+      m[k] = (e < nv9 && mcnt[e] > 0) ? e : INT_MAX;
+    }
+    m[1] = min(m[1], m[2]);
+    m[0] = min(m[0], m[1]);
+    int sfx = m[0];  // over lanes >= this one
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_down(sfx, off, 64);
+      if (tid + off < 64) sfx = min(sfx, o);
+    }
+    int after = __shfl_down(sfx, 1, 64);
+    if (tid == 63) after = INT_MAX;
+    m[2] = min(m[2], after);
+    m[1] = min(m[1], m[2]);
+    m[0] = min(m[0], m[1]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int e = 3 * tid + k;
+      if (e < nv9) nextv[e] = (m[k] == INT_MAX) ? -1 : m[k];
+    }
+    if (tid == 0) nextv[nv9] = -1;
   }
-  const int dn = tile_n * 16 + (lane & 15);      // D column: stencil node l
-  const int dnx = dn % 3, dny = (dn / 3) % 3, dnz = dn / 9;
-  // window slot of (node l, row r, column ky, kz) = dsl0 - r - 5 ky - 25 kz
-  const int dsl0 = (dnx + 2) + 5 * (dny + 2) + 25 * (dnz + 2);
-  // K order of a pass: step st, lane group kq -> particle q = 2 kq + st / 3,
-  // component e = st % 3, so a lane's six A operands come from two particles
+  // this thread's finalisation slot: the neighbour's constrained flag offset
+  const int tsl = min(tid, kSlots - 1);
+  const int nbo = (tsl % 5 - 2) + nxw * ((tsl / 5) % 5 + 5 * (tsl / 25));
+  // matrix-core roles (FP64 16x16x4): lane l feeds A[l % 16][l / 16] and
+  // B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16], v = 0..3.  Wave w
+  // owns product rows m = 16 w .. 16 w + 15, (r, g, d) = (m / 9, m % 9 / 3,
+  // m % 3); rows m >= 27 are padding (their A operands are those of row 26,
+  // their D rows are dropped).
+  const int wave = tid >> 6, lane = tid & 63;
+  const int kq = lane >> 4, li = lane & 15;
+  const int am = min(16 * wave + li, 26);
+  const int am_r = am / 9, am_g = (am % 9) / 3, am_d = am % 3;
   int zoff[9];  // packed C index of (3 g + b, 3 d + e), entry 3 b + e
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int e = 0; e < 3; ++e) zoff[3 * b + e] = tri9(3 * am_g + b, 3 * am_d + e);
-  FinRoles fr;
-  fin_roles(tid, nxw, fr);
+  // B columns of the two tiles: stencil nodes l = li and 16 + li (clamped)
+  const int bofs0 = kAsmRecA + 3 * li, bofs1 = kAsmRecA + 3 * min(16 + li, 26);
+  // D rows held: m = 16 w + kq + 4 v (r = 3 marks padding)
+  int dm_r[4], dm_o[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = 16 * wave + kq + 4 * v;
+    dm_r[v] = (m < 27) ? m / 9 : 3;
+    dm_o[v] = (m < 27) ? (3 * ((m % 9) / 3) + m % 3) * kWinPad - m / 9 : 0;
+  }
+  // D columns: node l = 16 tn + li; window slot of (l, r, ky, kz) is
+  // dsl(l) - r - 5 ky - 25 kz
+  int dsl[2];
+  bool dn_ok[2];
+#pragma unroll
+  for (int tn = 0; tn < 2; ++tn) {
+    const int n = 16 * tn + li;
+    dn_ok[tn] = n < 27;
+    const int l = min(n, 26);
+    dsl[tn] = (l % 3 + 2) + 5 * ((l / 3) % 3 + 2) + 25 * (l / 9 + 2);
+  }
   __syncthreads();
-  auto next_job = [&](int v, int t0, int& nv, int& nt) {
-    if (v >= 0 && t0 + kAsmChunk < mcnt[v]) {
-      nv = v;
-      nt = t0 + kAsmChunk;
-      return;
-    }
-    nv = nextv[v + 1];
-    nt = 0;
+  // a chunk's records are one contiguous range of np records from particle
+  // p0, read through a buffer resource of exactly that size: the loads past
+  // it return zeros, which fill the unused record slots
+  double2 ld[kStageLd];
+  auto fetch = [&](int p0, int np) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(rec + (long long)p0 * kAsmRec), (short)0, np * kAsmRec * 8, kBufferWord3);
+#pragma unroll
+    for (int j = 0; j < kStageLd; ++j)
+      ld[j] = __builtin_bit_cast(
+          double2, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (tid + kAsmThreads * j), 0, 0));
   };
-  // staging: a chunk's particles are consecutive, so its a_l and C values are
-  // two contiguous ranges; thread tid moves entries tid + 256 k of each
-  auto fetch = [&](int v, int t0, double* ra, double* rc) {
-    if (v < 0) return;
-    const int np = min(kAsmChunk, mcnt[v] - t0);
-    const long long st = mst[v] + t0;
 #pragma unroll
-    for (int k = 0; k < kARegs; ++k)
-      if (tid + 256 * k < kPA * np) ra[k] = Ag[kPA * st + tid + 256 * k];
-#pragma unroll
-    for (int k = 0; k < kCRegs; ++k)
-      if (tid + 256 * k < kPC * np) rc[k] = Cp[kPC * st + tid + 256 * k];
-  };
-  double ra[kARegs], rc[kCRegs];
-#pragma unroll
-  for (int k = 0; k < kARegs; ++k) ra[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < kCRegs; ++k) rc[k] = 0.0;
-  int jv, jt;
-  next_job(-1, 0, jv, jt);
-  fetch(jv, jt, ra, rc);
+  for (int j = 0; j < kStageLd; ++j) ld[j] = make_double2(0.0, 0.0);
+  // the non-empty columns in sweep order: v, with cnt particles from pst
+  int v = nextv[0];
+  int cnt = 0, pst = 0;
+  if (v >= 0) {
+    cnt = mcnt[v];
+    pst = mst[v];
+    fetch(pst, min(kAsmChunk, cnt));
+  }
   int next_row = rb;
   for (int ci = 0; ci < ncx; ++ci) {
     const int c = xa - 2 + ci;
     const int rlo = max(0, xa - c), rhi = min(2, xb - c);
-    for (int col = 0; col < 9; ++col) {
-      const int v = ci * 9 + col;
-      const int cnt = mcnt[v];
-      if (cnt == 0) continue;
+    while (v >= 0 && v < 9 * (ci + 1)) {
+      const int col = v - 9 * ci;
       const int ky = col % 3, kz = col / 3;
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      const int nv = nextv[v + 1];
+      const int ncnt = nv >= 0 ? mcnt[nv] : 0, npst = nv >= 0 ? mst[nv] : 0;
+      const int kofs = kAsmRecA + 3 * (am_r + 3 * ky + 9 * kz);
+      v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       for (int t0 = 0; t0 < cnt; t0 += kAsmChunk) {
-        const int np = min(kAsmChunk, cnt - t0);
+        const bool two = cnt - t0 > 4;  // particles 4.. present (uniform)
         __syncthreads();  // the previous pass's operand reads are done
 #pragma unroll
-        for (int k = 0; k < kARegs; ++k)
-          if (tid + 256 * k < kPA * np) (&av[0][0][0])[tid + 256 * k] = ra[k];
-#pragma unroll
-        for (int k = 0; k < kCRegs; ++k)
-          if (tid + 256 * k < kPC * np) (&pc[0][0])[tid + 256 * k] = rc[k];
+        for (int j = 0; j < kStageLd; ++j)
+          *reinterpret_cast<double2*>(stg + 2 * (tid + kAsmThreads * j)) = ld[j];
         __syncthreads();
         // prefetch the next chunk while this one is processed
-        int nv, nt;
-        next_job(v, t0, nv, nt);
-        fetch(nv, nt, ra, rc);
-        // A operands Z_r[g][3d + e] = sum_b a_k[b] C[3g + b][3d + e], k = (r, ky, kz),
-        // then B[(r, g, d)][l] += sum over the chunk's (p, eps), four at a time
-        {
-          const bool a_ok = am_ok && am_r >= rlo && am_r <= rhi;
-          double za[6];
+        if (t0 + kAsmChunk < cnt)
+          fetch(pst + t0 + kAsmChunk, min(kAsmChunk, cnt - t0 - kAsmChunk));
+        else if (nv >= 0)
+          fetch(npst, min(kAsmChunk, ncnt));
+        // operand reads for this lane's particles q = kq, kq + 4, all issued
+        // before the first use: a_q[k] (k = (r, ky, kz)), the nine C_q
+        // entries of its Z values, and a_q[l] of its two B columns
+        double ca[2][12], bb0[6], bb1[6];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int q = 2 * kq + j;
-            if (a_ok && q < np) {
-              const double* a = av[q][am_r + 3 * ky + 9 * kz];
-              const double* Cq = pc[q];
-              const double a0 = a[0], a1 = a[1], a2 = a[2];
+        for (int h = 0; h < 2; ++h) {
+          const double* R = stg + (kq + 4 * h) * kAsmRec;
 #pragma unroll
-              for (int e = 0; e < 3; ++e)
-                za[3 * j + e] = a0 * Cq[zoff[e]] + a1 * Cq[zoff[3 + e]] + a2 * Cq[zoff[6 + e]];
-            } else {
-              za[3 * j] = za[3 * j + 1] = za[3 * j + 2] = 0.0;
-            }
+          for (int b = 0; b < 3; ++b) ca[h][b] = R[kofs + b];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ca[h][3 + k] = R[zoff[k]];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            bb0[3 * h + e] = R[bofs0 + e];
+            bb1[3 * h + e] = R[bofs1 + e];
           }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // A operands Z_q[(r, g, d)][e]; K step st: particle kq + 4 (st / 3),
+        // component st % 3
+        double za[6];
 #pragma unroll
-          for (int st = 0; st < 6; ++st) {
-            if (st < 3 || np > 1) {  // uniform
-              const int q = 2 * kq + st / 3;
-              const double b = (q < np && bn_ok) ? av[q][bnc][st % 3] : 0.0;
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], b, acc, 0, 0, 0);
-            }
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int e = 0; e < 3; ++e)
+            za[3 * h + e] = ca[h][0] * ca[h][3 + e] + ca[h][1] * ca[h][6 + e] +
+                            ca[h][2] * ca[h][9 + e];
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], bb0[st], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], bb1[st], acc1, 0, 0, 0);
+        }
+        if (two) {
+#pragma unroll
+          for (int st = 3; st < 6; ++st) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], bb0[st], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[st], bb1[st], acc1, 0, 0, 0);
           }
         }
       }
-      // the column's blocks into the sliding window (disjoint per lane/wave):
-      // the four reads first, then the adds and stores
-      if (dn < 27) {
-        double* wp[4];
-        double wv[4];
+      // the column's blocks into the sliding window: this wave's entries
+      // only, the eight reads first, then the adds and stores
+      {
+        const int cofs = -5 * ky - 25 * kz;
+        double* wp[8];
+        double wv[8];
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int r = dm_r[vv] < 3 ? dm_r[vv] : 0;
-          wp[vv] = &win[(c + r + 3) % 3][dm_e[vv] * kSlotPad + dsl0 - r - 5 * ky - 25 * kz];
-          wv[vv] = *wp[vv];
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const int r = dm_r[v4] < 3 ? dm_r[v4] : 0;
+          double* row = win[(c + r + 3) % 3] + dm_o[v4] + cofs;
+          wp[v4] = row + dsl[0];
+          wp[4 + v4] = row + dsl[1];
+          wv[v4] = *wp[v4];
+          wv[4 + v4] = *wp[4 + v4];
         }
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int r = dm_r[vv];
-          if (r >= rlo && r <= rhi) *wp[vv] = wv[vv] + acc[vv];
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const bool rok = dm_r[v4] >= rlo && dm_r[v4] <= rhi;
+          if (rok && dn_ok[0]) *wp[v4] = wv[v4] + acc0[v4];
+          if (rok && dn_ok[1]) *wp[4 + v4] = wv[4 + v4] + acc1[v4];
         }
       }
+      v = nv;
+      cnt = ncnt;
+      pst = npst;
     }
-    __syncthreads();
+    __syncthreads();  // row c's sums are complete
     if (next_row < re && rx[next_row - rb] == c) {
-      int ro = next_row - rb;
-      bool rf = nbf[(c - xw0) + nxw * (2 + 5 * 2)] != 0;
-      finalize_row_block(win[(c + 3) % 3], next_row, c, xw0, L, nbf, fr, rf, rmass[ro], red);
+      const int ro = next_row - rb;
+      const uint8_t* nbx = nbf + (c - xw0);
+      finalize_row(win[(c + 3) % 3], next_row, L, nbx[nxw * (2 + 5 * 2)] != 0,
+                   tid < kSlots && nbx[nbo] != 0, rmass[ro], cb[ro], l1w[wave][ro]);
       ++next_row;
+    } else {
+      clear_row(win[(c + 3) % 3]);
     }
-    double* wz = win[(c + 3) % 3];
-    for (int e = tid; e < kRowStride; e += 256) wz[e] = 0.0;
-    __syncthreads();
+    // (the next pass's first barrier orders this row's clearing before
+    // any later window update)
+  }
+  __syncthreads();
+  // l1 block-Jacobi inverses of the segment's rows, one row per thread
+  for (int ro = tid; ro < re - rb; ro += kAsmThreads) {
+    double Dt[9];
+    for (int k = 0; k < 9; ++k) Dt[k] = cb[ro][k];
+    for (int g = 0; g < 3; ++g) Dt[4 * g] += l1w[0][ro][g] + l1w[1][ro][g];
+    double Di[9];
+    inv3(Dt, Di);
+    const long long i = rb + ro;
+    for (int k = 0; k < 9; ++k) L.Dinv[i * 9 + k] = Di[k];
+    if (L.Hb)
+      for (int k = 0; k < 9; ++k) L.Dinv32[i * 9 + k] = (float)Di[k];
   }
 }
 
@@ -852,11 +883,11 @@ static void node_vel(const LevelView& L0, const double* vstar, const double* dv,
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
                              const double* vstar, const double* dv, double dt, double* wnode,
-                             double* Cp, hipStream_t st) {
+                             double* rec, hipStream_t st) {
   node_vel(L0, vstar, dv, nullptr, 0.0, wnode, st);
   if (n > 0)
     k_particle_hessian<<<blocks_for(n), kTpb, 0, st>>>(s, L0, n, f, key, F, vol, mat,
-                                                       (const double4*)wnode, dt, Cp);
+                                                       (const double4*)wnode, dt, rec);
 }
 
 void launch_particle_eval(const SceneDev& s, const LevelView& L0, int n, const double* f,
@@ -890,13 +921,13 @@ void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, 
 }
 
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        int n, const double* f, const double* F, const double* Cp, double* Ag,
-                        const int* cstart, const int* ccount, const double* mass, const int* fixed,
-                        hipStream_t st) {
+                        int n, const double* f, const double* F, double* rec, const int* cstart,
+                        const int* ccount, const double* mass, const int* fixed, hipStream_t st) {
   const long long n27 = 27LL * n;
-  if (n27 > 0) k_particle_agrad<<<blocks_for(n27), kTpb, 0, st>>>(s, n27, f, F, Ag);
-  if (n_seg > 0)
-    k_assemble_strip<<<n_seg, 256, 0, st>>>(s, L0, seg_begin, Ag, Cp, cstart, ccount, mass, fixed);
+  if (n27 > 0) k_particle_agrad<<<blocks_for(n27), kTpb, 0, st>>>(s, n27, f, F, rec);
+  if (n_seg > 0 && n > 0)
+    k_assemble_strip<<<n_seg, kAsmThreads, 0, st>>>(s, L0, seg_begin, rec, cstart, ccount, mass,
+                                                     fixed);
 }
 
 }  // namespace hot
