@@ -523,23 +523,46 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
 // The assembly's right-hand operands a_lp = F_p^n^T grad w_lp for the 27
 // stencil nodes l of every particle, into the particle's record after C_p,
 // once per step (the assembly visits each particle from up to 9 x-lines).
-// One thread per (particle, node).
-__global__ void k_particle_agrad(SceneDev s, long long n27, const double* __restrict__ f,
-                                 const double* __restrict__ Fn, double* __restrict__ rec) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n27) return;
-  const long long p = e / 27;
-  const int l = (int)(e - 27 * p);
-  double w0, d0, w1, d1, w2, d2;
-  wdw(l % 3, f[3 * p], s.inv_dx, w0, d0);
-  wdw((l / 3) % 3, f[3 * p + 1], s.inv_dx, w1, d1);
-  wdw(l / 9, f[3 * p + 2], s.inv_dx, w2, d2);
-  double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
-  const double* F = Fn + 9 * p;
-  double* o = rec + kAsmRec * p + kAsmRecA + 3 * l;
-  o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
-  o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
-  o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
+// A group of kAgradP particles: their f and F are loaded once into LDS, one
+// thread per (particle, node) forms a_lp there, and the group writes the
+// particles' 81-value blocks as contiguous runs.
+constexpr int kAgradP = 8;
+constexpr int kAgradThreads = 27 * kAgradP;  // 216
+__global__ __launch_bounds__(kAgradThreads) void k_particle_agrad(SceneDev s, int n,
+                                                                  const double* __restrict__ f,
+                                                                  const double* __restrict__ Fn,
+                                                                  double* __restrict__ rec) {
+  __shared__ double pf[kAgradP][12];        // f (3), then F (9)
+  __shared__ double ab[kAgradP * 81];       // the group's a_lp, [particle][l][3]
+  const int tid = threadIdx.x;
+  const long long p0 = (long long)blockIdx.x * kAgradP;
+  const int np = (int)min((long long)kAgradP, (long long)n - p0);
+  if (tid < 12 * np) {
+    const int q = tid / 12, k = tid - 12 * q;
+    pf[q][k] = (k < 3) ? f[3 * (p0 + q) + k] : Fn[9 * (p0 + q) + (k - 3)];
+  }
+  __syncthreads();
+  {
+    const int q = tid / 27, l = tid - 27 * q;
+    if (q < np) {
+      const double* P = pf[q];
+      double w0, d0, w1, d1, w2, d2;
+      wdw(l % 3, P[0], s.inv_dx, w0, d0);
+      wdw((l / 3) % 3, P[1], s.inv_dx, w1, d1);
+      wdw(l / 9, P[2], s.inv_dx, w2, d2);
+      const double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
+      const double* F = P + 3;
+      double* o = ab + 81 * q + 3 * l;
+      o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
+      o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
+      o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 81 * np; e += kAgradThreads) {
+    const int q = e / 81, j = e - 81 * q;
+    rec[kAsmRec * (p0 + q) + kAsmRecA + j] = ab[e];
+  }
 }
 
 // Finalisation of level-0 row i held in the LDS window (the group's
@@ -923,8 +946,8 @@ void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, 
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
                         int n, const double* f, const double* F, double* rec, const int* cstart,
                         const int* ccount, const double* mass, const int* fixed, hipStream_t st) {
-  const long long n27 = 27LL * n;
-  if (n27 > 0) k_particle_agrad<<<blocks_for(n27), kTpb, 0, st>>>(s, n27, f, F, rec);
+  if (n > 0)
+    k_particle_agrad<<<(n + kAgradP - 1) / kAgradP, kAgradThreads, 0, st>>>(s, n, f, F, rec);
   if (n_seg > 0 && n > 0)
     k_assemble_strip<<<n_seg, kAsmThreads, 0, st>>>(s, L0, seg_begin, rec, cstart, ccount, mass,
                                                      fixed);
