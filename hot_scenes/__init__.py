@@ -330,9 +330,36 @@ def small_box(cells=(8, 8, 8), box_lo=(2, 2, 2), box_hi=(5, 6, 5), dx=0.1, seed=
     return sc
 
 
+def stretched_box(side=32, margin=8, seed=6000, E=1e5, levels=3, tol=1e-7, history=8,
+                  per_particle=False) -> Scene:
+    """The stretched-box convergence workload (Sec. 8): a soft FCR box at rest
+    whose deformation gradient starts as a diagonal matrix with entries drawn
+    uniformly from [0.7, 1.3] -- one matrix for the whole box, or with
+    ``per_particle`` one per particle.  No gravity and no boundary conditions,
+    so the first step is the box relaxing from that state.  dx = 1/64, a
+    side^3-cell box (8 particles per cell) centred in a (side + 2 margin)^3
+    grid; nu = 0.3, density 1000; L-BFGS window 8 and CN tolerance 1e-7 (the
+    paper's defaults)."""
+    dx = 1.0 / 64.0
+    n = side + 2 * margin
+    center = np.full(3, (margin + side / 2.0) * dx)
+    sc = _assemble(f"stretched_box_{side}", dx, (n,) * 3, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0),
+                   [((margin,) * 3, (margin + side,) * 3, 0, (0.0, 0.0, 0.0), center)],
+                   [material(FCR, E, 0.3, 1000.0)], [], seed, 0.0,
+                   tol=tol, lbfgs_history=history, mg_levels=levels, n_steps=1)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    d = rng.uniform(0.7, 1.3, size=(sc.n if per_particle else 1, 3))
+    F = np.zeros((sc.n, 3, 3))
+    for a in range(3):
+        F[:, a, a] = d[:, a]
+    sc.F = F
+    return sc
+
+
 CONFIGS = {
     "rotating_cube": rotating_cube,
     "stiffness_bar": stiffness_bar,
     "twisting_bars": twisting_bars,
     "sphere_slab": sphere_slab,
+    "stretched_box": stretched_box,
 }
