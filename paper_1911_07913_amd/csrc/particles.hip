@@ -501,9 +501,9 @@ __global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, con
 // contiguous range of records, 16 bytes per load; record slots past the
 // column's last particle are zero-filled, so every operand read and
 // matrix-core step is unconditional.  After cell c, row c receives nothing
-// more: it is finalised (mass, Dirichlet projection, smoother inverse) and
-// written once.  Every block of every particle is computed exactly once; no
-// atomics.
+// more: it is finalised (mass, Dirichlet projection) and written once; the
+// smoother's block inverses of the segment's rows are formed together at the
+// end.  Every block of every particle is computed exactly once; no atomics.
 constexpr int kAsmChunk = 8;                       // particles staged per pass
 constexpr int kAsmThreads = 128;                   // two waves
 constexpr int kStage = 1024;                       // staged doubles per pass
