@@ -180,7 +180,7 @@ def rotating_cube(cells=32, cube=16, seed=0) -> Scene:
         tol=1e-6, lbfgs_history=5, mg_levels=3, n_steps=1)
 
 
-def twisting_bars(side=16, seed=1000, length=192, n_steps=20, sweeps=4) -> Scene:
+def twisting_bars(side=16, seed=1000, length=192, n_steps=20, sweeps=5) -> Scene:
     """Four parallel Neo-Hookean bars twisted by opposite grips at +-2 rad/s.
 
     Grid 256x64x64 with dx = 1/64; bars run along x over cells [32, 32+length)

@@ -55,7 +55,7 @@ def test_stretched_box_step(levels):
 STRETCHED = {
     "lbfgs_h": (dict(levels=1, sweeps=1), "l1jacobi", 0),
     "hot_sgs": (dict(levels=3, sweeps=1), "sgs", 1),
-    "hot_l1jacobi": (dict(levels=3, sweeps=4), "l1jacobi", 0),
+    "hot_l1jacobi": (dict(levels=3, sweeps=5), "l1jacobi", 0),
 }
 
 
