@@ -371,11 +371,12 @@ hot_status hot_debug_read(const hot_scene* scene, int32_t what, int32_t level, v
  * particle state unchanged) with time step dt (<= 0: CFL rule). */
 hot_status hot_debug_prepare(hot_scene* scene, double dt);
 /* Process-wide settings for tests, applied to launches issued after the call.
- * HOT_SET_MULTIROW_MIN: level size (rows) from which the FP64 smoothing and
- *   residual sweeps of the V-cycle process two rows per wave instead of one
- *   (default 65536; a negative value restores the default).  Both forms
- *   compute every row with the same per-lane arithmetic, so a test can run
- *   either one on any level.
+ * HOT_SET_MULTIROW_MIN: level size (rows) from which the smoothing and
+ *   residual sweeps of the V-cycle run as work-groups over runs of 16
+ *   consecutive rows with the iterate window staged in LDS, instead of one
+ *   row per wave (default 16384 rows; a negative value restores the default).
+ *   Both forms compute every row with the same per-lane arithmetic, so a test
+ *   can run either one on any level.
  * *previous (nullable) receives the old value; an unknown key is
  * HOT_E_INVALID. */
 enum { HOT_SET_MULTIROW_MIN = 1 };

@@ -1843,7 +1843,7 @@ hot_status hot_debug_prepare(hot_scene* scene, double dt) {
 hot_status hot_debug_set(int32_t key, int64_t value, int64_t* previous) {
   if (key != HOT_SET_MULTIROW_MIN) return fail(HOT_E_INVALID, "unknown setting %d", key);
   if (value > INT32_MAX) return fail(HOT_E_INVALID, "value out of range");
-  int old = set_multirow_min(value < 0 ? -1 : (int)value);
+  int old = set_sweep_run_min(value < 0 ? -1 : (int)value);
   if (previous) *previous = old;
   return HOT_OK;
 }

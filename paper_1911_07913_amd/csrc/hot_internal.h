@@ -218,9 +218,10 @@ void launch_to_bf16(const LevelView& L, hipStream_t st);
 void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u, hipStream_t st);
 void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,
                      hipStream_t st);
-// Row count from which the FP64 smoothing and residual sweeps process several
-// rows per wave (process-wide; < 0 restores the default).  Returns the old value.
-int set_multirow_min(int rows);
+// Row count from which the smoothing and residual sweeps run over x-runs
+// instead of one row per wave (process-wide; < 0 restores the default).
+// Returns the old value.
+int set_sweep_run_min(int rows);
 // The V-cycle iterate u of every level (and the smoother's output) is stored
 // on the level's padded dense grid as 4-vectors (double4 or float4); b and r
 // are compact [n][3].

@@ -8,6 +8,7 @@
 // The FP64 path stores blocks as double; the mixed path stores BF16 blocks and
 // runs the V-cycle vectors and accumulation in FP32.
 #include <atomic>
+#include <type_traits>
 
 #include "mpm_math.h"
 
@@ -173,9 +174,7 @@ __device__ inline void row_matvec(const LevelView& L, int i, const V* __restrict
 
 // y_r = H_{i0+r} . x for R consecutive rows, computed by one wave with all
 // of the rows' loads issued before any is consumed, so that R rows' worth of
-// bytes are in flight per wave (a single row leaves the wave waiting on three
-// dependent memory round trips).  Large levels use SweepRows<V>::R rows per
-// wave; small levels one row per wave, to keep enough waves in flight.  FP64 blocks: lane l owns slots l and l + 64
+// bytes are in flight per wave.  FP64 blocks: lane l owns slots l and l + 64
 // (512-byte coalesced loads per entry).  BF16 blocks: lane l owns slots 2l and
 // 2l + 1 and reads both with one 32-bit load per entry.  Rows at or beyond
 // L.n contribute nothing.  Results are valid in all lanes.
@@ -185,7 +184,6 @@ struct SweepRows;
 // evicting the gathered iterate from L2.
 template <>
 struct SweepRows<double> {
-  static constexpr int R = 2;
   static __device__ inline int slot(int lane, int k) { return lane + 64 * k; }
   static __device__ inline void load(const double* Hrow, int c, int lane, bool p0, bool p1,
                                      double& h0, double& h1) {
@@ -201,10 +199,6 @@ struct SweepRows<double> {
 };
 template <>
 struct SweepRows<float> {
-  // one row per wave: the BF16 rows are short (2.3 KB), and more waves in
-  // flight beat more rows per wave here (measured: 1 row 0.157 ms, 2 rows
-  // 0.160 ms, 4 rows 0.173 ms per level-0 sweep at 1.5M particles)
-  static constexpr int R = 1;
   static __device__ inline int slot(int lane, int k) { return 2 * lane + k; }
   static __device__ inline void load(const uint16_t* Hrow, int c, int lane, bool p0, bool p1,
                                      float& h0, float& h1) {
@@ -610,6 +604,153 @@ __global__ __launch_bounds__(256) void k_smooth(LevelView L, const V* __restrict
       V upd = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
       V out = comp<V>(u4, pn, c) + upd;
       comp<V>(uo4, pn, c) = L.free_dof[3 * i + c] ? out : (V)0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sweeps over x-runs
+// Large levels: a work-group of four waves takes kRunRows consecutive rows.
+// Rows are ordered x fastest, so away from the edges of the active set these
+// are one run of consecutive grid points along x, whose 125-point stencils
+// together cover a window of 25 lines (dy, dz) of kRunRows + 4 points.  The
+// work-group loads that window of the iterate, and the rows' pattern words,
+// right-hand sides, block-Jacobi inverses and free flags, into LDS with
+// contiguous loads; a row then reads only its blocks from memory.  (A sweep
+// that gathers the neighbour values per row issues two 64-address gathers
+// and about eight small loads per row, which in the BF16 sweeps keep the
+// vector-memory address units about 80% busy.)  A work-group whose rows are
+// not one run gathers the neighbour values from memory.  Every row's
+// arithmetic is that of rows_matvec and k_smooth / k_residual, in the same
+// order (identical bits).
+constexpr int kRunRows = 16;
+constexpr int kRunWin = kRunRows + 4;  // window points per line
+template <typename V>
+struct RunRows;  // rows per wave per pass
+template <>
+struct RunRows<float> {
+  static constexpr int R = 4;
+};
+template <>
+struct RunRows<double> {
+  static constexpr int R = 1;
+};
+
+template <typename V, bool Smooth>
+__global__ __launch_bounds__(256) void k_sweep_run(LevelView L, const V* __restrict__ b,
+                                                   const typename Vec4Of<V>::type* __restrict__ u4,
+                                                   typename Vec4Of<V>::type* __restrict__ uo4,
+                                                   V* __restrict__ rout) {
+  typedef typename Vec4Of<V>::type V4;
+  typedef typename MatOf<V>::type M;
+  constexpr int R = RunRows<V>::R;
+  static_assert(9 * kRunRows <= 256 && kRunRows <= 64, "staging assumes one pass per array");
+  static_assert(kRunRows % (kRowWaves * R) == 0, "rows split evenly over the waves");
+  __shared__ V4 win[25 * kRunWin];
+  __shared__ uint4 spat[kRunRows];
+  __shared__ int spn[kRunRows];
+  __shared__ V sb[3 * kRunRows];
+  __shared__ V sd[Smooth ? 9 * kRunRows : 1];
+  __shared__ uint8_t sf[Smooth ? 3 * kRunRows : 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int i0 = xcd_block(blockIdx.x, gridDim.x) * kRunRows;
+  const int nr = min(kRunRows, L.n - i0);
+  if (tid < nr) {
+    spat[tid] = reinterpret_cast<const uint4*>(L.pat)[i0 + tid];
+    spn[tid] = L.nodes[i0 + tid];
+  }
+  if (tid < 3 * nr) {
+    sb[tid] = b[3 * (long long)i0 + tid];
+    if (Smooth) sf[tid] = L.free_dof[3 * (long long)i0 + tid];
+  }
+  if (Smooth && tid < 9 * nr) sd[tid] = MatOf<V>::Dinv(L)[9 * (long long)i0 + tid];
+  __syncthreads();
+  const int pn0 = spn[0];
+  const bool run = __ballot(lane >= nr || spn[min(lane, kRunRows - 1)] == pn0 + lane) == ~0ull;
+  if (run) {
+    // the window: points pn0 - 2 .. pn0 + nr + 1 of the 25 lines (dy, dz),
+    // all inside the padded grid
+    const int nw = nr + 4;
+    for (int e = tid; e < 25 * nw; e += 256) {
+      const int line = e / nw, xo = e - line * nw;
+      const long long p = (long long)pn0 + (xo - 2) +
+                          (long long)L.g.pd[0] * ((line % 5 - 2) + (long long)L.g.pd[1] * (line / 5 - 2));
+      win[line * kRunWin + xo] = u4[p];
+    }
+  }
+  __syncthreads();
+  // this lane's two slots: window line offset and x offset
+  int sl[2], sx[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int s = SweepRows<V>::slot(lane, k);
+    sl[k] = (s / 5) * kRunWin;
+    sx[k] = s % 5;
+  }
+#pragma unroll 1
+  for (int t0 = wave * (kRunRows / kRowWaves); t0 < (wave + 1) * (kRunRows / kRowWaves); t0 += R) {
+    if (t0 >= nr) break;
+    V h[R][2][9];
+    bool pr[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = t0 + r;
+      const bool live = t < nr;
+      const M* Hrow = MatOf<V>::H(L) + (long long)(i0 + (live ? t : 0)) * kRowStride;
+      const uint4 pw = live ? spat[t] : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t w[4] = {pw.x, pw.y, pw.z, pw.w};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) pr[r][k] = slot_present(w, SweepRows<V>::slot(lane, k));
+#pragma unroll
+      for (int c = 0; c < 9; ++c)
+        SweepRows<V>::load(Hrow, c, lane, pr[r][0], pr[r][1], h[r][0][c], h[r][1][c]);
+    }
+    V y[R][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = t0 + r;
+      V a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (pr[r][k]) {
+          const V4 xv = run ? win[sl[k] + t + sx[k]]
+                            : u4[spn[t] + slot_offset(L.g, SweepRows<V>::slot(lane, k))];
+          const V x0 = xv.x, x1 = xv.y, x2 = xv.z;
+          a0 += h[r][k][0] * x0 + h[r][k][1] * x1 + h[r][k][2] * x2;
+          a1 += h[r][k][3] * x0 + h[r][k][4] * x1 + h[r][k][5] * x2;
+          a2 += h[r][k][6] * x0 + h[r][k][7] * x1 + h[r][k][8] * x2;
+        }
+      }
+      y[r][0] = wave_sum_dpp(a0);
+      y[r][1] = wave_sum_dpp(a1);
+      y[r][2] = wave_sum_dpp(a2);
+    }
+    if (lane < 3 * R) {
+      const int rr = lane / 3, c = lane - 3 * rr;
+      const int t = t0 + rr;
+      V y0 = y[0][0], y1 = y[0][1], y2 = y[0][2];
+#pragma unroll
+      for (int q = 1; q < R; ++q)
+        if (q == rr) {
+          y0 = y[q][0];
+          y1 = y[q][1];
+          y2 = y[q][2];
+        }
+      if (t < nr) {
+        const long long i = i0 + t;
+        if (Smooth) {
+          const int pn = spn[t];
+          const V* Di = sd + 9 * t;
+          const V r0 = sb[3 * t] - y0, r1 = sb[3 * t + 1] - y1, r2 = sb[3 * t + 2] - y2;
+          const V upd = Di[3 * c] * r0 + Di[3 * c + 1] * r1 + Di[3 * c + 2] * r2;
+          const V uc = run ? reinterpret_cast<const V*>(win + 12 * kRunWin + t + 2)[c]
+                           : comp<V>(u4, pn, c);
+          const V out = uc + upd;
+          comp<V>(uo4, pn, c) = sf[3 * t + c] ? out : (V)0;
+        } else {
+          const V yv = c == 0 ? y0 : (c == 1 ? y1 : y2);
+          rout[3 * i + c] = sb[3 * t + c] - yv;
+        }
+      }
     }
   }
 }
@@ -1362,26 +1503,30 @@ void launch_jacobi_first(const LevelView& L, bool mixed, const void* b, void* u,
   else
     k_jacobi_first<double><<<blocks_for(L.n), kTpb, 0, st>>>(L, (const double*)b, (double4*)u);
 }
-// Levels with at least this many rows run several rows per wave (FP64:
-// SweepRows<double>::R).  Held in a process-wide variable so that a test can
-// move the threshold and run either form of the sweep on any level.
-constexpr int kMultiRowMinDefault = 65536;
-static std::atomic<int> g_multirow_min{kMultiRowMinDefault};
+// Sweeps of levels of at least kRunMin rows run over x-runs (k_sweep_run);
+// on smaller levels its fewer, longer work-groups leave the device
+// under-filled, and one row per wave is faster.  A process-wide override
+// (-1: the default) lets a test run either form on any level.
+constexpr int kRunMin = 16384;
+static std::atomic<int> g_run_min{-1};
+inline int run_min() {
+  const int v = g_run_min.load(std::memory_order_relaxed);
+  return v >= 0 ? v : kRunMin;
+}
 
 template <typename V>
 void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, void* out,
                   hipStream_t st) {
   typedef typename Vec4Of<V>::type V4;
-  constexpr int R = SweepRows<V>::R;
   const V4* u4 = (const V4*)u;
-  if (L.n >= g_multirow_min.load(std::memory_order_relaxed)) {
-    unsigned g = (unsigned)((L.n + kRowWaves * R - 1) / (kRowWaves * R));
+  if (L.n >= run_min()) {
+    const unsigned g = (unsigned)((L.n + kRunRows - 1) / kRunRows);
     if (smooth)
-      k_smooth<V, R><<<g, 256, 0, st>>>(L, b, u4, (V4*)out);
+      k_sweep_run<V, true><<<g, 256, 0, st>>>(L, b, u4, (V4*)out, nullptr);
     else
-      k_residual<V, R><<<g, 256, 0, st>>>(L, b, u4, (V*)out);
+      k_sweep_run<V, false><<<g, 256, 0, st>>>(L, b, u4, nullptr, (V*)out);
   } else {
-    unsigned g = (unsigned)((L.n + kRowWaves - 1) / kRowWaves);
+    const unsigned g = (unsigned)((L.n + kRowWaves - 1) / kRowWaves);
     if (smooth)
       k_smooth<V, 1><<<g, 256, 0, st>>>(L, b, u4, (V4*)out);
     else
@@ -1389,8 +1534,9 @@ void sweep_launch(bool smooth, const LevelView& L, const V* b, const void* u, vo
   }
 }
 
-int set_multirow_min(int rows) {
-  return g_multirow_min.exchange(rows < 0 ? kMultiRowMinDefault : rows);
+int set_sweep_run_min(int rows) {
+  const int old = g_run_min.exchange(rows < 0 ? -1 : rows);
+  return old < 0 ? kRunMin : old;
 }
 
 void launch_residual(const LevelView& L, bool mixed, const void* b, const void* u, void* r,

@@ -181,11 +181,12 @@ def test_sphere_slab_full_size_mixed():
     assert np.all(nd <= lim * (1.0 + 1e-9))
 
 
-def test_two_rows_per_wave_sweeps_bit_identical_at_full_size(full):
-    """Level 0 of this scene (281,580 rows) runs the FP64 sweeps two rows per
-    wave.  The same V-cycle with one row per wave on every level (the form
-    that the oracle-compared small scenes run by default) is bit-identical,
-    and so is a whole step."""
+def test_run_form_sweeps_bit_identical_at_full_size(full):
+    """Levels 0 and 1 of this scene (281,580 and 47,916 rows) run the sweeps
+    over x-runs with the iterate staged in LDS.  The same V-cycle with one
+    row per wave on every level (the form that the oracle-compared small
+    scenes run by default) is bit-identical, in FP64 and in mixed precision,
+    and so is a whole FP64 step."""
     hot = _hot()
     sc, dt, g = full
     n = g.debug_read(hot.DBG_LEVEL_NODES, 0, dtype=np.int32).size
@@ -198,6 +199,18 @@ def test_two_rows_per_wave_sweeps_bit_identical_at_full_size(full):
     finally:
         hot.debug_set(hot.SET_MULTIROW_MIN, -1)
     assert np.array_equal(u1, u2)
+    m = hot.Scene.from_scene(sc, precision=hot.HOT_MIXED)
+    try:
+        m.debug_prepare(dt)
+        v2 = m.debug_apply(0, b)
+        try:
+            hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30)
+            v1 = m.debug_apply(0, b)
+        finally:
+            hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+    finally:
+        m.close()
+    assert np.array_equal(v1, v2)
     outs = []
     for forced in (None, 1 << 30):
         s = hot.Scene.from_scene(sc)

@@ -74,6 +74,25 @@ def test_mixed_vcycle_close_to_fp64(prepared_mixed):
     assert np.all(ug[hz.free[0] == 0] == 0.0)
 
 
+def test_mixed_vcycle_run_form_bit_identical(prepared_mixed):
+    """The BF16 sweeps' large-level form (work-groups over runs of 16 rows
+    with the iterate window in LDS, and a memory gather where the rows are
+    not one run), forced onto every level, gives the one-row V-cycle bit for
+    bit."""
+    hot = _hot()
+    name, sc, dt, st, hz, g = prepared_mixed
+    n = st.lev0.n
+    b = np.random.Generator(np.random.PCG64(16)).normal(size=3 * n) * hz.free[0]
+    try:
+        hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30)
+        u1 = g.debug_apply(0, b)
+        hot.debug_set(hot.SET_MULTIROW_MIN, 0)
+        u2 = g.debug_apply(0, b)
+    finally:
+        hot.debug_set(hot.SET_MULTIROW_MIN, -1)
+    assert np.array_equal(u1, u2)
+
+
 def _mixed_vs_oracle(sc, smoother="l1jacobi"):
     """The oracle's FP64 step and the library's mixed-precision step of the
     same scene at the scene's tolerance, with the same smoother."""

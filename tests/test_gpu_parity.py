@@ -152,20 +152,22 @@ def _compare_step(sc, precision=0, tol_x=1e-10, tol_v=1e-10):
     return out, info, res, logi, cn, st, g.stats
 
 
-@pytest.fixture(params=["one_row", "two_rows"])
+@pytest.fixture(params=["one_row", "run_form"])
 def rows_per_wave(request):
-    """Run the FP64 smoothing and residual sweeps with one row per wave on
-    every level ("one_row"), or with the two-rows-per-wave form that large
-    levels use, forced onto every level ("two_rows")."""
+    """Run the smoothing and residual sweeps with one row per wave on every
+    level ("one_row"), or in the form that large levels use (work-groups over
+    runs of 16 rows with the iterate window in LDS), forced onto every level
+    ("run_form")."""
     hot = _hot()
     hot.debug_set(hot.SET_MULTIROW_MIN, 1 << 30 if request.param == "one_row" else 0)
     yield request.param
     hot.debug_set(hot.SET_MULTIROW_MIN, -1)
 
 
-def test_vcycle_two_rows_per_wave(prepared):
-    """The two-rows-per-wave sweeps give the one-row V-cycle bit for bit, and
-    so match the oracle's V-cycle."""
+def test_vcycle_run_form(prepared):
+    """The large-level form of the sweeps (x-runs, iterate window in LDS),
+    forced onto every level, gives the one-row V-cycle bit for bit, and so
+    matches the oracle's V-cycle."""
     hot = _hot()
     name, sc, dt, st, hz, g = prepared
     n = st.lev0.n
