@@ -11,6 +11,7 @@ quantities are computed with vectorised numpy over particles, scatters use
 ``-m "not gpu"`` tests in ``tests/test_oracle_*.py`` (B-spline identities,
 material finite differences and closed forms, pattern counts in closed form,
 Galerkin vs dense products and vs the composite-kernel re-discretisation,
+the quadratic embedding's weight moments and Galerkin energy identity,
 V-cycle symmetry and exactness, two-loop vs dense BFGS, converged step vs a
 dense projected-Newton minimiser, boundary conditions and the time-step rule
 in closed form, l1 block-Jacobi special cases and contraction, coarsest PCG
@@ -196,25 +197,62 @@ def parents_1d(c):
     return J0, J1, w0, w1
 
 
-def coarse_dims(dims):
-    return np.asarray(dims, dtype=np.int64) // 2 + 1
+def quad_bspline(t):
+    """Quadratic B-spline N(t) of unit spacing, support |t| < 3/2."""
+    a = np.abs(np.asarray(t, dtype=np.float64))
+    return np.where(a <= 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
 
 
-def prolongation(fine: Level):
+def parents_1d_quadratic(c):
+    """Quadratic node embedding along one axis, the alternative kernel of
+    Sec. 4.2 (HOT-quadratic in Sec. 7): coarse node J sits at fine node 2J and
+    weighs fine node c by the quadratic B-spline of the coarse spacing,
+    N((c - 2J) / 2).  The parents are J = floor(c/2) - 1 .. floor(c/2) + 1;
+    returns (J0, J1, J2, w0, w1, w2) (a weight is 0 where 2J is 3 or more
+    fine nodes away)."""
+    c = np.asarray(c, dtype=np.int64)
+    h = c // 2
+    Js = [h - 1, h, h + 1]
+    ws = [quad_bspline((c - 2 * J) / 2.0) for J in Js]
+    return (*Js, *ws)
+
+
+def coarse_dims(dims, embedding="linear"):
+    d = np.asarray(dims, dtype=np.int64)
+    return d // 2 + 1 if embedding == "linear" else (d + 2) // 2 + 2
+
+
+def prolongation(fine: Level, embedding="linear"):
     """Prolongation P (node level, n_fine x n_coarse) and the coarse level.
 
     P = R^T with R = (d x^0 / d x^1)^T (Sec. 4.1); entries are products of the
-    per-axis linear weights 1 and 1/2 (Sec. 4.2), so 3^d nonzeros per coarse
-    column (Sec. 6)."""
-    cd = coarse_dims(fine.dims)
+    per-axis embedding weights.  Linear (HOT, Sec. 4.2): 1 and 1/2, so 3^d
+    nonzeros per coarse column (Sec. 6).  Quadratic (HOT-quadratic): the
+    coarse quadratic B-spline at the fine nodes, 3/4, 1/2 and 1/8, 5^d
+    nonzeros per coarse column; its coarse node K sits at fine node 2K - 2
+    (the coarse grid keeps one node of margin below the fine one, so that
+    nodes at the lower edge of every level keep all their parents)."""
+    cd = coarse_dims(fine.dims, embedding)
     rows, cols, vals = [], [], []
-    per_axis = [parents_1d(fine.coords[:, a]) for a in range(3)]
-    for sx in range(2):
-        for sy in range(2):
-            for sz in range(2):
+    if embedding == "linear":
+        per_axis = [parents_1d(fine.coords[:, a]) for a in range(3)]
+        npar = 2
+    elif embedding == "quadratic":
+        per_axis = [parents_1d_quadratic(fine.coords[:, a] + 2) for a in range(3)]
+        npar = 3
+    else:
+        raise ValueError(f"unknown embedding {embedding!r}")
+    for sx in range(npar):
+        for sy in range(npar):
+            for sz in range(npar):
                 J = np.stack([per_axis[0][sx], per_axis[1][sy], per_axis[2][sz]], -1)
-                w = per_axis[0][2 + sx] * per_axis[1][2 + sy] * per_axis[2][2 + sz]
+                w = (per_axis[0][npar + sx] * per_axis[1][npar + sy] *
+                     per_axis[2][npar + sz])
                 keep = w > 0
+                if np.any(keep):
+                    Jk = J[keep]
+                    if np.any(Jk < 0) or np.any(Jk >= cd[None, :]):
+                        raise ValueError("a coarse parent falls outside the coarse grid")
                 rows.append(np.nonzero(keep)[0])
                 cols.append(linear(J[keep], cd))
                 vals.append(w[keep])
@@ -570,12 +608,16 @@ class Hierarchy:
     pass
 
 
-def build_hierarchy(st, H0_slots, nbr0, levels, project_pattern=True):
+def build_hierarchy(st, H0_slots, nbr0, levels, project_pattern=True, embedding="linear"):
     """Galerkin hierarchy H^{m+1} = P~^T H^m P~ (Eq. buildMultigrid, Sec. 4.1)
     with P~ = Pi P: rows of constrained fine DOFs are removed before the
     product so Dirichlet conditions hold at every level.  A coarse DOF whose
     diagonal comes out exactly zero has no free fine DOF below it; it is
-    constrained at its level (diagonal set to 1)."""
+    constrained at its level (diagonal set to 1).  embedding: "linear" (HOT)
+    or "quadratic" (HOT-quadratic, whose coarse stencils reach 3 nodes, so
+    no 125-slot patterns are formed)."""
+    if embedding != "linear":
+        project_pattern = False
     hz = Hierarchy()
     lev = st.lev0
     hz.levels = [lev]
@@ -591,7 +633,7 @@ def build_hierarchy(st, H0_slots, nbr0, levels, project_pattern=True):
     hz.Pnode = []
     hz.patterns = [fine_pattern(st.scene, lev)] if project_pattern else [None]
     for m in range(levels - 1):
-        Pn, coarse = prolongation(lev)
+        Pn, coarse = prolongation(lev, embedding)
         Pd = sp.kron(Pn, sp.identity(3), format="csr")
         Pt = sp.diags(hz.free[m]) @ Pd
         Ac = (Pt.T @ hz.A[m] @ Pt).tocsr()
@@ -1032,10 +1074,16 @@ def g2p(st, dv):
 
 
 def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=None,
-         sweeps=None, return_internals=False, smoother="l1jacobi", solver="hot"):
+         sweeps=None, return_internals=False, smoother="l1jacobi", solver="hot",
+         embedding="linear"):
     """One implicit MPM step: P2G, the solve for dv, G2P (Sec. 3.1).  solver:
     "hot" (Alg. HOT), "pn-pcg" or "pn-mgpcg" (Alg. 1 with the diagonal or the
-    multigrid preconditioner)."""
+    multigrid preconditioner).  embedding "quadratic" builds HOT's hierarchy
+    with the quadratic node embedding (HOT-quadratic, Sec. 7; l1 block-Jacobi
+    smoothing only: the colouring of the Gauss-Seidel smoother assumes
+    stencils of +-2 nodes)."""
+    if embedding != "linear" and smoother != "l1jacobi":
+        raise ValueError("the quadratic embedding is built with l1 block-Jacobi smoothing only")
     if dt is None or dt <= 0:
         dt = time_step(scene)
     levels = scene.mg_levels if levels is None else levels
@@ -1054,7 +1102,7 @@ def step(scene, dt=None, t=0.0, levels=None, history=None, tol=None, max_iters=N
             return out, info, dict(st=st, dv=dv)
         return out, info
     H0, nbr0 = hessian_slots(st)
-    hz = build_hierarchy(st, H0, nbr0, levels)
+    hz = build_hierarchy(st, H0, nbr0, levels, embedding=embedding)
     dv, info = solve(st, hz, tol, history, max_iters=max_iters, sweeps=sweeps,
                      smoother=smoother)
     out = g2p(st, dv)
