@@ -236,20 +236,21 @@ __global__ void k_node_vel(LevelView L, const double* __restrict__ vstar,
   wn[L.nodes[i]] = make_double4(vel[0], vel[1], vel[2], 0.0);
 }
 
-// F_p(dv) = (I + dt sum_i v_i grad w_ip^T) F_p^n with v_i from k_node_vel.
-__device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pidx_key,
-                                  const double* fp, const double* Fn,
-                                  const double4* __restrict__ wn, double dt, double* F) {
+// F_p(dv) = (I + dt sum_i v_i grad w_ip^T) F_p^n with v_i from k_node_vel;
+// node_v(k, vel) supplies the velocity of stencil node k.
+template <typename NodeV>
+__device__ inline void particle_F_with(const SceneDev& s, const double* fp, const double* Fn,
+                                       double dt, double* F, NodeV node_v) {
   Weights W;
   bspline_weights(fp, s.inv_dx, W);
   double gv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    const double4 wv = wn[pidx_key + stencil_offset(L.g, k)];
+    double vel[3];
+    node_v(k, vel);
     double g[3];
     node_grad(W, kx, ky, kz, g);
-    const double vel[3] = {wv.x, wv.y, wv.z};
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) gv[3 * a + b] += vel[a] * g[b];
   }
@@ -262,6 +263,16 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
       }
       F[3 * r + c] = acc;
     }
+}
+__device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pidx_key,
+                                  const double* fp, const double* Fn,
+                                  const double4* __restrict__ wn, double dt, double* F) {
+  particle_F_with(s, fp, Fn, dt, F, [&](int k, double* vel) {
+    const double4 wv = wn[pidx_key + stencil_offset(L.g, k)];
+    vel[0] = wv.x;
+    vel[1] = wv.y;
+    vel[2] = wv.z;
+  });
 }
 
 // Per-particle projected stress derivative at dv = 0, scaled by dt^2 V_p
@@ -285,16 +296,53 @@ __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView 
 
 // Energy density and stress at the trial point: psi_out[p] = V_p psi(F_p),
 // S_out[p] = V_p P(F_p) F_p^n^T (the particle's force tensor, Sec. 4.1).
+// Particles are sorted by base node, so the block's particles usually have
+// base nodes within a short run of padded indices k0 .. k1; their 27-node
+// stencils then read, for each of the 9 (y, z) offsets, a contiguous range
+// of the node array of k1 - k0 + 3 nodes.  The block stages those ranges in
+// LDS with contiguous loads and each particle reads its nodes there (the
+// per-particle gathers of 27 nodes keep the vector-memory address units
+// over 80% busy); particles outside the staged range, and blocks whose range
+// is too long, read the node array directly.  The values and the order of
+// the sums are those of the direct form (identical bits).
+constexpr int kEvalWin = 64;  // staged nodes per (y, z) offset
 __global__ __launch_bounds__(256) void k_particle_eval(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                 const int* __restrict__ key, const double* __restrict__ Fn,
                                 const double* __restrict__ vol, const int* __restrict__ mat,
                                 const double4* __restrict__ wn, double dt,
                                 double* __restrict__ psi_out, double* __restrict__ S_out) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double win[3][9 * kEvalWin];
+  const int tid = threadIdx.x;
+  const int pb = blockIdx.x * blockDim.x;
+  const int p = pb + tid;
+  const int k0 = key[pb], k1 = key[min(pb + (int)blockDim.x, n) - 1];
+  const int span = k1 - k0 + 3;  // nodes per staged range
+  const bool staged = k1 >= k0 && span <= kEvalWin;
+  if (staged) {
+    for (int e = tid; e < 9 * span; e += blockDim.x) {
+      const int r = e / span, xo = e - r * span;  // r = ky + 3 kz
+      const double4 wv = wn[k0 + xo + stencil_offset(L.g, 3 * r)];
+      win[0][r * kEvalWin + xo] = wv.x;
+      win[1][r * kEvalWin + xo] = wv.y;
+      win[2][r * kEvalWin + xo] = wv.z;
+    }
+  }
+  __syncthreads();
   if (p >= n) return;
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
-  particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
+  const int kp = key[p];
+  const int d = kp - k0;
+  if (staged && d >= 0 && d + 2 < span) {
+    particle_F_with(s, f + 3 * p, fn, dt, F, [&](int k, double* vel) {
+      const int e = (k / 3) * kEvalWin + d + k % 3;
+      vel[0] = win[0][e];
+      vel[1] = win[1][e];
+      vel[2] = win[2][e];
+    });
+  } else {
+    particle_F(s, L, kp, f + 3 * p, fn, wn, dt, F);
+  }
   double P[9];
   double ps = psi_and_piola(s.mats[mat[p]], F, P);
   double V = vol[p];
