@@ -169,32 +169,59 @@ __global__ void k_fill(long long n, int* p, int v) {
 
 // Level-0 symbolic pattern: block (i, j) is present iff some particle's
 // stencil holds both nodes, i.e. some non-empty base cell b satisfies
-// b in [max(i,j) - 2, min(i,j)] on every axis.  One thread per (row, word).
+// b in [max(i,j) - 2, min(i,j)] on every axis.  Only the 27 base cells
+// i + r, r in [-2, 0]^3, can serve row i; slot d (offset j - i) is served by
+// the cells with r in [max(-2, d - 2), min(0, d)] per axis.  One thread per
+// row loads the row's 27 cell occupancies once and forms each slot's bit
+// against that slot's cell mask.
+struct SlotCellMasks {
+  uint32_t m[kSlots];  // bit r = rx + 3 ry + 9 rz: cell i + (rx - 2, ry - 2, rz - 2) serves the slot
+};
+constexpr SlotCellMasks make_slot_cell_masks() {
+  SlotCellMasks t{};
+  for (int s = 0; s < kSlots; ++s) {
+    const int d[3] = {s % 5 - 2, (s / 5) % 5 - 2, s / 25 - 2};
+    uint32_t m = 0;
+    for (int r = 0; r < 27; ++r) {
+      const int rr[3] = {r % 3 - 2, (r / 3) % 3 - 2, r / 9 - 2};
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        const int lo = d[a] - 2 > -2 ? d[a] - 2 : -2;
+        const int hi = d[a] < 0 ? d[a] : 0;
+        if (rr[a] < lo || rr[a] > hi) ok = false;
+      }
+      if (ok) m |= 1u << r;
+    }
+    t.m[s] = m;
+  }
+  return t;
+}
+__constant__ SlotCellMasks kSlotCellMasks = make_slot_cell_masks();
+
 __global__ void k_fine_pattern(LevelView L, const int* __restrict__ counts) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)L.n * 4) return;
-  int row = (int)(t >> 2), w = (int)(t & 3);
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= L.n) return;
   int x, y, z;
   unpidx(L.g, L.nodes[row], x, y, z);
-  uint32_t bits = 0;
-  for (int k = 0; k < 32; ++k) {
-    int s = w * 32 + k;
-    if (s >= kSlots) break;
-    int dx = s % 5 - 2, dy = (s / 5) % 5 - 2, dz = s / 25 - 2;
-    int lo[3] = {max(x, x + dx) - 2, max(y, y + dy) - 2, max(z, z + dz) - 2};
-    int hi[3] = {min(x, x + dx), min(y, y + dy), min(z, z + dz)};
-    bool any = false;
-    for (int bz = lo[2]; bz <= hi[2] && !any; ++bz)
-      for (int by = lo[1]; by <= hi[1] && !any; ++by)
-        for (int bx = lo[0]; bx <= hi[0] && !any; ++bx) {
-          if (bx < -2 || by < -2 || bz < -2 || bx >= L.g.dims[0] + 2 || by >= L.g.dims[1] + 2 ||
-              bz >= L.g.dims[2] + 2)
-            continue;
-          any = counts[pidx(L.g, bx, by, bz)] > 0;
-        }
-    if (any) bits |= (1u << k);
+  uint32_t occ = 0;
+#pragma unroll
+  for (int r = 0; r < 27; ++r) {
+    const int bx = x + r % 3 - 2, by = y + (r / 3) % 3 - 2, bz = z + r / 9 - 2;
+    if (bx < -2 || by < -2 || bz < -2 || bx >= L.g.dims[0] + 2 || by >= L.g.dims[1] + 2 ||
+        bz >= L.g.dims[2] + 2)
+      continue;
+    if (counts[pidx(L.g, bx, by, bz)] > 0) occ |= 1u << r;
   }
-  L.pat[t] = bits;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int s = w * 32 + k;
+      if (s < kSlots && (occ & kSlotCellMasks.m[s])) bits |= 1u << k;
+    }
+    L.pat[4 * (long long)row + w] = bits;
+  }
 }
 
 // Number of structurally present blocks of a level (popcount of its pattern),
@@ -382,7 +409,7 @@ void launch_fill_int(long long n, int* p, int v, hipStream_t st) {
   if (n > 0) k_fill<<<blocks_for(n), kTpb, 0, st>>>(n, p, v);
 }
 void launch_fine_pattern(const LevelView& L, const int* counts, hipStream_t st) {
-  if (L.n > 0) k_fine_pattern<<<blocks_for((long long)L.n * 4), kTpb, 0, st>>>(L, counts);
+  if (L.n > 0) k_fine_pattern<<<blocks_for(L.n), kTpb, 0, st>>>(L, counts);
 }
 
 void launch_seg_flags(const LevelView& L, int* flags, hipStream_t st) {
