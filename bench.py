@@ -504,6 +504,10 @@ def main():
                     help="skip the stretched-box convergence comparison")
     ap.add_argument("--no-mixed-error", action="store_true",
                     help="skip the per-step mixed-vs-FP64 error pass (untimed)")
+    ap.add_argument("--sweep-run-min", type=int, default=None,
+                    help="level size (rows) from which the V-cycle sweeps stage x-runs in LDS "
+                         "(default: the library's; a huge value keeps every level one row per "
+                         "wave, to profile that form)")
     ap.add_argument("--cpu-worker", action="store_true")
     a = ap.parse_args()
     if a.cpu_worker:
@@ -520,6 +524,8 @@ def main():
     from paper_1911_07913_amd import hot
     hot.lib()
     assert torch.cuda.is_available(), "no HIP device"
+    if a.sweep_run_min is not None:
+        hot.debug_set(hot.SET_MULTIROW_MIN, a.sweep_run_min)
 
     def prec_name(p):
         return "fp64" if p == hot.HOT_FP64 else "mixed"
@@ -572,6 +578,8 @@ def main():
                         "gbs": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                     for k, v in r["prof"].items()},
     }
+    if a.sweep_run_min is not None:
+        line["config"]["sweep_run_min"] = a.sweep_run_min
     if hot.HOT_MIXED in results and main_p != hot.HOT_MIXED:
         rm = results[hot.HOT_MIXED]
         line["mixed"] = {"value": a.steps / rm["seconds"], "unit": "steps/s",
