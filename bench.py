@@ -33,15 +33,16 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 # What bounds each traced kernel, and the algorithmic FP64 flops of the
-# ALU-bound ones per particle.  Level-0 assembly per particle: a_ip = F^T grad w
-# for 27 nodes (27 x 9 FMA), C+ a_jp for 27 nodes (27 x 81 FMA), and the 378
+# ALU-bound ones per particle.  Level-0 assembly per particle, from the
+# particle's C+ and a_ip = F^T grad w operands (formed with C+ in the
+# stress-derivative pass): C+ a_jp for 27 nodes (27 x 81 FMA) and the 378
 # distinct 3x3 blocks a_ip^T (C+ a_jp) of the symmetric 27 x 27 block pattern
-# (378 x 27 FMA): 12,636 FMA = 25,272 flop.
+# (378 x 27 FMA): 12,393 FMA = 24,786 flop.
 BOUND = {"smooth0": "hbm", "residual0": "hbm", "sgs0": "hbm", "rap0": "hbm", "particle_eval": "hbm",
          "gradient": "hbm", "assemble_h0": "alu", "particle_hessian": "alu"}
 # traced spans that hold several kernels (not candidates for the dominant kernel)
 COMPOSITE = {"vcycle"}
-FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 9 + 27 * 81 + 378 * 27)}
+FLOP_PER_PARTICLE = {"assemble_h0": 2.0 * (27 * 81 + 378 * 27)}
 
 CSRC = os.path.join(ROOT, "paper_1911_07913_amd", "csrc")
 # committed PMC summaries: per-launch HBM traffic of a kernel in the precision

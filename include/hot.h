@@ -119,7 +119,9 @@ typedef struct {
 } hot_bc;
 
 /* Device allocator hook (e.g. a framework's caching allocator).  alloc returns
- * device memory of at least `bytes` bytes or NULL; free releases it. */
+ * device memory of at least `bytes` bytes, aligned to 256 bytes (as hipMalloc's
+ * is), or NULL; free releases it.  A misaligned block is freed again and the
+ * call that needed it fails with HOT_E_INVALID. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);

@@ -186,6 +186,13 @@ hot_status ensure(hot_scene* s, DBuf& b, size_t bytes) {
   size_t want = bytes + bytes / 4;
   b.p = s->alloc.alloc(want, s->alloc.ctx);
   if (!b.p) return fail(HOT_E_NOMEM, "device allocation of %zu bytes failed", want);
+  if (reinterpret_cast<uintptr_t>(b.p) % 256 != 0) {
+    // the kernels read and write 16- and 32-byte vectors and records
+    void* bad = b.p;
+    s->alloc.free(bad, s->alloc.ctx);
+    b.p = nullptr;
+    return fail(HOT_E_INVALID, "the allocator returned %p, which is not 256-byte aligned", bad);
+  }
   b.cap = want;
   s->bytes_live += want;
   return HOT_OK;
@@ -683,9 +690,9 @@ hot_status build_hessian(hot_scene* s, const double* dv) {
                                pt.mat, P<double>(s->vstar), dv, dt, P<double>(s->wnode),
                                P<double>(s->arec), st));
   PROF(s, HOT_PROF_ASSEMBLE,
-       launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, n, P<double>(s->f), pt.F,
-                          P<double>(s->arec), P<int>(s->start),
-                          P<int>(s->counts), P<double>(s->mass), P<int>(s->fixed), st));
+       launch_assemble_h0(s->sd, L0, P<int>(s->seg_begin), s->n_seg, n, P<double>(s->arec),
+                          P<int>(s->start), P<int>(s->counts), P<double>(s->mass),
+                          P<int>(s->fixed), st));
   for (int m = 0; m + 1 < s->levels; ++m) {
     // rows of the half-coarsened grid: x-y parents of level m's nodes
     const GridGeom& fg = s->L[m].g;
@@ -980,7 +987,7 @@ double prof_launch_bytes(hot_scene* s, int kind) {
     case HOT_PROF_RAP0: return 72.0 * nnz0 + 23.0 * n0 + 72.0 * nnz1 + 111.0 * n1;
     case HOT_PROF_EVAL: return 192.0 * np + 72.0 * n0;
     case HOT_PROF_GRAD: return 96.0 * np + 64.0 * n0;
-    case HOT_PROF_PHESS: return 472.0 * np + 24.0 * n0;
+    case HOT_PROF_PHESS: return 1120.0 * np + 24.0 * n0;
     case HOT_PROF_VCYCLE: return vcycle_bytes(s);
   }
   return 0.0;

@@ -182,7 +182,8 @@ void launch_p2g(const SceneDev& s, const LevelView& L0, const Bricks& B, const d
 // (v* + dv + alpha p) into `wnode`, a double4 array over the padded level-0
 // grid, so each particle gathers 27 nodes with two loads per node and no map
 // lookup.
-// projected stress derivative of each particle at F(dv) (dv = NULL: dv = 0)
+// each particle's level-0 assembly record: its projected stress derivative
+// at F(dv) (dv = NULL: dv = 0) and its a_l = F^n^T grad w_l operands
 void launch_particle_hessian(const SceneDev& s, const LevelView& L0, int n, const double* f,
                              const int* key, const double* F, const double* vol, const int* mat,
                              const double* vstar, const double* dv, double dt, double* wnode,
@@ -200,12 +201,11 @@ void launch_gradient(const SceneDev& s, const LevelView& L0, const Bricks& B, co
 void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, const int* key,
                 double* x, double* v, double* C, double* F, const int* mat, const double* vstar,
                 const double* dv, double dt, double* wnode, hipStream_t st);
-// level-0 Hessian: the particles' a_l operands into their assembly records
-// (after C_p, written by launch_particle_hessian), then the row segments'
-// blocks
+// level-0 Hessian: the row segments' blocks from the particles' assembly
+// records (C_p and the a_l operands, written by launch_particle_hessian)
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        int n, const double* f, const double* F, double* rec, const int* cstart,
-                        const int* ccount, const double* mass, const int* fixed, hipStream_t st);
+                        int n, const double* rec, const int* cstart, const int* ccount,
+                        const double* mass, const int* fixed, hipStream_t st);
 
 // matrix.hip
 void launch_finalize_level(const LevelView& L, int zero_diag_rule, hipStream_t st);

@@ -275,10 +275,23 @@ __device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pid
   });
 }
 
-// Per-particle projected stress derivative at dv = 0, scaled by dt^2 V_p
+// Quadratic B-spline weight and its derivative (times 1/dx) for stencil
+// offset k in {0, 1, 2} at fractional position f (Sec. 3 kernel).
+__device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
+  double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
+  double w0 = 0.5 * (a * a), w1 = 0.75 - b * b, w2 = 0.5 * (c * c);
+  double d0 = (f - 1.5) * inv_dx, d1 = -2.0 * b * inv_dx, d2 = c * inv_dx;
+  w = (k == 0) ? w0 : ((k == 1) ? w1 : w2);
+  dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
+}
+
+// A particle's level-0 assembly record (kAsmRec doubles), one thread per
+// particle: the projected stress derivative at F(dv), scaled by dt^2 V_p
 // (the particle's contribution to the level-0 Hessian, Alg. HOT
-// projectHessian): 45 upper-triangle entries at the head of the particle's
-// assembly record.
+// projectHessian), as 45 upper-triangle entries, then the assembly's
+// right-hand operands a_lp = F_p^n^T grad w_lp for the 27 stencil nodes l
+// (component-minor).  The thread writes its whole record, so every cache
+// line of it is complete when it leaves the L2.
 __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                    const int* __restrict__ key, const double* __restrict__ Fn,
                                    const double* __restrict__ vol, const int* __restrict__ mat,
@@ -289,9 +302,39 @@ __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView 
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
   particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
-  double C45[45];
-  projected_dPdF(s.mats[mat[p]], F, dt * dt * vol[p], C45);
-  for (int i = 0; i < 45; ++i) rec[kAsmRec * (long long)p + i] = C45[i];
+  // records start on 16-byte boundaries (kAsmRec even): entries 2j, 2j + 1
+  // go out as one 16-byte store
+  double2* R2 = reinterpret_cast<double2*>(rec + kAsmRec * (long long)p);
+  double c44;  // C entry 44 shares a 16-byte store with the first a value
+  {
+    double C45[45];
+    projected_dPdF(s.mats[mat[p]], F, dt * dt * vol[p], C45);
+#pragma unroll
+    for (int j = 0; j < 22; ++j) R2[j] = make_double2(C45[2 * j], C45[2 * j + 1]);
+    c44 = C45[44];
+  }
+  const double f0 = f[3 * p], f1 = f[3 * p + 1], f2 = f[3 * p + 2];
+  double wx[3], dx[3], wy[3], dy[3], wz[3], dz[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    wdw(k, f0, s.inv_dx, wx[k], dx[k]);
+    wdw(k, f1, s.inv_dx, wy[k], dy[k]);
+    wdw(k, f2, s.inv_dx, wz[k], dz[k]);
+  }
+  static_assert(kAsmRecA == 45 && kAsmRec == kAsmRecA + 81, "record layout");
+  double a[81];
+#pragma unroll
+  for (int l = 0; l < 27; ++l) {
+    const int kx = l % 3, ky = (l / 3) % 3, kz = l / 9;
+    const double gx = dx[kx] * wy[ky] * wz[kz], gy = wx[kx] * dy[ky] * wz[kz],
+                 gz = wx[kx] * wy[ky] * dz[kz];
+    a[3 * l] = fn[0] * gx + fn[3] * gy + fn[6] * gz;
+    a[3 * l + 1] = fn[1] * gx + fn[4] * gy + fn[7] * gz;
+    a[3 * l + 2] = fn[2] * gx + fn[5] * gy + fn[8] * gz;
+  }
+  R2[22] = make_double2(c44, a[0]);
+#pragma unroll
+  for (int j = 0; j < 40; ++j) R2[23 + j] = make_double2(a[1 + 2 * j], a[2 + 2 * j]);
 }
 
 // Energy density and stress at the trial point: psi_out[p] = V_p psi(F_p),
@@ -559,59 +602,6 @@ constexpr int kStageLd = kStage / (2 * kAsmThreads);  // 16-byte loads per threa
 constexpr int kBufferWord3 = 0x00020000;          // buffer resource word 3 (raw, 32-bit)
 static_assert(kAsmChunk * kAsmRec <= kStage, "staging area too small");
 static_assert((kAsmRec % 2) == 0, "records must keep 16-byte alignment");
-
-__device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw) {
-  double a = 1.5 - f, b = f - 1.0, c = f - 0.5;
-  double w0 = 0.5 * (a * a), w1 = 0.75 - b * b, w2 = 0.5 * (c * c);
-  double d0 = (f - 1.5) * inv_dx, d1 = -2.0 * b * inv_dx, d2 = c * inv_dx;
-  w = (k == 0) ? w0 : ((k == 1) ? w1 : w2);
-  dw = (k == 0) ? d0 : ((k == 1) ? d1 : d2);
-}
-
-// The assembly's right-hand operands a_lp = F_p^n^T grad w_lp for the 27
-// stencil nodes l of every particle, into the particle's record after C_p,
-// once per step (the assembly visits each particle from up to 9 x-lines).
-// A group of kAgradP particles: their f and F are loaded once into LDS, one
-// thread per (particle, node) forms a_lp there, and the group writes the
-// particles' 81-value blocks as contiguous runs.
-constexpr int kAgradP = 8;
-constexpr int kAgradThreads = 27 * kAgradP;  // 216
-__global__ __launch_bounds__(kAgradThreads) void k_particle_agrad(SceneDev s, int n,
-                                                                  const double* __restrict__ f,
-                                                                  const double* __restrict__ Fn,
-                                                                  double* __restrict__ rec) {
-  __shared__ double pf[kAgradP][12];        // f (3), then F (9)
-  __shared__ double ab[kAgradP * 81];       // the group's a_lp, [particle][l][3]
-  const int tid = threadIdx.x;
-  const long long p0 = (long long)blockIdx.x * kAgradP;
-  const int np = (int)min((long long)kAgradP, (long long)n - p0);
-  if (tid < 12 * np) {
-    const int q = tid / 12, k = tid - 12 * q;
-    pf[q][k] = (k < 3) ? f[3 * (p0 + q) + k] : Fn[9 * (p0 + q) + (k - 3)];
-  }
-  __syncthreads();
-  {
-    const int q = tid / 27, l = tid - 27 * q;
-    if (q < np) {
-      const double* P = pf[q];
-      double w0, d0, w1, d1, w2, d2;
-      wdw(l % 3, P[0], s.inv_dx, w0, d0);
-      wdw((l / 3) % 3, P[1], s.inv_dx, w1, d1);
-      wdw(l / 9, P[2], s.inv_dx, w2, d2);
-      const double gx = d0 * w1 * w2, gy = w0 * d1 * w2, gz = w0 * w1 * d2;
-      const double* F = P + 3;
-      double* o = ab + 81 * q + 3 * l;
-      o[0] = F[0] * gx + F[3] * gy + F[6] * gz;
-      o[1] = F[1] * gx + F[4] * gy + F[7] * gz;
-      o[2] = F[2] * gx + F[5] * gy + F[8] * gz;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < 81 * np; e += kAgradThreads) {
-    const int q = e / 81, j = e - 81 * q;
-    rec[kAsmRec * (p0 + q) + kAsmRecA + j] = ab[e];
-  }
-}
 
 // Finalisation of level-0 row i held in the LDS window (the group's
 // kAsmThreads threads, no barrier): mass on the diagonal, Dirichlet
@@ -992,10 +982,8 @@ void launch_g2p(const SceneDev& s, const LevelView& L0, int n, const double* f, 
 }
 
 void launch_assemble_h0(const SceneDev& s, const LevelView& L0, const int* seg_begin, int n_seg,
-                        int n, const double* f, const double* F, double* rec, const int* cstart,
-                        const int* ccount, const double* mass, const int* fixed, hipStream_t st) {
-  if (n > 0)
-    k_particle_agrad<<<(n + kAgradP - 1) / kAgradP, kAgradThreads, 0, st>>>(s, n, f, F, rec);
+                        int n, const double* rec, const int* cstart, const int* ccount,
+                        const double* mass, const int* fixed, hipStream_t st) {
   if (n_seg > 0 && n > 0)
     k_assemble_strip<<<n_seg, kAsmThreads, 0, st>>>(s, L0, seg_begin, rec, cstart, ccount, mass,
                                                      fixed);
