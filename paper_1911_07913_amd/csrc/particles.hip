@@ -264,15 +264,64 @@ __device__ inline void particle_F_with(const SceneDev& s, const double* fp, cons
       F[3 * r + c] = acc;
     }
 }
-__device__ inline void particle_F(const SceneDev& s, const LevelView& L, int pidx_key,
-                                  const double* fp, const double* Fn,
-                                  const double4* __restrict__ wn, double dt, double* F) {
-  particle_F_with(s, fp, Fn, dt, F, [&](int k, double* vel) {
-    const double4 wv = wn[pidx_key + stencil_offset(L.g, k)];
-    vel[0] = wv.x;
-    vel[1] = wv.y;
-    vel[2] = wv.z;
-  });
+
+// Node velocities for the one-thread-per-particle passes.  Particles are
+// sorted by base node, so a block's particles usually have base nodes within
+// a short run k0 .. k1 of padded indices, and their 27-node stencils read,
+// for each of the 9 (y, z) offsets, a contiguous range of k1 - k0 + 3 nodes.
+// The block stages those ranges in LDS with contiguous loads (per-particle
+// gathers of 27 nodes keep the vector-memory address units over 80% busy);
+// particles outside the staged range, and blocks whose range is too long,
+// read the node array directly.  The values are the same either way.
+constexpr int kNodeWin = 64;  // staged nodes per (y, z) offset
+struct NodeStage {
+  int k0, span;
+  bool staged;
+};
+// Every thread of the block calls this (it ends with a barrier).
+__device__ inline NodeStage stage_node_ranges(const LevelView& L, const int* __restrict__ key,
+                                              int n, const double4* __restrict__ wn,
+                                              double (*win)[9 * kNodeWin]) {
+  const int pb = blockIdx.x * blockDim.x;
+  NodeStage ns;
+  ns.k0 = key[pb];
+  const int k1 = key[min(pb + (int)blockDim.x, n) - 1];
+  ns.span = k1 - ns.k0 + 3;
+  ns.staged = k1 >= ns.k0 && ns.span <= kNodeWin;
+  if (ns.staged) {
+    for (int e = threadIdx.x; e < 9 * ns.span; e += blockDim.x) {
+      const int r = e / ns.span, xo = e - r * ns.span;  // r = ky + 3 kz
+      const double4 wv = wn[ns.k0 + xo + stencil_offset(L.g, 3 * r)];
+      win[0][r * kNodeWin + xo] = wv.x;
+      win[1][r * kNodeWin + xo] = wv.y;
+      win[2][r * kNodeWin + xo] = wv.z;
+    }
+  }
+  __syncthreads();
+  return ns;
+}
+// body(node_v), with node_v(k, vel) giving stencil node k's velocity for the
+// particle whose base node is kp.
+template <typename Body>
+__device__ inline void with_node_velocities(const NodeStage& ns, const double (*win)[9 * kNodeWin],
+                                            const LevelView& L, const double4* __restrict__ wn,
+                                            int kp, Body body) {
+  const int d = kp - ns.k0;
+  if (ns.staged && d >= 0 && d + 2 < ns.span) {
+    body([&](int k, double* vel) {
+      const int e = (k / 3) * kNodeWin + d + k % 3;
+      vel[0] = win[0][e];
+      vel[1] = win[1][e];
+      vel[2] = win[2][e];
+    });
+  } else {
+    body([&](int k, double* vel) {
+      const double4 wv = wn[kp + stencil_offset(L.g, k)];
+      vel[0] = wv.x;
+      vel[1] = wv.y;
+      vel[2] = wv.z;
+    });
+  }
 }
 
 // Quadratic B-spline weight and its derivative (times 1/dx) for stencil
@@ -291,17 +340,22 @@ __device__ inline void wdw(int k, double f, double inv_dx, double& w, double& dw
 // projectHessian), as 45 upper-triangle entries, then the assembly's
 // right-hand operands a_lp = F_p^n^T grad w_lp for the 27 stencil nodes l
 // (component-minor).  The thread writes its whole record, so every cache
-// line of it is complete when it leaves the L2.
+// line of it is complete when it leaves the L2.  Node velocities come from
+// the block's staged ranges.
 __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                    const int* __restrict__ key, const double* __restrict__ Fn,
                                    const double* __restrict__ vol, const int* __restrict__ mat,
                                    const double4* __restrict__ wn, double dt,
                                    double* __restrict__ rec) {
+  __shared__ double win[3][9 * kNodeWin];
+  const NodeStage ns = stage_node_ranges(L, key, n, wn, win);
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
-  particle_F(s, L, key[p], f + 3 * p, fn, wn, dt, F);
+  with_node_velocities(ns, win, L, wn, key[p], [&](auto node_v) {
+    particle_F_with(s, f + 3 * p, fn, dt, F, node_v);
+  });
   // records start on 16-byte boundaries (kAsmRec even): entries 2j, 2j + 1
   // go out as one 16-byte store
   double2* R2 = reinterpret_cast<double2*>(rec + kAsmRec * (long long)p);
@@ -339,53 +393,21 @@ __global__ __launch_bounds__(256) void k_particle_hessian(SceneDev s, LevelView 
 
 // Energy density and stress at the trial point: psi_out[p] = V_p psi(F_p),
 // S_out[p] = V_p P(F_p) F_p^n^T (the particle's force tensor, Sec. 4.1).
-// Particles are sorted by base node, so the block's particles usually have
-// base nodes within a short run of padded indices k0 .. k1; their 27-node
-// stencils then read, for each of the 9 (y, z) offsets, a contiguous range
-// of the node array of k1 - k0 + 3 nodes.  The block stages those ranges in
-// LDS with contiguous loads and each particle reads its nodes there (the
-// per-particle gathers of 27 nodes keep the vector-memory address units
-// over 80% busy); particles outside the staged range, and blocks whose range
-// is too long, read the node array directly.  The values and the order of
-// the sums are those of the direct form (identical bits).
-constexpr int kEvalWin = 64;  // staged nodes per (y, z) offset
+// Node velocities come from the block's staged ranges.
 __global__ __launch_bounds__(256) void k_particle_eval(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                                 const int* __restrict__ key, const double* __restrict__ Fn,
                                 const double* __restrict__ vol, const int* __restrict__ mat,
                                 const double4* __restrict__ wn, double dt,
                                 double* __restrict__ psi_out, double* __restrict__ S_out) {
-  __shared__ double win[3][9 * kEvalWin];
-  const int tid = threadIdx.x;
-  const int pb = blockIdx.x * blockDim.x;
-  const int p = pb + tid;
-  const int k0 = key[pb], k1 = key[min(pb + (int)blockDim.x, n) - 1];
-  const int span = k1 - k0 + 3;  // nodes per staged range
-  const bool staged = k1 >= k0 && span <= kEvalWin;
-  if (staged) {
-    for (int e = tid; e < 9 * span; e += blockDim.x) {
-      const int r = e / span, xo = e - r * span;  // r = ky + 3 kz
-      const double4 wv = wn[k0 + xo + stencil_offset(L.g, 3 * r)];
-      win[0][r * kEvalWin + xo] = wv.x;
-      win[1][r * kEvalWin + xo] = wv.y;
-      win[2][r * kEvalWin + xo] = wv.z;
-    }
-  }
-  __syncthreads();
+  __shared__ double win[3][9 * kNodeWin];
+  const NodeStage ns = stage_node_ranges(L, key, n, wn, win);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double F[9], fn[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * p + i];
-  const int kp = key[p];
-  const int d = kp - k0;
-  if (staged && d >= 0 && d + 2 < span) {
-    particle_F_with(s, f + 3 * p, fn, dt, F, [&](int k, double* vel) {
-      const int e = (k / 3) * kEvalWin + d + k % 3;
-      vel[0] = win[0][e];
-      vel[1] = win[1][e];
-      vel[2] = win[2][e];
-    });
-  } else {
-    particle_F(s, L, kp, f + 3 * p, fn, wn, dt, F);
-  }
+  with_node_velocities(ns, win, L, wn, key[p], [&](auto node_v) {
+    particle_F_with(s, f + 3 * p, fn, dt, F, node_v);
+  });
   double P[9];
   double ps = psi_and_piola(s.mats[mat[p]], F, P);
   double V = vol[p];
@@ -517,35 +539,40 @@ __device__ inline void snow_clamp(double* F, double lo, double hi) {
 }
 
 // Grid-to-particle APIC transfer, deformation update, lagged plasticity and
-// advection (Sec. 3.1).
-__global__ __launch_bounds__(256) void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
+// advection (Sec. 3.1).  Node velocities come from the block's staged ranges.
+// Two waves per SIMD: left to itself the compiler takes 256 registers plus
+// spill registers, which allows only one.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_g2p(SceneDev s, LevelView L, int n, const double* __restrict__ f,
                       const int* __restrict__ key, double* __restrict__ x,
                       double* __restrict__ v, double* __restrict__ C, double* __restrict__ Fn,
                       const int* __restrict__ mat, const double4* __restrict__ wn, double dt) {
+  __shared__ double win[3][9 * kNodeWin];
+  const NodeStage ns = stage_node_ranges(L, key, n, wn, win);
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double fp[3] = {f[3 * p], f[3 * p + 1], f[3 * p + 2]};
   Weights W;
   bspline_weights(fp, s.inv_dx, W);
   double vp[3] = {0, 0, 0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int kp = key[p];
+  with_node_velocities(ns, win, L, wn, key[p], [&](auto node_v) {
 #pragma unroll
-  for (int k = 0; k < 27; ++k) {
-    const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-    const double4 wv = wn[kp + stencil_offset(L.g, k)];
-    const double vel[3] = {wv.x, wv.y, wv.z};
-    double w = node_weight(W, kx, ky, kz);
-    double g[3];
-    node_grad(W, kx, ky, kz, g);
-    double d[3] = {(kx - fp[0]) * s.dx, (ky - fp[1]) * s.dx, (kz - fp[2]) * s.dx};
-    for (int a = 0; a < 3; ++a) {
-      vp[a] += w * vel[a];
-      for (int b = 0; b < 3; ++b) {
-        B[3 * a + b] += w * vel[a] * d[b];
-        gv[3 * a + b] += vel[a] * g[b];
+    for (int k = 0; k < 27; ++k) {
+      const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+      double vel[3];
+      node_v(k, vel);
+      double w = node_weight(W, kx, ky, kz);
+      double g[3];
+      node_grad(W, kx, ky, kz, g);
+      double d[3] = {(kx - fp[0]) * s.dx, (ky - fp[1]) * s.dx, (kz - fp[2]) * s.dx};
+      for (int a = 0; a < 3; ++a) {
+        vp[a] += w * vel[a];
+        for (int b = 0; b < 3; ++b) {
+          B[3 * a + b] += w * vel[a] * d[b];
+          gv[3 * a + b] += vel[a] * g[b];
+        }
       }
     }
-  }
+  });
   double fn[9], F[9];
   for (int i = 0; i < 9; ++i) fn[i] = Fn[9 * (long long)p + i];
   for (int r = 0; r < 3; ++r)
